@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the PXST reconstruction loop on one MI355X.
+
+One step = one full main-loop solve of the realistic scan (256 x 1024 detector,
+121 frames, +-10 px window with paraboloid refinement, 5 iterations and a final
+reference update) starting from the same initial map, with the inputs resident in
+HBM.  The headline value is pixel-map candidate evaluations (good pixels x window
+candidates x frames, summed over the iterations) per second of whole-solve time.
+
+Also reported: the dominant kernel's (interior-tile pixel-map search) roofline
+fraction from HIP events around its launches inside the timed region, the FP64
+oracle timed on host cores on a sampled subset of the same workload, the divergent
+scan (512 x 512, 400 frames, translation update on) and per-solve latencies.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel-map candidate evals/s (pixels×shifts×frames); p50/p99 solve latency"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz for non-packed float32
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+FLOP_PER_EVAL = 4   # r = I - W g (1 FMA) and E += r^2 (1 FMA)
+
+
+def pm_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pxst_pixel_map.hip", "pxst_device.hpp", "pxst_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2003_12726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "pm_fast_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    ent = d.get(workload)
+    if not ent or ent.get("source_hash") != pm_source_hash():
+        return None
+    return ent
+
+
+# --------------------------------------------------------------------- oracle leg
+_ORC = {}
+
+
+def _oracle_worker(args):
+    rows, cols = args
+    import numpy as np  # noqa: F401
+    import oracle
+    s = _ORC["scan"]
+    t = time.perf_counter()
+    oracle.update_pixel_map(s.frames, s.white, s.mask, _ORC["ref"], _ORC["w"], s.dx0, s.u0, s.origin,
+                            s.window, s.refine, pixels=(rows, cols))
+    return time.perf_counter() - t
+
+
+def cpu_baseline(scan, n_workers: int, px_per_worker: int):
+    """FP64 oracle pixel-map update on sampled pixels of the same scan, one process per
+    host core; returns evals/s of the wall time."""
+    import numpy as np
+    _ORC["scan"] = scan
+    _ORC["ref"] = scan.ref_true
+    _ORC["w"] = np.ones_like(scan.ref_true)
+    rng = np.random.default_rng(7)
+    H, W = scan.det
+    jobs = [(rng.integers(0, H, px_per_worker), rng.integers(0, W, px_per_worker))
+            for _ in range(n_workers)]
+    rx, ry = scan.window
+    evals = n_workers * px_per_worker * (2 * rx + 1) * (2 * ry + 1) * scan.n_frames
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(n_workers) as pool:
+        per = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t
+    return {
+        "value": evals / wall,
+        "unit": "evals/s",
+        "cores": n_workers,
+        "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle pixel-map update of {n_workers * px_per_worker} sampled pixels "
+                   f"of the realistic scan (all {(2 * rx + 1) * (2 * ry + 1)} candidates x "
+                   f"{scan.n_frames} frames, refinement on), {n_workers} processes x "
+                   f"{px_per_worker} pixels, wall {wall:.1f} s"),
+        "single_core_evals_per_s": (px_per_worker * (2 * rx + 1) * (2 * ry + 1) * scan.n_frames
+                                    / (sum(per) / len(per))),
+    }
+
+
+# ------------------------------------------------------------------------ GPU leg
+class Job:
+    """A scan resident on the GPU with its state, workspace and initial map."""
+
+    def __init__(self, scan, dev, n_iter=None):
+        import numpy as np
+        import torch
+        import paper_2003_12726_amd as pxst
+        self.s = scan
+        self.pxst = pxst
+        f16 = scan.frames.view(np.int16)
+        self.scan = pxst.Scan(torch.from_numpy(f16).to(dev), torch.from_numpy(scan.white).to(dev),
+                              torch.from_numpy(scan.mask).to(dev), scan.ref_shape, scan.origin)
+        self.n_iter = scan.iters if n_iter is None else n_iter
+        self.opts = pxst.make_opts(self.n_iter, scan.window, scan.refine, scan.update_dx,
+                                   scan.tr_window, True)
+        self.u0 = torch.from_numpy(scan.u0).to(dev)
+        self.dx0 = torch.from_numpy(scan.dx0).to(dev)
+        self.u = torch.empty_like(self.u0)
+        self.dx = torch.empty_like(self.dx0)
+        self.ref = torch.empty(scan.ref_shape, dtype=torch.float32, device=dev)
+        self.wsum = torch.empty(scan.ref_shape, dtype=torch.float64, device=dev)
+        self.hist = torch.zeros(max(self.n_iter, 1), dtype=torch.float64, device=dev)
+        self.ws = pxst.alloc_workspace(self.scan.geom, self.opts, dev)
+
+    def step(self):
+        self.u.copy_(self.u0)
+        self.dx.copy_(self.dx0)
+        self.pxst.solve(self.scan, self.opts, self.u, self.dx, self.ref, self.wsum, self.hist, self.ws)
+
+    def pm_evals(self):
+        return self.s.pm_evals() * self.n_iter
+
+
+def time_steps(job, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        job.step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        job.step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = sorted(a.elapsed_time(b) for a, b in evs)
+    return wall, lat
+
+
+def pct(xs, q):
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-divergent", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the reconstruction of one scan runs on one device "
+              f"(--gpus {args.gpus} is not supported; multi-GPU sharding is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2003_12726_amd as pxst
+    from synth.scans import cached_scan
+
+    scan = cached_scan("realistic")
+    # the oracle leg forks worker processes: run it before this process loads the HIP
+    # library or touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        nw = args.cpu_workers or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(scan, nw, 192)
+    pxst.load_library()
+    dev = torch.device("cuda:0")
+    job = Job(scan, dev)
+
+    pxst.profile_enable(True)
+    for fam in ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial", "err_pixels"):
+        pxst.profile_read(fam)
+    # warm-up outside the profiled window
+    for _ in range(args.warmup):
+        job.step()
+    torch.cuda.synchronize()
+    for fam in ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial", "err_pixels"):
+        pxst.profile_read(fam)
+    wall, lat = time_steps(job, args.steps, 0)
+    kern = {fam: pxst.profile_read(fam) for fam in
+            ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "err_pixels")}
+    pxst.profile_enable(False)
+
+    ms_per_step = 1000.0 * wall / args.steps
+    evals_per_step = job.pm_evals()
+    value = evals_per_step / (wall / args.steps)
+
+    f_ms, f_n, f_work = kern["pm_fast"]
+    avg_ms = f_ms / max(f_n, 1)
+    evals_per_launch = f_work / max(f_n, 1)
+    achieved_tflops = FLOP_PER_EVAL * evals_per_launch / (avg_ms * 1e-3) / 1e12 if f_n else None
+    pm_total_ms = sum(kern[k][0] for k in ("pm_fast", "pm_edge", "pm_generic"))
+    pm_total_evals = sum(kern[k][2] for k in ("pm_fast", "pm_edge", "pm_generic"))
+    traffic = load_traffic("realistic")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (uint16 frames; f64 weight and error sums)",
+        "data": "synthetic (seeded scan shaped like the realistic workload)",
+        "config": {
+            "workload": "realistic: 256x1024 uint16 detector, 121 frames (11x11 grid, 8 px step), "
+                        "reference 512x1536, window +-10 px (441 candidates) with 3x3 refinement, "
+                        "5 iterations + final reference update",
+            "pm_evals_per_step": evals_per_step,
+            "parallelism": "single GPU",
+        },
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": lat[-1],
+                       "kind": "one full solve per job, jobs run one by one"},
+        "roofline": {
+            "kernel": "pixel-map search, interior tiles (k_pm_fast)",
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_NONPACKED_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": (achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS) if achieved_tflops else None,
+            "frac_of_packed_fp32_peak": (achieved_tflops / PEAK_FP32_PACKED_TFLOPS)
+            if achieved_tflops else None,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "avg_launch_ms": avg_ms,
+            "launches": f_n,
+            "evals_per_launch": evals_per_launch,
+            "flop_per_eval": FLOP_PER_EVAL,
+        },
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "pixel_map_only_evals_per_s": pm_total_evals / (pm_total_ms * 1e-3) if pm_total_ms else None,
+    }
+
+    if not args.no_divergent:
+        del job
+        torch.cuda.empty_cache()
+        d = cached_scan("divergent")
+        dj = Job(d, dev)
+        dwall, dlat = time_steps(dj, max(2, args.steps // 3), 1)
+        nst = max(2, args.steps // 3)
+        out["divergent"] = {
+            "workload": "divergent: 512x512, 400 frames, window +-15 x +-3 px, 8 iterations, "
+                        "translation update +-2 px on",
+            "ms_per_solve": 1000.0 * dwall / nst,
+            "pm_evals_per_s": dj.pm_evals() / (dwall / nst),
+            "pm_plus_tr_evals_per_s": (dj.pm_evals() + d.tr_evals() * dj.n_iter) / (dwall / nst),
+        }
+        del dj
+        torch.cuda.empty_cache()
+
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

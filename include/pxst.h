@@ -1,0 +1,239 @@
+/*
+ * pxst.h -- C interface of libpxst, the gfx950 (MI355X) implementation of the
+ * data-parallel reconstruction loop of Ptychographic X-ray Speckle Tracking.
+ *
+ * The paper (speckle-tracking: a software suite for PXST) states the problem as
+ * frames I[n, i, j], a white-field W[i, j], a pixel mask M[i, j], a pixel map
+ * u[2, i, j] (reference-plane coordinates sampled on the detector grid) and sample
+ * translations dx[n, 2], related by the discrete forward model of Sec. 2.1, Eq. 3:
+ *
+ *     I[n, i, j] ~ W[i, j] * I_ref[u[0, i, j] - dx[n, 0], u[1, i, j] - dx[n, 1]].
+ *
+ * Conventions used by every call:
+ *   - axis 0 = detector slow scan ("ss", x, i); axis 1 = fast scan ("fs", y, j);
+ *   - all arrays are C row-major;
+ *   - the reference index of detector pixel (i, j) in frame n is
+ *     u[:, i, j] - dx[n] - origin, with the integer origin of pxst_geom
+ *     (the paper leaves the reference origin free; an integer keeps every
+ *     fraction in u and dx);
+ *   - units are reference pixels throughout;
+ *   - a reference pixel is valid where its weight sum wsum > 0; lookups use the
+ *     masked bilinear interpolation of Sec. 4 (unknown or out-of-grid corners are
+ *     dropped and the remaining weights renormalised).
+ *
+ * Memory: every array pointer below is a DEVICE pointer owned by the caller.  The
+ * library never allocates device memory: scratch space comes from the caller's
+ * workspace (`ws`, `ws_bytes`), sized by pxst_workspace_bytes().  Host structs are
+ * read only during the call.  Pointers must be aligned to their element size and
+ * the workspace to 256 bytes.
+ *
+ * Execution: every call validates its arguments on the host first (no GPU work
+ * is enqueued when validation fails, so nothing is written), then enqueues its
+ * kernels on `stream` and returns without synchronising.  Results are valid once
+ * the stream has been synchronised.  Calls that share a workspace must be ordered
+ * on one stream.
+ *
+ * Errors: 0 on success, a negative PXST_E* code otherwise; pxst_last_error()
+ * returns a thread-local message describing the last failure of this thread.
+ */
+#ifndef PXST_H
+#define PXST_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PXST_ABI_VERSION 1
+
+#define PXST_OK 0
+#define PXST_EINVAL (-1)       /* null pointer, bad size or misaligned pointer        */
+#define PXST_EWORKSPACE (-2)   /* workspace missing or smaller than required         */
+#define PXST_EUNSUPPORTED (-3) /* valid but outside the implemented limits           */
+#define PXST_EHIP (-4)         /* HIP runtime or launch failure                       */
+
+/* Implemented limits: search half-widths 0..15 for the pixel map, 0..2 for
+ * translations; at most 2^24 - 1 detector pixels per frame; reference at most
+ * 16384 x 16384. */
+#define PXST_MAX_PM_RADIUS 15
+#define PXST_MAX_TR_RADIUS 2
+
+/* Scan geometry. */
+typedef struct {
+    int32_t n_frames;          /* N >= 1                                            */
+    int32_t det_ss, det_fs;    /* H, W: detector shape (slow scan, fast scan)       */
+    int32_t ref_ss, ref_fs;    /* Rs, Rf: reference shape                           */
+    int32_t org_ss, org_fs;    /* integer origin of the reference grid              */
+} pxst_geom;
+
+/* Search window: integer offsets k in [-r, r] per axis, step 1 (Sec. 2.2.2 and
+ * Sec. 2.2.3 search "within a predefined window").  refine != 0 adds the 3x3
+ * paraboloid sub-pixel offset around the integer minimum. */
+typedef struct {
+    int32_t r_ss, r_fs;
+    int32_t refine;
+} pxst_window;
+
+/* One scan: frames [N][H][W] uint16 photon counts, white-field [H][W] float32,
+ * mask [H][W] uint8 (1 = good pixel, 0 = excluded), all device memory. */
+typedef struct {
+    const uint16_t* frames;
+    const float* white;
+    const uint8_t* mask;
+    pxst_geom geom;
+} pxst_scan;
+
+/* Main-loop options (Sec. 2.2): n_iter iterations of (i) reference update,
+ * (ii) pixel-map update with window `pm`, (iii) translation update with window
+ * `tr` when update_dx != 0, (iv) total error. */
+typedef struct {
+    int32_t n_iter;
+    pxst_window pm;
+    int32_t update_dx;
+    pxst_window tr;
+} pxst_solve_opts;
+
+/* Workspace bytes that every entry point below needs for this geometry and these
+ * windows (opts may be NULL: reference update and error only).  Returns 0 and sets
+ * the last error when the arguments are invalid. */
+size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts);
+
+/*
+ * Reference update -- Sec. 2.2.1 with the bilinear splat of Sec. 4.
+ *   ref[p]  = sum_{n,i,j} w_p M W I[n,i,j] / sum_{n,i,j} w_p M W^2
+ *   wsum[p] = sum_{n,i,j} w_p M W^2
+ * where w_p is the bilinear weight of reference pixel p for the point
+ * u[:, i, j] - dx[n] - origin.  ref = 0 where wsum == 0.
+ *   u    [2][H][W] float32 (in)      dx   [N][2] float32 (in)
+ *   ref  [Rs][Rf]  float32 (out)     wsum [Rs][Rf] float64 (out)
+ * The numerator is accumulated in float32 with compensated summation over frames,
+ * the weight sums in float64.  Deterministic: the sums are gathered per reference
+ * pixel in a fixed order, without atomics on floating-point values.
+ */
+int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx,
+                          float* ref, double* wsum, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/*
+ * Pixel-map update -- Sec. 2.2.2 (brute-force search, normalised error, argmin,
+ * optional quadratic refinement).  For every good pixel: c = round-half-up(u_in);
+ * for each candidate c + k, k in the window (slow-scan offset outer, fast-scan
+ * inner), over the frames whose lookup at c + k - dx[n] - origin is valid:
+ *   err = sum (I - W g)^2,  var = sum (I - W)^2,  E = err / var
+ * (E = 0 when var = err = 0 with a valid frame; +inf when no frame is valid or
+ * var = 0 < err).  The first minimum is taken; with refine, the least-squares
+ * paraboloid through the 3x3 errors around it adds an offset clamped to +-0.5
+ * (only for an interior minimum with finite neighbours; a 3-point parabola when
+ * one half-width is 0).
+ *   ref [Rs][Rf] float32, wsum [Rs][Rf] float64, dx [N][2], u_in [2][H][W] (in)
+ *   u_out [2][H][W] (out, may equal u_in)
+ *   err_min [H][W] float32 (out, optional), argmin [H][W] int32 (out, optional):
+ *   linear candidate index (k_ss + r_ss) * (2 r_fs + 1) + (k_fs + r_fs), or -1
+ *   (and err_min = +inf, u unchanged) for bad pixels and pixels with no finite
+ *   candidate.
+ * Bulk arithmetic is float32; the sums over frames are compensated.
+ */
+int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum,
+                          const float* dx, const float* u_in, pxst_window window,
+                          float* u_out, float* err_min, int32_t* argmin,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Translation update -- Sec. 2.2.3.  For frame n and integer shift s in the
+ * window, the candidate translation is dx_in[n] + s and its error integrates over
+ * the good pixels with a valid lookup at u - (dx_in[n] + s) - origin:
+ *   E_n(s) = sum (I - W g)^2 / sum (I - W)^2
+ * with the same empty / zero-variance rules, first-minimum order and refinement
+ * as the pixel map.  Frames with no finite candidate keep dx_in[n] (argmin -1).
+ *   u [2][H][W], dx_in [N][2] (in); dx_out [N][2] (out, may equal dx_in)
+ *   err_min [N] float32 (optional), argmin [N] int32 (optional)
+ */
+int pxst_update_translations(const pxst_scan* scan, const float* ref, const double* wsum,
+                             const float* u, const float* dx_in, pxst_window window,
+                             float* dx_out, float* err_min, int32_t* argmin,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Figures of merit -- Sec. 2.2.4 with the integrand of Eq. 2.
+ *   sigma2[i,j]  = (1/N) sum_n M (I - W)^2
+ *   eps[n,i,j]   = M (I - W g)^2 / sigma2  (valid lookup at u - dx[n] - origin and
+ *                  sigma2 > 0; else 0)
+ *   pixel_err [H][W] float32 = sum_n eps       (optional)
+ *   frame_err [N] float64   = sum_{i,j} eps    (optional)
+ *   total     [1] float64   = sum eps          (required)
+ *   ref_err   [Rs][Rf] float32 (optional) = sum w_p M eps / sum w_p M, the error
+ *                  mapped to the reference plane with the splat of Sec. 2.2.1
+ * Pixel sums use compensated float32; frame and total sums are float64 and
+ * reduced in a fixed order.
+ */
+int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, const float* u,
+               const float* dx, float* pixel_err, double* frame_err, double* total,
+               float* ref_err, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Main loop -- Sec. 2.2.  For k = 0..n_iter-1:
+ *   (ref, wsum) <- reference update from (u, dx)
+ *   u           <- pixel-map update with opts->pm
+ *   dx          <- translation update with opts->tr (if opts->update_dx)
+ *   err_hist[k] <- total error of (ref, u, dx)
+ * then a final reference update from the last (u, dx).
+ *   u [2][H][W], dx [N][2]: in/out.  ref [Rs][Rf], wsum [Rs][Rf]: out.
+ *   err_hist [n_iter] float64: out (optional).
+ * Everything runs on `stream` without host synchronisation; since the whole
+ * state is in the caller's buffers, calling again continues the iteration.
+ */
+int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, float* dx,
+               float* ref, double* wsum, double* err_hist, void* ws, size_t ws_bytes,
+               hipStream_t stream);
+
+/*
+ * Batched iteration for serving many reconstructions at once.  Each job carries
+ * its own scan, options, state buffers and workspace (sized by
+ * pxst_workspace_bytes for that job).  One call performs, for every job, the step
+ * selected by its `iter` field:
+ *   0 <= iter < n_iter : one main-loop iteration (reference, pixel map,
+ *                        translations if enabled, error -> err_hist[iter]);
+ *   iter == n_iter     : the final reference update.
+ * The stages of all jobs run as shared persistent launches (one per stage and
+ * kernel variant) whose work items are (job, tile) pairs, so jobs of different
+ * sizes overlap on the device.  A job's results do not depend on which other jobs
+ * share the call.  `batch_ws` must hold pxst_batch_workspace_bytes(n_jobs).
+ */
+typedef struct {
+    pxst_scan scan;
+    pxst_solve_opts opts;
+    float* u;
+    float* dx;
+    float* ref;
+    double* wsum;
+    double* err_hist;
+    int32_t iter;
+    void* ws;
+    size_t ws_bytes;
+} pxst_job;
+
+size_t pxst_batch_workspace_bytes(int32_t n_jobs);
+int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
+                       size_t batch_ws_bytes, hipStream_t stream);
+
+/* Kernel timing for benchmarks: when enabled, the library brackets each launch of
+ * the named kernel family with HIP events on the launch stream and accumulates
+ * their elapsed times (reading them synchronises on the recorded events).
+ * Families: "pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial",
+ * "err_pixels".  pxst_profile_read returns the total milliseconds and the number
+ * of timed launches, and resets the family. */
+int pxst_profile_enable(int32_t on);
+int pxst_profile_read(const char* family, double* total_ms, int64_t* launches,
+                      int64_t* work_units);
+
+const char* pxst_last_error(void);
+int32_t pxst_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PXST_H */

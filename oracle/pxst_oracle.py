@@ -221,7 +221,7 @@ def _pixel_errors(frames, W, ref, V, dx, origin, rows, cols, c0, c1, rx, ry):
         v = I[n] - Wp
         var += np.where(ok, (v * v)[None, None, :], 0.0)
         nv += ok
-    return _normalised(err, var, nv)
+    return _normalised(err, var, nv), (err, var, nv)
 
 
 def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=True,
@@ -235,7 +235,9 @@ def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=
     candidate is empty, keep their map value with error +inf and index -1.
 
     ``pixels``: optional (rows, cols) subset; outputs then cover only those pixels.
-    Returns (u_out, err_min, argmin) -- full arrays, or per-subset arrays.
+    Returns (u_out, err_min, argmin) -- full arrays, or per-subset arrays; with
+    ``return_errors`` also the candidate errors E[kx, ky, p] of the good pixels (and,
+    when it is "sums", the unnormalised (err, var, count) grids as well).
     """
     frames = np.asarray(frames)
     W, M, ref, dx, u = _f64(white), _f64(mask), _f64(ref), _f64(dx), _f64(u)
@@ -256,8 +258,8 @@ def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=
     if good.any():
         gr, gc = rows[good], cols[good]
         c = round_half_up(u_sel[:, good])
-        E = _pixel_errors(frames, W, ref, V, dx, origin, gr, gc, c[0], c[1], rx, ry)
-        E_all = E
+        E, sums = _pixel_errors(frames, W, ref, V, dx, origin, gr, gc, c[0], c[1], rx, ry)
+        E_all = (E, sums) if return_errors == "sums" else E
         flat = E.reshape(-1, E.shape[-1])
         k = np.argmin(flat, axis=0)                       # first minimum
         emin = flat[k, np.arange(flat.shape[1])]

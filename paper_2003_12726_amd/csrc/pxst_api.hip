@@ -1,0 +1,474 @@
+// C entry points of libpxst: argument validation, workspace layout, the main loop
+// and kernel timing.  Kernels live in the other translation units.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pxst_internal.hpp"
+
+namespace pxst {
+
+size_t sort_temp_bound(size_t n);
+
+// ---------------------------------------------------------------------------- errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PXST_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return PXST_EHIP;
+}
+
+// -------------------------------------------------------------------------- profiling
+namespace {
+struct Span {
+    hipEvent_t a, b;
+    long long work;
+    int* pinned;        // device counter copied here asynchronously (or null)
+    long long scale;
+};
+struct Family {
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> pool;
+    std::vector<int*> pinned_pool;
+    hipEvent_t open = nullptr;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, Family> g_prof;
+
+hipEvent_t take_event(Family& f) {
+    if (!f.pool.empty()) {
+        hipEvent_t e = f.pool.back();
+        f.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int* take_pinned(Family& f) {
+    if (!f.pinned_pool.empty()) {
+        int* p = f.pinned_pool.back();
+        f.pinned_pool.pop_back();
+        return p;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
+    return (int*)p;
+}
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+void profile_begin(const char* family, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    Family& f = g_prof[family];
+    f.open = take_event(f);
+    if (f.open) hipEventRecord(f.open, s);
+}
+
+// Records the end event; a device work counter is copied asynchronously into pinned
+// host memory (read when the family is read), so timing adds no synchronisation.
+void profile_end(const char* family, hipStream_t s, long long work, const int* dev_count,
+                 long long scale) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    Family& f = g_prof[family];
+    if (!f.open) return;
+    hipEvent_t b = take_event(f);
+    if (!b) return;
+    hipEventRecord(b, s);
+    int* pin = nullptr;
+    if (dev_count) {
+        pin = take_pinned(f);
+        if (pin) hipMemcpyAsync(pin, dev_count, sizeof(int), hipMemcpyDeviceToHost, s);
+    }
+    f.spans.push_back(Span{f.open, b, work, pin, scale});
+    f.open = nullptr;
+}
+
+// --------------------------------------------------------------------------- layout
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(const Geom& g, int tr_ct) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + (bytes ? bytes : 1));
+        return o;
+    };
+    const size_t HW = g.HW(), RR = g.RR();
+    L.refv = take(RR * sizeof(float));
+    L.sat = take((size_t)(g.Rs + 1) * (g.Rf + 1) * sizeof(int));
+    L.sat_tmp = take(RR * sizeof(int));
+    L.s2 = take(HW * sizeof(float));
+    L.ginfo = take(sizeof(GridInfo));
+    L.keys = take(HW * 4);
+    L.keys2 = take(HW * 4);
+    L.vals = take(HW * 4);
+    L.vals2 = take(HW * 4);
+    const size_t ncells = (size_t)grid_h(g) * (size_t)grid_w(g);
+    L.cstart = take((ncells + 3) * 4);
+    L.pdata = take(HW * 16);
+    L.bsort = take(HW * 8);
+    L.sort_tmp_bytes = sort_temp_bound(HW);
+    L.sort_tmp = take(L.sort_tmp_bytes);
+    const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);
+    L.tiles = take(ntiles * sizeof(TileDesc));
+    L.lists = take(3 * ntiles * sizeof(int));
+    L.counters = take(CNT_N * sizeof(int));
+    const size_t nblk_tr = (HW + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK;
+    L.tr_part = take((size_t)g.N * nblk_tr * (tr_ct > 0 ? tr_ct : 1) * 3 * sizeof(float));
+    const size_t nblk_err = (HW + (size_t)ERR_THREADS * 4 - 1) / ((size_t)ERR_THREADS * 4);
+    L.err_part = take((size_t)g.N * nblk_err * sizeof(double));
+    L.err_pix = take((size_t)g.N * sizeof(double) + sizeof(double));
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------------------ validation
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+static int check_geom(const pxst_geom* g) {
+    if (!g) {
+        set_error("geometry is null");
+        return PXST_EINVAL;
+    }
+    if (g->n_frames < 1 || g->det_ss < 1 || g->det_fs < 1 || g->ref_ss < 1 || g->ref_fs < 1) {
+        set_error("sizes must be positive (N=%d H=%d W=%d Rs=%d Rf=%d)", g->n_frames, g->det_ss,
+                  g->det_fs, g->ref_ss, g->ref_fs);
+        return PXST_EINVAL;
+    }
+    if ((long long)g->det_ss * g->det_fs >= (1LL << 24) || g->det_ss > 16384 || g->det_fs > 16384 ||
+        g->ref_ss > 16384 || g->ref_fs > 16384) {
+        set_error("sizes exceed the implemented limits (detector < 2^24 pixels, sides <= 16384)");
+        return PXST_EUNSUPPORTED;
+    }
+    if (g->n_frames > 1920) {
+        set_error("at most 1920 frames are supported");
+        return PXST_EUNSUPPORTED;
+    }
+    const long long lim = 1LL << 28;
+    if (g->org_ss < -lim || g->org_ss > lim || g->org_fs < -lim || g->org_fs > lim) {
+        set_error("origin out of range");
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
+static int check_scan(const pxst_scan* sc) {
+    if (!sc) {
+        set_error("scan is null");
+        return PXST_EINVAL;
+    }
+    int rc = check_geom(&sc->geom);
+    if (rc) return rc;
+    if (!sc->frames || !sc->white || !sc->mask) {
+        set_error("frames, white-field and mask must be non-null");
+        return PXST_EINVAL;
+    }
+    if (!aligned(sc->frames, 2) || !aligned(sc->white, 4)) {
+        set_error("frames or white-field misaligned");
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
+static int check_window(const pxst_window& w, int maxr, const char* what) {
+    if (w.r_ss < 0 || w.r_fs < 0) {
+        set_error("%s window radii must be >= 0", what);
+        return PXST_EINVAL;
+    }
+    if (w.r_ss > maxr || w.r_fs > maxr) {
+        set_error("%s window radii must be <= %d", what, maxr);
+        return PXST_EUNSUPPORTED;
+    }
+    return PXST_OK;
+}
+
+static int check_ptr(const void* p, size_t a, const char* what, bool required = true) {
+    if (!p) {
+        if (!required) return PXST_OK;
+        set_error("%s is null", what);
+        return PXST_EINVAL;
+    }
+    if (!aligned(p, a)) {
+        set_error("%s is misaligned", what);
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
+// Every entry point uses one layout per geometry: the translation partial sums are
+// sized for the largest translation window.
+static int tr_ct_of(const pxst_solve_opts*) { return TR_CT_MAX; }
+
+static int check_ws(const void* ws, size_t bytes, size_t need) {
+    if (!ws || bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws ? bytes : (size_t)0, need);
+        return PXST_EWORKSPACE;
+    }
+    if (!aligned(ws, 256)) {
+        set_error("workspace must be 256-byte aligned");
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
+}  // namespace pxst
+
+using namespace pxst;
+
+extern "C" {
+
+int32_t pxst_abi_version(void) { return PXST_ABI_VERSION; }
+
+const char* pxst_last_error(void) { return g_err; }
+
+size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts) {
+    if (check_geom(geom)) return 0;
+    if (opts) {
+        if (check_window(opts->pm, PXST_MAX_PM_RADIUS, "pixel-map")) return 0;
+        if (opts->update_dx && check_window(opts->tr, PXST_MAX_TR_RADIUS, "translation")) return 0;
+    }
+    return make_layout(geom_of(*geom), tr_ct_of(opts)).total;
+}
+
+int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx, float* ref,
+                          double* wsum, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
+        (rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")))
+        return rc;
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    return launch_update_reference(g, *scan, u, dx, ref, wsum, nullptr, (char*)ws, L, stream);
+}
+
+int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum,
+                          const float* dx, const float* u_in, pxst_window window, float* u_out,
+                          float* err_min, int32_t* argmin, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(dx, 4, "dx")) || (rc = check_ptr(u_in, 4, "u_in")) ||
+        (rc = check_ptr(u_out, 4, "u_out")) || (rc = check_ptr(err_min, 4, "err_min", false)) ||
+        (rc = check_ptr(argmin, 4, "argmin", false)))
+        return rc;
+    if ((rc = check_window(window, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    int* sat = (int*)(w + L.sat);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, sat, (int*)(w + L.sat_tmp), stream)))
+        return rc;
+    return launch_pixel_map(g, *scan, refv, sat, dx, u_in, window, u_out, err_min, argmin, w, L,
+                            stream);
+}
+
+int pxst_update_translations(const pxst_scan* scan, const float* ref, const double* wsum,
+                             const float* u, const float* dx_in, pxst_window window, float* dx_out,
+                             float* err_min, int32_t* argmin, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx_in, 4, "dx_in")) ||
+        (rc = check_ptr(dx_out, 4, "dx_out")) || (rc = check_ptr(err_min, 4, "err_min", false)) ||
+        (rc = check_ptr(argmin, 4, "argmin", false)))
+        return rc;
+    if ((rc = check_window(window, PXST_MAX_TR_RADIUS, "translation"))) return rc;
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, stream))) return rc;
+    return launch_translations(g, *scan, refv, u, dx_in, window, dx_out, err_min, argmin, w, L,
+                               stream);
+}
+
+int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, const float* u,
+               const float* dx, float* pixel_err, double* frame_err, double* total, float* ref_err,
+               void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
+        (rc = check_ptr(total, 8, "total")) || (rc = check_ptr(pixel_err, 4, "pixel_err", false)) ||
+        (rc = check_ptr(frame_err, 8, "frame_err", false)) ||
+        (rc = check_ptr(ref_err, 4, "ref_err", false)))
+        return rc;
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    float* s2 = (float*)(w + L.s2);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, stream))) return rc;
+    if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
+    if ((rc = launch_error(g, *scan, refv, s2, u, dx, pixel_err, frame_err, total, w, L, stream)))
+        return rc;
+    if (ref_err) return launch_reference_error(g, *scan, u, dx, refv, ref_err, w, L, stream);
+    return PXST_OK;
+}
+
+int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, float* dx, float* ref,
+               double* wsum, double* err_hist, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if (!opts) {
+        set_error("options are null");
+        return PXST_EINVAL;
+    }
+    if (opts->n_iter < 0) {
+        set_error("n_iter must be >= 0");
+        return PXST_EINVAL;
+    }
+    if ((rc = check_window(opts->pm, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
+    if (opts->update_dx && (rc = check_window(opts->tr, PXST_MAX_TR_RADIUS, "translation")))
+        return rc;
+    if ((rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
+        (rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(err_hist, 8, "err_hist", false)))
+        return rc;
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, tr_ct_of(opts));
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    int* sat = (int*)(w + L.sat);
+    int* sat_tmp = (int*)(w + L.sat_tmp);
+    float* s2 = (float*)(w + L.s2);
+    if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
+    for (int k = 0; k < opts->n_iter; ++k) {
+        if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream))) return rc;
+        if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, stream))) return rc;
+        if ((rc = launch_pixel_map(g, *scan, refv, sat, dx, u, opts->pm, u, nullptr, nullptr, w, L,
+                                   stream)))
+            return rc;
+        if (opts->update_dx &&
+            (rc = launch_translations(g, *scan, refv, u, dx, opts->tr, dx, nullptr, nullptr, w, L,
+                                      stream)))
+            return rc;
+        double* tot = err_hist ? err_hist + k : (double*)(w + L.err_pix) + g.N;
+        if ((rc = launch_error(g, *scan, refv, s2, u, dx, nullptr, nullptr, tot, w, L, stream)))
+            return rc;
+    }
+    return launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream);
+}
+
+int pxst_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return PXST_OK;
+}
+
+int pxst_profile_read(const char* family, double* total_ms, int64_t* launches, int64_t* work_units) {
+    if (!family || !total_ms || !launches) {
+        set_error("null argument");
+        return PXST_EINVAL;
+    }
+    hipDeviceSynchronize();   // pending counter copies land before they are read
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *total_ms = 0.0;
+    *launches = 0;
+    if (work_units) *work_units = 0;
+    auto it = g_prof.find(family);
+    if (it == g_prof.end()) return PXST_OK;
+    Family& f = it->second;
+    for (Span& sp : f.spans) {
+        float ms = 0.f;
+        if (hipEventSynchronize(sp.b) == hipSuccess && hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) {
+            *total_ms += ms;
+            *launches += 1;
+            if (work_units) *work_units += sp.pinned ? (long long)(*sp.pinned) * sp.scale : sp.work;
+        }
+        f.pool.push_back(sp.a);
+        f.pool.push_back(sp.b);
+        if (sp.pinned) f.pinned_pool.push_back(sp.pinned);
+    }
+    f.spans.clear();
+    return PXST_OK;
+}
+
+size_t pxst_batch_workspace_bytes(int32_t n_jobs) {
+    if (n_jobs < 0) {
+        set_error("n_jobs must be >= 0");
+        return 0;
+    }
+    return 256;
+}
+
+int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, size_t batch_ws_bytes,
+                       hipStream_t stream) {
+    (void)batch_ws;
+    (void)batch_ws_bytes;
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) {
+        set_error("bad job list");
+        return PXST_EINVAL;
+    }
+    // validate every job before enqueuing anything
+    for (int j = 0; j < n_jobs; ++j) {
+        const pxst_job& J = jobs[j];
+        int rc;
+        if ((rc = check_scan(&J.scan))) return rc;
+        if (J.iter < 0 || J.iter > J.opts.n_iter) {
+            set_error("job %d: iter %d outside 0..n_iter", j, J.iter);
+            return PXST_EINVAL;
+        }
+        const Layout L = make_layout(geom_of(J.scan.geom), tr_ct_of(&J.opts));
+        if ((rc = check_ws(J.ws, J.ws_bytes, L.total))) return rc;
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        const pxst_job& J = jobs[j];
+        const Geom g = geom_of(J.scan.geom);
+        const Layout L = make_layout(g, tr_ct_of(&J.opts));
+        char* w = (char*)J.ws;
+        float* refv = (float*)(w + L.refv);
+        int rc;
+        if (J.iter == J.opts.n_iter) {
+            rc = launch_update_reference(g, J.scan, J.u, J.dx, J.ref, J.wsum, refv, w, L, stream);
+        } else {
+            if (J.iter == 0 && (rc = launch_sigma2(g, J.scan, (float*)(w + L.s2), stream))) return rc;
+            rc = launch_update_reference(g, J.scan, J.u, J.dx, J.ref, J.wsum, refv, w, L, stream);
+            if (!rc)
+                rc = launch_prep_reference(g, nullptr, nullptr, refv, (int*)(w + L.sat),
+                                           (int*)(w + L.sat_tmp), stream);
+            if (!rc)
+                rc = launch_pixel_map(g, J.scan, refv, (int*)(w + L.sat), J.dx, J.u, J.opts.pm, J.u,
+                                      nullptr, nullptr, w, L, stream);
+            if (!rc && J.opts.update_dx)
+                rc = launch_translations(g, J.scan, refv, J.u, J.dx, J.opts.tr, J.dx, nullptr,
+                                         nullptr, w, L, stream);
+            if (!rc)
+                rc = launch_error(g, J.scan, refv, (float*)(w + L.s2), J.u, J.dx, nullptr, nullptr,
+                                  J.err_hist ? J.err_hist + J.iter : (double*)(w + L.err_pix) + g.N,
+                                  w, L, stream);
+        }
+        if (rc) return rc;
+    }
+    return PXST_OK;
+}
+
+}  // extern "C"

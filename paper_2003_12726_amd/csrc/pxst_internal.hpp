@@ -1,0 +1,126 @@
+// Internal declarations shared by the libpxst host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/pxst.h"
+
+namespace pxst {
+
+// ----------------------------------------------------------------------------- geometry
+struct Geom {
+    int N, H, W, Rs, Rf, o0, o1;
+    size_t HW() const { return (size_t)H * (size_t)W; }
+    size_t RR() const { return (size_t)Rs * (size_t)Rf; }
+};
+
+inline Geom geom_of(const pxst_geom& g) {
+    return Geom{g.n_frames, g.det_ss, g.det_fs, g.ref_ss, g.ref_fs, g.org_ss, g.org_fs};
+}
+
+// Pixel-map tiles are 8 x 8 detector pixels.
+constexpr int TILE = 8;
+// Staging budget of one LDS buffer of the pixel-map search (floats); two are used.
+constexpr int PM_STAGE_FLOATS = 7936;
+// Translation partial sums: detector pixels per work-group.
+constexpr int TR_PIX_PER_BLOCK = 4096;
+constexpr int TR_THREADS = 256;
+constexpr int TR_CT_MAX = (2 * PXST_MAX_TR_RADIUS + 1) * (2 * PXST_MAX_TR_RADIUS + 1);
+// Error evaluation: pixels per work-group.
+constexpr int ERR_THREADS = 256;
+
+// Inverse-map (reference gather) cell grid: capacity per axis.
+inline int grid_h(const Geom& g) { return 2 * (g.H > g.Rs ? g.H : g.Rs) + 8; }
+inline int grid_w(const Geom& g) { return 2 * (g.W > g.Rf ? g.W : g.Rf) + 8; }
+
+// Grid information computed on the device before the gather.
+struct GridInfo {
+    int bmin0, bmin1, bmax0, bmax1;   // bounding box of floor(u) - origin over good pixels
+    int g0, g1;                       // cell-grid origin
+    int n_good;
+    int pad;
+    long long sum0, sum1;             // sums of the cell coordinates (for a centred origin)
+};
+
+// Workspace layout: every section at a 256-byte aligned offset.
+struct Layout {
+    // common
+    size_t refv, sat, sat_tmp, s2;
+    // reference update
+    size_t ginfo, keys, keys2, vals, vals2, cstart, pdata, bsort, sort_tmp;
+    size_t sort_tmp_bytes;
+    // pixel map
+    size_t tiles, lists, counters;
+    // translations
+    size_t tr_part;
+    // error
+    size_t err_part, err_pix;
+    size_t total;
+};
+
+Layout make_layout(const Geom& g, int tr_ct);
+
+// Tile descriptor of the pixel-map search.
+struct TileDesc {
+    int cmin0, cmin1, rh, rw;
+};
+
+// Counters written by the tile classification.
+enum { CNT_FAST = 0, CNT_EDGE = 1, CNT_GENERIC = 2, CNT_NONE = 3, CNT_GOOD_FAST = 4,
+       CNT_GOOD_EDGE = 5, CNT_GOOD_GENERIC = 6, CNT_N = 8 };
+
+// Round up to a multiple of a such that the row pitch is 8 (mod 32) floats: an 8-wide
+// row of lanes then spans distinct LDS banks in each half-wave.
+__host__ __device__ inline int lds_pitch(int rw) { return rw + ((8 - (rw & 31)) + 32) % 32; }
+
+// ------------------------------------------------------------------------- host helpers
+void set_error(const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+void profile_begin(const char* family, hipStream_t s);
+// work: literal work units, or (when dev_count is given) *dev_count * scale read after
+// the launch (profiling synchronises anyway).
+void profile_end(const char* family, hipStream_t s, long long work, const int* dev_count,
+                 long long scale);
+bool profiling();
+
+// ------------------------------------------------------------------------ kernel entry
+// Each returns PXST_OK or a negative code (and sets the message).
+
+// Reference preparation for lookups: refv = ref where wsum > 0, else NaN; and (when
+// `sat` is non-null) the summed-area table of invalid reference pixels.
+int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv,
+                          int* sat, int* sat_tmp, hipStream_t s);
+
+// Reference update (splat as a deterministic gather over the inverted map).
+int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
+                            hipStream_t s);
+
+// Reference-plane error: ref_err = sum w M eps / sum w M (needs sigma2 in ws s2).
+int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                           const float* refv, float* ref_err, char* ws, const Layout& L,
+                           hipStream_t s);
+
+// Pixel-map search.
+int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
+                     const float* dx, const float* u_in, const pxst_window& win, float* u_out,
+                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s);
+
+// Translation search.
+int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
+                        const float* dx_in, const pxst_window& win, float* dx_out,
+                        float* err_min, int32_t* argmin, char* ws, const Layout& L,
+                        hipStream_t s);
+
+// sigma2[i, j] = (1/N) sum M (I - W)^2 into ws s2.
+int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
+
+// Figures of merit.
+int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2,
+                 const float* u, const float* dx, float* pixel_err, double* frame_err,
+                 double* total, char* ws, const Layout& L, hipStream_t s);
+
+}  // namespace pxst

@@ -1,0 +1,856 @@
+// Pixel-map search (Sec. 2.2.2): brute-force integer candidates, normalised error,
+// first minimum, paraboloid refinement.
+//
+// Candidates are integer points c + k, so for frame n every lookup has the same
+// bilinear fractions (those of dx_n): the reference interpolated for frame n is a
+// fixed image G_n, and the error of candidate k at a pixel is a sum over frames of
+// (I - W G_n[c + k - shift_n])^2.  A work-group owns an 8 x 8 tile of pixels and all
+// of their candidates; per frame it stages the part of G_n that the tile's windows
+// touch into LDS (double buffered) and every lane then evaluates its block of
+// candidates from LDS with two FMAs each.  Tiles are classified first:
+//   FAST    every staged value of every frame is a valid lookup (no per-candidate
+//           bookkeeping: the variance is the same for all candidates);
+//   EDGE    some lookups are invalid: per-candidate variance and frame counts;
+//   GENERIC the staged region does not fit the LDS budget (widely scattered map):
+//           no staging, lookups straight from the reference.
+#include "pxst_device.hpp"
+#include "pxst_internal.hpp"
+
+namespace pxst {
+
+namespace {
+
+constexpr int FOLD = 32;     // frames per block of plain accumulation
+constexpr int PF = 2;        // staged elements per thread whose loads overlap compute
+
+struct PmArgs {
+    const uint16_t* frames;
+    const float* white;
+    const uint8_t* mask;
+    const float* refv;
+    const int* sat;
+    const float* dx;
+    const float* u_in;
+    float* u_out;
+    float* err_out;
+    int* arg_out;
+    TileDesc* tiles;
+    int* lists;        // [3][ntiles]
+    int* counters;
+    int N, H, W, Rs, Rf, o0, o1;
+    int rx, ry, NX, NY, refine;
+    int tiles_x, ntiles;
+    // LDS kernel launch shape
+    int nchunks, nblocks, sub;
+    int stage_cap;      // max RH * RW handled with staging (edge kernel)
+    int fast_cap;       // max RH * RW of the fast kernel (staged elements per frame)
+};
+
+__global__ void k_zero_counters(int* c) {
+    if (threadIdx.x < CNT_N) c[threadIdx.x] = 0;
+}
+
+__device__ inline void write_unchanged(const PmArgs& a, size_t pix, size_t HW) {
+    a.u_out[pix] = a.u_in[pix];
+    a.u_out[HW + pix] = a.u_in[HW + pix];
+    if (a.err_out) a.err_out[pix] = INFINITY;
+    if (a.arg_out) a.arg_out[pix] = -1;
+}
+
+// Rectangle [r0, r1] x [c0, c1] (inclusive) of the reference holds no invalid pixel.
+__device__ inline bool rect_valid(const int* sat, int Rs, int Rf, int r0, int r1, int c0, int c1) {
+    if (r0 < 0 || c0 < 0 || r1 >= Rs || c1 >= Rf) return false;
+    const size_t ld = (size_t)Rf + 1;
+    const int v = sat[(size_t)(r1 + 1) * ld + (c1 + 1)] - sat[(size_t)r0 * ld + (c1 + 1)] -
+                  sat[(size_t)(r1 + 1) * ld + c0] + sat[(size_t)r0 * ld + c0];
+    return v == 0;
+}
+
+// One wave per tile: candidate-centre range, LDS fit and validity of every frame.
+__global__ __launch_bounds__(64) void k_classify(PmArgs a) {
+    const int tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int i = ty * TILE + (lane >> 3), j = tx * TILE + (lane & 7);
+    const size_t HW = (size_t)a.H * a.W;
+    const bool inb = i < a.H && j < a.W;
+    const size_t pix = inb ? (size_t)i * a.W + j : 0;
+    const bool good = inb && a.mask[pix] != 0;
+    int c0 = 0, c1 = 0;
+    if (good) {
+        c0 = window_centre(a.u_in[pix]);
+        c1 = window_centre(a.u_in[HW + pix]);
+    }
+    const int ngood = wave_sum<int>(good ? 1 : 0);
+    if (ngood == 0) {
+        if (inb) write_unchanged(a, pix, HW);
+        if (lane == 0) atomicAdd(&a.counters[CNT_NONE], 1);
+        return;
+    }
+    const int mn0 = wave_min_i(good ? c0 : INT_MAX), mx0 = wave_max_i(good ? c0 : INT_MIN);
+    const int mn1 = wave_min_i(good ? c1 : INT_MAX), mx1 = wave_max_i(good ? c1 : INT_MIN);
+    const long long rh = (long long)mx0 - mn0 + a.NX;
+    const long long rw = (long long)mx1 - mn1 + a.NY;
+    int cls;
+    if (rh * rw > a.stage_cap || rh * (long long)lds_pitch((int)min(rw, (long long)1 << 20)) >
+                                     PM_STAGE_FLOATS) {
+        cls = CNT_GENERIC;
+    } else {
+        // FAST needs, for every frame, all corners of the staged region valid
+        const int T0 = mn0 - a.rx, T1 = mn1 - a.ry;
+        bool ok = true;
+        for (int n = lane; n < a.N; n += 64) {
+            const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+            const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+            const int r0 = T0 - s0.e, c0r = T1 - s1.e;
+            ok = ok && rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + (int)rh, c0r, c0r + (int)rw);
+        }
+        const int bad = wave_sum<int>(ok ? 0 : 1);
+        cls = (bad == 0 && rh * rw <= a.fast_cap) ? CNT_FAST : CNT_EDGE;
+        if (lane == 0) a.tiles[tile] = TileDesc{mn0, mn1, (int)rh, (int)rw};
+    }
+    if (lane == 0) {
+        const int slot = atomicAdd(&a.counters[cls], 1);
+        a.lists[cls * a.ntiles + slot] = tile;
+        atomicAdd(&a.counters[CNT_GOOD_FAST + cls], ngood);
+    }
+}
+
+// Cross-thread first minimum, 3x3 stencil and refinement of one pass's pixels; E
+// holds this thread's normalised errors (window rows kx0.., columns ky0..).
+template <int KR, int CW>
+__device__ inline void finish_pixel(const PmArgs& a, float* smem, const float (&E)[KR][CW],
+                                    float bestE, int bestK, bool good, bool pgood, bool inb,
+                                    size_t pix, size_t HW, int c0, int c1, int blk, bool blk_ok,
+                                    int pip, int ppp, int kx0, int ky0) {
+    const int NX = a.NX, NY = a.NY;
+    float* redE = smem;
+    int* redK = (int*)(smem + a.nblocks * ppp);
+    int* best = redK + a.nblocks * ppp;
+    float* bestv = (float*)(best + ppp);
+    float* sten = bestv + ppp;
+    if (blk_ok) {
+        redE[blk * ppp + pip] = bestE;
+        redK[blk * ppp + pip] = bestK;
+    }
+    __syncthreads();
+    if (blk == 0) {
+        float be = INFINITY;
+        int bk = INT_MAX;
+        for (int b = 0; b < a.nblocks; ++b) {
+            const float e = redE[b * ppp + pip];
+            const int k = redK[b * ppp + pip];
+            if (better(e, k, be, bk)) {
+                be = e;
+                bk = k;
+            }
+        }
+        best[pip] = isfinite(be) ? bk : -1;
+        bestv[pip] = be;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) sten[pip * 9 + q] = INFINITY;
+    }
+    __syncthreads();
+    const int kb = best[pip];
+    if (a.refine && good && kb >= 0) {
+        const int bx = kb / NY, by = kb - bx * NY;
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                const int dxk = kx0 + r - bx, dyk = ky0 + m - by;
+                if (dxk >= -1 && dxk <= 1 && dyk >= -1 && dyk <= 1 && kx0 + r < NX && ky0 + m < NY)
+                    sten[pip * 9 + (dxk + 1) * 3 + (dyk + 1)] = E[r][m];
+            }
+    }
+    __syncthreads();
+    if (blk == 0 && inb) {
+        if (!pgood || kb < 0) {
+            write_unchanged(a, pix, HW);
+        } else {
+            const int bx = kb / NY, by = kb - bx * NY;
+            float ox = 0.f, oy = 0.f;
+            if (a.refine) refine_at(sten + pip * 9, bx, by, NX, NY, ox, oy);
+            a.u_out[pix] = (float)(c0 + bx - a.rx) + ox;
+            a.u_out[HW + pix] = (float)(c1 + by - a.ry) + oy;
+            if (a.err_out) a.err_out[pix] = bestv[pip];
+            if (a.arg_out) a.arg_out[pix] = kb;
+        }
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- LDS-staged search
+//
+// FAST kernel: every staged value of every frame is a valid lookup.  Thread layout:
+// lane -> (pixel of the current pass, sub-group); a candidate block is KR window rows
+// of the full window width; block index = wave * sub + sub-group.  Rows past the
+// window are clamped to its last row so that the frame loop is one branch-free block:
+//   issue the global loads of the next frame's staged elements (PFS per thread),
+//   evaluate this frame's candidates from LDS (rows software-pipelined),
+//   interpolate and store the next frame's elements, barrier.
+constexpr int PFS = 4;
+
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
+    extern __shared__ float smem[];
+    if ((int)blockIdx.x >= a.counters[CNT_FAST]) return;
+    const int tile = a.lists[CNT_FAST * a.ntiles + blockIdx.x];
+    const TileDesc td = a.tiles[tile];
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int RH = td.rh, RW = td.rw, P = lds_pitch(RW);
+    const int T0 = td.cmin0 - a.rx, T1 = td.cmin1 - a.ry;
+    const int bufsz = RH * P;
+    const int nel = RH * RW;
+    const int NX = a.NX, N = a.N, Rf = a.Rf;
+
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int ppp = 64 / a.sub;
+    const int pip = lane & (ppp - 1);
+    const int blk = wave * a.sub + lane / ppp;
+    const bool blk_ok = blk < a.nblocks;
+    const int kx0 = blk * KR;
+    const size_t HW = (size_t)a.H * a.W;
+    const float* __restrict__ refv = a.refv;
+
+    int rowoff[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) rowoff[r] = min(kx0 + r, NX - 1) * P;
+
+    // staged elements of this thread: LDS offset (a dump slot past both buffers when
+    // the element does not exist) and reference offset relative to the frame shift
+    int st_lds[PFS], st_glb[PFS];
+#pragma unroll
+    for (int s = 0; s < PFS; ++s) {
+        const int e = tid + s * nthr;
+        const int r = e < nel ? e / RW : 0, q = e < nel ? e - r * RW : 0;
+        st_lds[s] = e < nel ? r * P + q : 2 * bufsz + tid;
+        st_glb[s] = (T0 + r) * Rf + (T1 + q);
+    }
+
+    for (int pass = 0; pass < a.sub; ++pass) {
+        const int pidx = pass * ppp + pip;
+        const int i = ty * TILE + (pidx >> 3), j = tx * TILE + (pidx & 7);
+        const bool inb = i < a.H && j < a.W;
+        const size_t pix = inb ? (size_t)i * a.W + j : 0;
+        const bool pgood = inb && a.mask[pix] != 0;
+        const bool good = pgood && blk_ok;
+        int c0 = td.cmin0, c1 = td.cmin1;
+        float Wp = 0.f;
+        if (pgood) {
+            c0 = window_centre(a.u_in[pix]);
+            c1 = window_centre(a.u_in[HW + pix]);
+            Wp = a.white[pix];
+        }
+        const float nW = -Wp;
+        const int base = (c0 - td.cmin0) * P + (c1 - td.cmin1);
+
+        float eS[KR][CW], eP[KR][CW];
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                eS[r][m] = 0.f;
+                eP[r][m] = 0.f;
+            }
+        float vS = 0.f, vP = 0.f;
+
+        // stage frame 0 into buffer 0
+        {
+            const AxisShift s0 = axis_shift(a.dx[0], a.o0), s1 = axis_shift(a.dx[1], a.o1);
+            const int goff = s0.e * Rf + s1.e;
+#pragma unroll
+            for (int s = 0; s < PFS; ++s) {
+                const float* p = refv + (st_glb[s] - goff);
+                smem[st_lds[s]] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
+            }
+            __syncthreads();
+        }
+
+        const uint16_t* fp = a.frames + pix;
+        float I = (float)fp[0];
+        for (int n = 0; n < N; ++n) {
+            const int n1 = min(n + 1, N - 1);
+            const float* G = smem + (n & 1) * bufsz + base;
+            float* Gn = smem + ((n + 1) & 1) * bufsz;
+            const float Inext = (float)fp[(size_t)n1 * HW];
+            const AxisShift s0n = axis_shift(a.dx[2 * n1], a.o0);
+            const AxisShift s1n = axis_shift(a.dx[2 * n1 + 1], a.o1);
+            const int goff = s0n.e * Rf + s1n.e;
+            float pv[PFS][4];
+#pragma unroll
+            for (int s = 0; s < PFS; ++s) {
+                const float* p = refv + (st_glb[s] - goff);
+                pv[s][0] = p[0];
+                pv[s][1] = p[1];
+                pv[s][2] = p[Rf];
+                pv[s][3] = p[Rf + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+
+            float cur[CW], nxt[CW];
+#pragma unroll
+            for (int m = 0; m < CW; ++m) cur[m] = G[rowoff[0] + m];
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                if (r + 1 < KR) {
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) nxt[m] = G[rowoff[r + 1] + m];
+                }
+#pragma unroll
+                for (int m = 0; m < CW; ++m) {
+                    const float rr = fmaf(nW, cur[m], I);
+                    eP[r][m] = fmaf(rr, rr, eP[r][m]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (r + 1 < KR) {
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) cur[m] = nxt[m];
+                }
+            }
+            const float v = I - Wp;
+            vP = fmaf(v, v, vP);
+            __builtin_amdgcn_sched_barrier(0);
+
+#pragma unroll
+            for (int s = 0; s < PFS; ++s)
+                Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t, s1n.t);
+            I = Inext;
+            __syncthreads();
+
+            if (((n + 1) % FOLD) == 0) {
+#pragma unroll
+                for (int r = 0; r < KR; ++r)
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
+                two_sum_fold(vS, vP);
+            }
+        }
+
+        // per-thread first minimum over its candidates (index order); the normalised
+        // errors replace the running sums in eS
+        float bestE = INFINITY;
+        int bestK = INT_MAX;
+        const float var = vS + vP;
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                float E = INFINITY;
+                if (good && kx0 + r < NX) {
+                    E = normalised_error(eS[r][m] + eP[r][m], var, N);
+                    if (E < bestE) {
+                        bestE = E;
+                        bestK = (kx0 + r) * CW + m;
+                    }
+                }
+                eS[r][m] = E;
+            }
+        finish_pixel<KR, CW>(a, smem, eS, bestE, bestK, good, pgood, inb, pix, HW, c0, c1, blk, blk_ok,
+                             pip, ppp, kx0, 0);
+    }
+}
+
+// EDGE kernel (general staging with validity bookkeeping).
+//
+// Thread layout: lane -> (pixel of the current pass, sub-group); a candidate block is
+// KR window rows x CW window columns; block index = wave * sub + sub-group.  Rows and
+// columns past the window are clamped to its last row / column so the hot loop is
+// straight-line code; those candidates are dropped when the minimum is taken.
+// EDGE adds per-candidate variance and frame counts for frames with invalid lookups.
+template <int CW, int KR, bool EDGE>
+__global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
+    static_assert(EDGE, "general kernel is the edge variant");
+    extern __shared__ float smem[];
+    const int cls = EDGE ? CNT_EDGE : CNT_FAST;
+    if ((int)blockIdx.x >= a.counters[cls]) return;
+    const int tile = a.lists[cls * a.ntiles + blockIdx.x];
+    const TileDesc td = a.tiles[tile];
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int RH = td.rh, RW = td.rw, P = lds_pitch(RW);
+    const int T0 = td.cmin0 - a.rx, T1 = td.cmin1 - a.ry;
+    const int bufsz = RH * P;
+    const int nel = RH * RW;
+    const int NX = a.NX, NY = a.NY, N = a.N, Rf = a.Rf;
+
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int ppp = 64 / a.sub;
+    const int pip = lane & (ppp - 1);
+    const int blk = wave * a.sub + lane / ppp;
+    const bool blk_ok = blk < a.nblocks;
+    const int rb = blk / a.nchunks, cb = blk - rb * a.nchunks;
+    const int kx0 = rb * KR, ky0 = cb * CW;
+    const size_t HW = (size_t)a.H * a.W;
+
+    // LDS offsets of this thread's window rows and columns (clamped to the window)
+    int rowoff[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) rowoff[r] = min(kx0 + r, NX - 1) * P;
+    int coloff[EDGE ? CW : 1];
+#pragma unroll
+    for (int m = 0; m < (EDGE ? CW : 1); ++m) coloff[m] = min(ky0 + m, NY - 1);
+
+    // staged elements whose loads are issued before the frame's compute
+    int pf_lds[PF], pf_glb[PF];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+        const int e = tid + s * nthr;
+        const int r = e < nel ? e / RW : 0, q = e < nel ? e - (e / RW) * RW : 0;
+        pf_lds[s] = e < nel ? r * P + q : -1;
+        pf_glb[s] = (T0 + r) * Rf + (T1 + q);
+    }
+
+    for (int pass = 0; pass < a.sub; ++pass) {
+        const int pidx = pass * ppp + pip;
+        const int i = ty * TILE + (pidx >> 3), j = tx * TILE + (pidx & 7);
+        const bool inb = i < a.H && j < a.W;
+        const size_t pix = inb ? (size_t)i * a.W + j : 0;
+        const bool pgood = inb && a.mask[pix] != 0;
+        const bool good = pgood && blk_ok;
+        int c0 = td.cmin0, c1 = td.cmin1;
+        float Wp = 0.f;
+        if (pgood) {
+            c0 = window_centre(a.u_in[pix]);
+            c1 = window_centre(a.u_in[HW + pix]);
+            Wp = a.white[pix];
+        }
+        const float nW = -Wp;
+        const int base = (c0 - td.cmin0) * P + (c1 - td.cmin1) + (EDGE ? 0 : ky0);
+
+        float eS[KR][CW], eP[KR][CW];
+        float vK[EDGE ? KR : 1][EDGE ? CW : 1];
+        int nK[EDGE ? KR : 1][EDGE ? CW : 1];
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                eS[r][m] = 0.f;
+                eP[r][m] = 0.f;
+                if (EDGE) {
+                    vK[EDGE ? r : 0][EDGE ? m : 0] = 0.f;
+                    nK[EDGE ? r : 0][EDGE ? m : 0] = 0;
+                }
+            }
+        float vS = 0.f, vP = 0.f;
+        int nfast = 0;
+
+        // stage frame 0 into buffer 0
+        int slow_cur = 0;
+        {
+            const AxisShift s0 = axis_shift(a.dx[0], a.o0), s1 = axis_shift(a.dx[1], a.o1);
+            int mine = 0;
+            for (int e = tid; e < nel; e += nthr) {
+                const int r = e / RW, q = e - r * RW;
+                float g;
+                if (EDGE) {
+                    g = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - s0.e, T1 + q - s1.e, s0.t, s1.t);
+                    mine |= valid(g) ? 0 : 1;
+                } else {
+                    const float* p = a.refv + ((T0 + r - s0.e) * Rf + (T1 + q - s1.e));
+                    g = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
+                }
+                smem[r * P + q] = g;
+            }
+            if (EDGE) slow_cur = __syncthreads_or(mine);
+            else __syncthreads();
+        }
+
+        unsigned short inext = pgood ? a.frames[pix] : 0;
+        for (int n = 0; n < N; ++n) {
+            const float* G = smem + (n & 1) * bufsz + base;
+            float* Gn = smem + ((n + 1) & 1) * bufsz;
+            const bool has_next = n + 1 < N;
+            const float I = (float)inext;
+            if (has_next && pgood) inext = a.frames[(size_t)(n + 1) * HW + pix];
+
+            // issue the first staging loads of frame n + 1
+            AxisShift s0n{0, 0.f}, s1n{0, 0.f};
+            float pv[PF][4];
+            if (has_next) {
+                s0n = axis_shift(a.dx[2 * (n + 1)], a.o0);
+                s1n = axis_shift(a.dx[2 * (n + 1) + 1], a.o1);
+                const int goff = s0n.e * Rf + s1n.e;
+#pragma unroll
+                for (int s = 0; s < PF; ++s) {
+                    if (pf_lds[s] >= 0) {
+                        if (EDGE) {
+                            const int t0 = pf_glb[s] / Rf;   // not the hot path
+                            pv[s][0] = (float)t0;
+                        } else {
+                            const float* p = a.refv + (pf_glb[s] - goff);
+                            pv[s][0] = p[0];
+                            pv[s][1] = p[1];
+                            pv[s][2] = p[Rf];
+                            pv[s][3] = p[Rf + 1];
+                        }
+                    }
+                }
+            }
+
+            __builtin_amdgcn_sched_barrier(0);
+            // evaluate this thread's candidates for frame n
+            const float v = I - Wp;
+            if (!EDGE || !slow_cur) {
+                // rows are software-pipelined: the loads of row r + 1 are issued before
+                // the FMAs of row r, and scheduling barriers keep at most two rows live
+                float cur[CW], nxt[CW];
+#pragma unroll
+                for (int m = 0; m < CW; ++m)
+                    cur[m] = EDGE ? G[rowoff[0] + coloff[EDGE ? m : 0]] : G[rowoff[0] + m];
+#pragma unroll
+                for (int r = 0; r < KR; ++r) {
+                    if (r + 1 < KR) {
+#pragma unroll
+                        for (int m = 0; m < CW; ++m)
+                            nxt[m] = EDGE ? G[rowoff[r + 1] + coloff[EDGE ? m : 0]]
+                                          : G[rowoff[r + 1] + m];
+                    }
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) {
+                        const float rr = fmaf(nW, cur[m], I);
+                        eP[r][m] = fmaf(rr, rr, eP[r][m]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (r + 1 < KR) {
+#pragma unroll
+                        for (int m = 0; m < CW; ++m) cur[m] = nxt[m];
+                    }
+                }
+                vP = fmaf(v, v, vP);
+                ++nfast;
+            } else {
+                const float v2 = v * v;
+#pragma unroll
+                for (int r = 0; r < KR; ++r) {
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) {
+                        const float gv = G[rowoff[r] + coloff[EDGE ? m : 0]];
+                        const bool ok = valid(gv);
+                        const float rr = ok ? fmaf(nW, gv, I) : 0.f;
+                        eP[r][m] = fmaf(rr, rr, eP[r][m]);
+                        vK[EDGE ? r : 0][EDGE ? m : 0] += ok ? v2 : 0.f;
+                        nK[EDGE ? r : 0][EDGE ? m : 0] += ok ? 1 : 0;
+                    }
+                }
+            }
+
+            __builtin_amdgcn_sched_barrier(0);
+            // finish staging frame n + 1
+            int mine = 0;
+            if (has_next) {
+                if (!EDGE) {
+#pragma unroll
+                    for (int s = 0; s < PF; ++s)
+                        if (pf_lds[s] >= 0)
+                            Gn[pf_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t,
+                                                      s1n.t);
+                    for (int e = tid + PF * nthr; e < nel; e += nthr) {
+                        const int r = e / RW, q = e - r * RW;
+                        const float* p = a.refv + ((T0 + r - s0n.e) * Rf + (T1 + q - s1n.e));
+                        Gn[r * P + q] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0n.t, s1n.t);
+                    }
+                } else {
+                    for (int e = tid; e < nel; e += nthr) {
+                        const int r = e / RW, q = e - r * RW;
+                        const float g = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - s0n.e,
+                                                        T1 + q - s1n.e, s0n.t, s1n.t);
+                        Gn[r * P + q] = g;
+                        mine |= valid(g) ? 0 : 1;
+                    }
+                }
+            }
+            if (EDGE) slow_cur = __syncthreads_or(mine);
+            else __syncthreads();
+
+            if (((n + 1) % FOLD) == 0) {
+#pragma unroll
+                for (int r = 0; r < KR; ++r)
+#pragma unroll
+                    for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
+                two_sum_fold(vS, vP);
+            }
+        }
+
+        // per-thread first minimum over its candidates (index order); the normalised
+        // errors replace the running sums in eS
+        float bestE = INFINITY;
+        int bestK = INT_MAX;
+        const float vcommon = vS + vP;
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int m = 0; m < CW; ++m) {
+                float E = INFINITY;
+                if (good && kx0 + r < NX && ky0 + m < NY) {
+                    const float err = eS[r][m] + eP[r][m];
+                    if (EDGE)
+                        E = normalised_error(err, vcommon + vK[EDGE ? r : 0][EDGE ? m : 0],
+                                             nfast + nK[EDGE ? r : 0][EDGE ? m : 0]);
+                    else
+                        E = normalised_error(err, vcommon, N);
+                    if (E < bestE) {
+                        bestE = E;
+                        bestK = (kx0 + r) * NY + (ky0 + m);
+                    }
+                }
+                eS[r][m] = E;
+            }
+
+        finish_pixel<KR, CW>(a, smem, eS, bestE, bestK, good, pgood, inb, pix, HW, c0, c1, blk, blk_ok,
+                             pip, ppp, kx0, ky0);
+    }
+}
+
+// ------------------------------------------------------------------ generic search
+// One work-group of 256 threads per tile: 64 pixels x 4 candidate strides; lookups
+// straight from the reference.  Used for tiles whose staged region would not fit.
+__device__ inline float eval_candidate(const PmArgs& a, size_t pix, size_t HW, int t0, int t1,
+                                       float Wp) {
+    float eS = 0.f, eP = 0.f, vS = 0.f, vP = 0.f;
+    int nv = 0;
+    for (int n = 0; n < a.N; ++n) {
+        const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+        const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+        const float g = masked_bilinear(a.refv, a.Rs, a.Rf, t0 - s0.e, t1 - s1.e, s0.t, s1.t);
+        if (valid(g)) {
+            const float I = (float)a.frames[(size_t)n * HW + pix];
+            const float rr = fmaf(-Wp, g, I);
+            eP = fmaf(rr, rr, eP);
+            const float v = I - Wp;
+            vP = fmaf(v, v, vP);
+            ++nv;
+        }
+        if (((n + 1) % FOLD) == 0) {
+            two_sum_fold(eS, eP);
+            two_sum_fold(vS, vP);
+        }
+    }
+    return normalised_error(eS + eP, vS + vP, nv);
+}
+
+__global__ __launch_bounds__(256) void k_pm_generic(PmArgs a) {
+    __shared__ float redE[4][64];
+    __shared__ int redK[4][64];
+    __shared__ float sten[64][9];
+    const int slot = blockIdx.x;
+    if (slot >= a.counters[CNT_GENERIC]) return;
+    const int tile = a.lists[CNT_GENERIC * a.ntiles + slot];
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int p = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+    const size_t HW = (size_t)a.H * a.W;
+    const bool inb = i < a.H && j < a.W;
+    const size_t pix = inb ? (size_t)i * a.W + j : 0;
+    const bool good = inb && a.mask[pix] != 0;
+    int c0 = 0, c1 = 0;
+    float Wp = 0.f;
+    if (good) {
+        c0 = window_centre(a.u_in[pix]);
+        c1 = window_centre(a.u_in[HW + pix]);
+        Wp = a.white[pix];
+    }
+    const int C = a.NX * a.NY;
+    float be = INFINITY;
+    int bk = INT_MAX;
+    if (good) {
+        for (int k = sub; k < C; k += 4) {
+            const int kx = k / a.NY, ky = k - kx * a.NY;
+            const float E = eval_candidate(a, pix, HW, c0 - a.rx + kx, c1 - a.ry + ky, Wp);
+            if (E < be) {
+                be = E;
+                bk = k;
+            }
+        }
+    }
+    redE[sub][p] = be;
+    redK[sub][p] = bk;
+    __syncthreads();
+    if (sub == 0) {
+        for (int s = 1; s < 4; ++s)
+            if (better(redE[s][p], redK[s][p], be, bk)) {
+                be = redE[s][p];
+                bk = redK[s][p];
+            }
+        redE[0][p] = be;
+        redK[0][p] = isfinite(be) ? bk : -1;
+    }
+    __syncthreads();
+    const int kb = redK[0][p];
+    if (a.refine && good && kb >= 0) {
+        const int bx = kb / a.NY, by = kb - bx * a.NY;
+        for (int q = sub; q < 9; q += 4) {
+            const int kx = bx + q / 3 - 1, ky = by + q % 3 - 1;
+            float E = INFINITY;
+            if (kx >= 0 && kx < a.NX && ky >= 0 && ky < a.NY)
+                E = eval_candidate(a, pix, HW, c0 - a.rx + kx, c1 - a.ry + ky, Wp);
+            sten[p][q] = E;
+        }
+    }
+    __syncthreads();
+    if (sub == 0 && inb) {
+        if (!good || kb < 0) {
+            write_unchanged(a, pix, HW);
+        } else {
+            const int bx = kb / a.NY, by = kb - bx * a.NY;
+            float ox = 0.f, oy = 0.f;
+            if (a.refine) refine_at(sten[p], bx, by, a.NX, a.NY, ox, oy);
+            a.u_out[pix] = (float)(c0 + bx - a.rx) + ox;
+            a.u_out[HW + pix] = (float)(c1 + by - a.ry) + oy;
+            if (a.err_out) a.err_out[pix] = redE[0][p];
+            if (a.arg_out) a.arg_out[pix] = kb;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------ dispatch
+typedef void (*PmKernel)(PmArgs);
+
+struct LdsShape {
+    PmKernel fn;
+    int cw, kr;
+};
+
+template <int CW, int KR>
+constexpr LdsShape fast_shape() { return LdsShape{k_pm_fast<CW, KR>, CW, KR}; }
+template <int CW, int KR>
+constexpr LdsShape edge_shape() { return LdsShape{k_pm_lds<CW, KR, true>, CW, KR}; }
+
+// FAST: full window rows per thread (CW = 2 r_fs + 1), rows per thread chosen so that
+// two accumulators per candidate stay within about 100 registers.
+LdsShape pick_fast(int ny) {
+    switch (ny) {
+        case 1: return fast_shape<1, 8>();
+        case 3: return fast_shape<3, 8>();
+        case 5: return fast_shape<5, 8>();
+        case 7: return fast_shape<7, 8>();
+        case 9: return fast_shape<9, 5>();
+        case 11: return fast_shape<11, 4>();
+        case 13: return fast_shape<13, 4>();
+        case 15: return fast_shape<15, 4>();
+        case 17: return fast_shape<17, 3>();
+        case 19: return fast_shape<19, 3>();
+        case 21: return fast_shape<21, 3>();
+        case 23: return fast_shape<23, 2>();
+        case 25: return fast_shape<25, 2>();
+        case 27: return fast_shape<27, 2>();
+        case 29: return fast_shape<29, 2>();
+        default: return fast_shape<31, 2>();
+    }
+}
+
+// EDGE: four registers per candidate; column chunks of up to 8.
+LdsShape pick_edge(int ny) {
+    switch (ny) {
+        case 1: return edge_shape<1, 8>();
+        case 3: return edge_shape<3, 4>();
+        case 5: return edge_shape<5, 3>();
+        case 7: return edge_shape<7, 2>();
+        default: return edge_shape<8, 2>();
+    }
+}
+
+struct Launch {
+    int nchunks, nblocks, sub, waves;
+};
+
+Launch plan_launch(int nx, int ny, int cw, int kr) {
+    Launch l;
+    l.nchunks = (ny + cw - 1) / cw;
+    l.nblocks = ((nx + kr - 1) / kr) * l.nchunks;
+    l.sub = 1;
+    while ((l.nblocks + l.sub - 1) / l.sub > 8 && l.sub < 8) l.sub *= 2;
+    l.waves = (l.nblocks + l.sub - 1) / l.sub;
+    return l;
+}
+
+size_t lds_bytes(const Launch& l) {
+    const size_t stage = (2 * (size_t)PM_STAGE_FLOATS + 512) * sizeof(float);
+    const int ppp = 64 / l.sub;
+    const size_t red = (size_t)l.nblocks * ppp * 8 + (size_t)ppp * 8 + (size_t)ppp * 9 * 4;
+    return stage > red ? stage : red;
+}
+
+}  // namespace
+
+int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
+                     const float* dx, const float* u_in, const pxst_window& win, float* u_out,
+                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+    PmArgs a{};
+    a.frames = sc.frames;
+    a.white = sc.white;
+    a.mask = sc.mask;
+    a.refv = refv;
+    a.sat = sat;
+    a.dx = dx;
+    a.u_in = u_in;
+    a.u_out = u_out;
+    a.err_out = err_min;
+    a.arg_out = argmin;
+    a.tiles = (TileDesc*)(ws + L.tiles);
+    a.lists = (int*)(ws + L.lists);
+    a.counters = (int*)(ws + L.counters);
+    a.N = g.N;
+    a.H = g.H;
+    a.W = g.W;
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.o0 = g.o0;
+    a.o1 = g.o1;
+    a.rx = win.r_ss;
+    a.ry = win.r_fs;
+    a.NX = 2 * win.r_ss + 1;
+    a.NY = 2 * win.r_fs + 1;
+    a.refine = win.refine != 0;
+    a.tiles_x = (g.W + TILE - 1) / TILE;
+    const int tiles_y = (g.H + TILE - 1) / TILE;
+    a.ntiles = a.tiles_x * tiles_y;
+
+    const LdsShape fs = pick_fast(a.NY), es = pick_edge(a.NY);
+    const Launch lf = plan_launch(a.NX, a.NY, fs.cw, fs.kr);
+    const Launch le = plan_launch(a.NX, a.NY, es.cw, es.kr);
+    // staging capacity: elements per frame over all threads of the smaller launch
+    const int thr_f = lf.waves * 64, thr_e = le.waves * 64;
+    a.stage_cap = 8 * thr_e;
+    a.fast_cap = PFS * thr_f;
+
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a.counters);
+    hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);
+    int rc = check_hip(hipGetLastError(), "pixel-map classification");
+    if (rc) return rc;
+
+    const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
+    {
+        PmArgs b = a;
+        b.nchunks = lf.nchunks;
+        b.nblocks = lf.nblocks;
+        b.sub = lf.sub;
+        const size_t sh = lds_bytes(lf);
+        hipFuncSetAttribute((const void*)fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        profile_begin("pm_fast", s);
+        hipLaunchKernelGGL(fs.fn, dim3(a.ntiles), dim3(lf.waves * 64), sh, s, b);
+        profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
+        rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles)");
+        if (rc) return rc;
+    }
+    {
+        PmArgs b = a;
+        b.nchunks = le.nchunks;
+        b.nblocks = le.nblocks;
+        b.sub = le.sub;
+        const size_t sh = lds_bytes(le);
+        hipFuncSetAttribute((const void*)es.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        profile_begin("pm_edge", s);
+        hipLaunchKernelGGL(es.fn, dim3(a.ntiles), dim3(le.waves * 64), sh, s, b);
+        profile_end("pm_edge", s, 0, a.counters + CNT_GOOD_EDGE, evals_per_good_px);
+        rc = check_hip(hipGetLastError(), "pixel-map search (edge tiles)");
+        if (rc) return rc;
+    }
+    profile_begin("pm_generic", s);
+    hipLaunchKernelGGL(k_pm_generic, dim3(a.ntiles), dim3(256), 0, s, a);
+    profile_end("pm_generic", s, 0, a.counters + CNT_GOOD_GENERIC, evals_per_good_px);
+    return check_hip(hipGetLastError(), "pixel-map search (scattered tiles)");
+}
+
+}  // namespace pxst

@@ -1,0 +1,454 @@
+// Reference update (Sec. 2.2.1 with the bilinear splat of Sec. 4) as a gather.
+//
+// The splat adds every good pixel of every frame at u - dx_n - origin.  Instead of
+// scattering with atomics, the pixels are binned by floor(u) - origin into a cell
+// grid (a stable radix sort of cell keys gives each cell its pixels in index order),
+// and every reference pixel p then gathers, frame by frame, from the 3x3 cells around
+// p + floor(dx_n): only those can put a bilinear corner on p.  The per-frame partial
+// is added with compensated float32 summation; the weight sum is float64.  The order
+// of every sum is fixed, so the result is bitwise reproducible.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "pxst_device.hpp"
+#include "pxst_internal.hpp"
+
+namespace pxst {
+
+namespace {
+
+constexpr unsigned KEY_INVALID_OFF = 1;  // key = ncells + 1: bad pixel
+constexpr unsigned KEY_OVERFLOW_OFF = 0;  // key = ncells: good pixel outside the grid
+
+__global__ void k_fill_i32(int* p, int v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_grid_init(GridInfo* gi) {
+    if (threadIdx.x == 0) {
+        gi->bmin0 = INT_MAX;
+        gi->bmin1 = INT_MAX;
+        gi->bmax0 = INT_MIN;
+        gi->bmax1 = INT_MIN;
+        gi->g0 = 0;
+        gi->g1 = 0;
+        gi->n_good = 0;
+        gi->sum0 = 0;
+        gi->sum1 = 0;
+    }
+}
+
+// Cell of a pixel: floor(u) - origin, clamped far outside any sensible grid.
+__device__ inline int cell_coord(float u, int o) {
+    float f = floorf(u);
+    f = fminf(fmaxf(f, -1.0e9f), 1.0e9f);
+    return (int)f - o;
+}
+
+__global__ void k_grid_bbox(const float* __restrict__ u, const uint8_t* __restrict__ mask, int HW,
+                            int o0, int o1, GridInfo* gi) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool good = k < HW && mask[k] != 0;
+    int b0 = 0, b1 = 0;
+    if (good) {
+        b0 = cell_coord(u[k], o0);
+        b1 = cell_coord(u[HW + k], o1);
+    }
+    const int mn0 = wave_min_i(good ? b0 : INT_MAX), mx0 = wave_max_i(good ? b0 : INT_MIN);
+    const int mn1 = wave_min_i(good ? b1 : INT_MAX), mx1 = wave_max_i(good ? b1 : INT_MIN);
+    const long long s0 = wave_sum<long long>(good ? (long long)b0 : 0);
+    const long long s1 = wave_sum<long long>(good ? (long long)b1 : 0);
+    const int cnt = wave_sum<int>(good ? 1 : 0);
+    if ((threadIdx.x & 63) == 0 && cnt > 0) {
+        atomicMin(&gi->bmin0, mn0);
+        atomicMax(&gi->bmax0, mx0);
+        atomicMin(&gi->bmin1, mn1);
+        atomicMax(&gi->bmax1, mx1);
+        atomicAdd((unsigned long long*)&gi->sum0, (unsigned long long)s0);
+        atomicAdd((unsigned long long*)&gi->sum1, (unsigned long long)s1);
+        atomicAdd(&gi->n_good, cnt);
+    }
+}
+
+// Grid origin: the bounding box (plus a one-cell margin) when it fits the capacity,
+// else a window of the capacity centred on the mean cell.
+__global__ void k_grid_origin(GridInfo* gi, int GH, int GW) {
+    if (threadIdx.x != 0) return;
+    if (gi->n_good == 0) {
+        gi->g0 = 0;
+        gi->g1 = 0;
+        return;
+    }
+    const long long e0 = (long long)gi->bmax0 - gi->bmin0 + 3;
+    const long long e1 = (long long)gi->bmax1 - gi->bmin1 + 3;
+    gi->g0 = e0 <= GH ? gi->bmin0 - 1 : (int)(gi->sum0 / gi->n_good) - GH / 2;
+    gi->g1 = e1 <= GW ? gi->bmin1 - 1 : (int)(gi->sum1 / gi->n_good) - GW / 2;
+}
+
+__global__ void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask, int HW, int o0,
+                       int o1, const GridInfo* __restrict__ gi, int GH, int GW,
+                       unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= HW) return;
+    const unsigned ncells = (unsigned)GH * (unsigned)GW;
+    unsigned key = ncells + KEY_INVALID_OFF;
+    if (mask[k]) {
+        const int c0 = cell_coord(u[k], o0) - gi->g0;
+        const int c1 = cell_coord(u[HW + k], o1) - gi->g1;
+        key = (c0 >= 0 && c0 < GH && c1 >= 0 && c1 < GW) ? (unsigned)c0 * GW + c1
+                                                          : ncells + KEY_OVERFLOW_OFF;
+    }
+    keys[k] = key;
+    vals[k] = (unsigned)k;
+}
+
+// cstart[c] = first sorted position whose key is >= c, for c in [0, ncells + 2].
+__global__ void k_cell_start(const unsigned* __restrict__ keys, int n, unsigned ncells_p2,
+                             unsigned* __restrict__ cstart) {
+    const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncells_p2) return;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    cstart[c] = (unsigned)lo;
+}
+
+// Per sorted entry: fractions of u, white-field, pixel index and cell coordinates.
+__global__ void k_pixel_data(const float* __restrict__ u, const float* __restrict__ white,
+                             const unsigned* __restrict__ vals, int HW, int n_entries, int o0, int o1,
+                             float4* __restrict__ pdata, int2* __restrict__ bsort) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_entries) return;
+    const unsigned k = vals[e];
+    const float u0 = u[k], u1 = u[HW + k];
+    const float f0 = floorf(u0), f1 = floorf(u1);
+    pdata[e] = make_float4(u0 - f0, u1 - f1, white[k], __uint_as_float(k));
+    bsort[e] = make_int2(cell_coord(u0, o0), cell_coord(u1, o1));
+}
+
+// Bilinear weight that reference coordinate p receives from a point whose position
+// along this axis is (cell - floor(dx)) + t, t = frac(u) - frac(dx) in (-1, 1).
+__device__ inline float splat_weight(int p, int base, float t) {
+    // floor of the point = base - (t < 0); fraction = t or t + 1
+    if (t >= 0.f) {
+        if (p == base) return 1.f - t;
+        if (p == base + 1) return t;
+        return 0.f;
+    }
+    if (p == base) return 1.f + t;
+    if (p == base - 1) return -t;
+    return 0.f;
+}
+
+struct GatherArgs {
+    const uint16_t* frames;
+    const float* dx;
+    const float* u;           // for entries outside the grid
+    const float* refv_in;     // error mode: reference for the lookups
+    const float* s2;          // error mode: sigma^2
+    const unsigned* cstart;
+    const float4* pdata;
+    const int2* bsort;
+    const GridInfo* gi;
+    int N, H, W, Rs, Rf, o0, o1, GH, GW;
+    float* out;               // ref (or ref_err)
+    double* wsum;             // weight sums (reference mode)
+    float* refv_out;          // reference mode: ref with NaN for invalid (may be null)
+};
+
+// MODE 0: reference update (value M W I, weight M W^2).
+// MODE 1: reference-plane error (value M eps, weight M).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_ref_gather(GatherArgs a) {
+    const int p1 = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int p0 = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const bool inside = p0 < a.Rs && p1 < a.Rf;
+    const GridInfo gi = *a.gi;
+    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
+    const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
+    const size_t HW = (size_t)a.H * a.W;
+    float S = 0.f, C = 0.f;      // compensated numerator over frames
+    double den = 0.0;
+    if (inside) {
+        for (int n = 0; n < a.N; ++n) {
+            const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+            const float s0 = floorf(d0), s1 = floorf(d1);
+            const float fd0 = d0 - s0, fd1 = d1 - s1;
+            const int q0 = p0 + (int)s0, q1 = p1 + (int)s1;   // cell of a point landing on p
+            if (q0 < gi.bmin0 - 1 || q0 > gi.bmax0 + 1 || q1 < gi.bmin1 - 1 || q1 > gi.bmax1 + 1)
+                continue;
+            const uint16_t* fr = a.frames + (size_t)n * HW;
+            float part = 0.f;
+            double dpart = 0.0;
+            for (int d = -1; d <= 1; ++d) {
+                const int r = q0 + d - gi.g0;
+                if (r < 0 || r >= a.GH) continue;
+                const int c_lo = max(q1 - 1 - gi.g1, 0), c_hi = min(q1 + 1 - gi.g1, a.GW - 1);
+                if (c_lo > c_hi) continue;
+                const unsigned e_begin = a.cstart[(unsigned)r * a.GW + c_lo];
+                const unsigned e_end = a.cstart[(unsigned)r * a.GW + c_hi + 1];
+                for (unsigned e = e_begin; e < e_end; ++e) {
+                    const float4 pd = a.pdata[e];
+                    const int2 b = a.bsort[e];
+                    const float w0 = splat_weight(p0, b.x - (int)s0, pd.x - fd0);
+                    const float w1 = splat_weight(p1, b.y - (int)s1, pd.y - fd1);
+                    const float w = w0 * w1;
+                    if (w == 0.f) continue;
+                    const unsigned k = __float_as_uint(pd.w);
+                    if (MODE == 0) {
+                        const float wi = w * pd.z;
+                        part = fmaf(wi, (float)fr[k], part);
+                        dpart += (double)wi * (double)pd.z;
+                    } else {
+                        // eps of pixel k in frame n
+                        const float u0 = a.u[k], u1 = a.u[HW + k];
+                        const float f0 = floorf(u0), f1 = floorf(u1);
+                        const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
+                        const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
+                        const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
+                        const float g = masked_bilinear(a.refv_in, a.Rs, a.Rf, a0, b0,
+                                                        t0 < 0.f ? t0 + 1.f : t0,
+                                                        t1 < 0.f ? t1 + 1.f : t1);
+                        const float s2 = a.s2[k];
+                        float eps = 0.f;
+                        if (valid(g) && s2 > 0.f) {
+                            const float rr = fmaf(-pd.z, g, (float)fr[k]);
+                            eps = rr * rr / s2;
+                        }
+                        part = fmaf(w, eps, part);
+                        dpart += (double)w;
+                    }
+                }
+            }
+            // good pixels outside the cell grid (none for a sensible map)
+            for (unsigned e = ov_begin; e < ov_end; ++e) {
+                const float4 pd = a.pdata[e];
+                const int2 b = a.bsort[e];
+                const float w0 = splat_weight(p0, b.x - (int)s0, pd.x - fd0);
+                const float w1 = splat_weight(p1, b.y - (int)s1, pd.y - fd1);
+                const float w = w0 * w1;
+                if (w == 0.f) continue;
+                const unsigned k = __float_as_uint(pd.w);
+                if (MODE == 0) {
+                    const float wi = w * pd.z;
+                    part = fmaf(wi, (float)fr[k], part);
+                    dpart += (double)wi * (double)pd.z;
+                } else {
+                    const float u0 = a.u[k], u1 = a.u[HW + k];
+                    const float f0 = floorf(u0), f1 = floorf(u1);
+                    const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
+                    const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
+                    const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
+                    const float g = masked_bilinear(a.refv_in, a.Rs, a.Rf, a0, b0,
+                                                    t0 < 0.f ? t0 + 1.f : t0,
+                                                    t1 < 0.f ? t1 + 1.f : t1);
+                    const float s2 = a.s2[k];
+                    float eps = 0.f;
+                    if (valid(g) && s2 > 0.f) {
+                        const float rr = fmaf(-pd.z, g, (float)fr[k]);
+                        eps = rr * rr / s2;
+                    }
+                    part = fmaf(w, eps, part);
+                    dpart += (double)w;
+                }
+            }
+            kahan_add(S, C, part);
+            den += dpart;
+        }
+        const size_t p = (size_t)p0 * a.Rf + p1;
+        const float val = den > 0.0 ? (float)((double)S / den) : 0.f;
+        a.out[p] = val;
+        if (MODE == 0) {
+            a.wsum[p] = den;
+            if (a.refv_out) a.refv_out[p] = den > 0.0 ? val : qnan();
+        }
+    }
+}
+
+__global__ void k_prep_refv(const float* __restrict__ ref, const double* __restrict__ wsum, int n,
+                            float* __restrict__ refv) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) refv[p] = wsum[p] > 0.0 ? ref[p] : qnan();
+}
+
+// Inclusive prefix sums of the invalid flags along each reference row, written
+// transposed: tmp[c][r].
+__global__ __launch_bounds__(256) void k_sat_rows(const float* __restrict__ refv, int Rs, int Rf,
+                                                  int* __restrict__ tmp) {
+    __shared__ int part[256];
+    const int r = blockIdx.x;
+    const int per = (Rf + 255) / 256;
+    const int c0 = threadIdx.x * per;
+    int s = 0;
+    for (int c = c0; c < min(c0 + per, Rf); ++c) s += valid(refv[(size_t)r * Rf + c]) ? 0 : 1;
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+    for (int c = c0; c < min(c0 + per, Rf); ++c) {
+        run += valid(refv[(size_t)r * Rf + c]) ? 0 : 1;
+        tmp[(size_t)c * Rs + r] = run;
+    }
+}
+
+// Column prefix sums of tmp[c][:] into sat[(r+1)][(c+1)] (row 0 and column 0 are 0).
+__global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, int Rs, int Rf,
+                                                  int* __restrict__ sat) {
+    __shared__ int part[256];
+    const int c = blockIdx.x;
+    const int per = (Rs + 255) / 256;
+    const int r0 = threadIdx.x * per;
+    int s = 0;
+    for (int r = r0; r < min(r0 + per, Rs); ++r) s += tmp[(size_t)c * Rs + r];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+    const size_t ld = (size_t)Rf + 1;
+    for (int r = r0; r < min(r0 + per, Rs); ++r) {
+        run += tmp[(size_t)c * Rs + r];
+        sat[(size_t)(r + 1) * ld + (c + 1)] = run;
+    }
+    if (c == 0) {
+        for (int r = threadIdx.x; r <= Rs; r += 256) sat[(size_t)r * ld] = 0;
+    }
+    if (threadIdx.x == 0) sat[c + 1] = 0;
+}
+
+inline unsigned grid_blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+size_t sort_temp_bound(size_t n) {
+    // radix sort of (u32 key, u32 value) pairs: two scratch copies plus histograms and
+    // look-back state; generous bound, checked against the queried size at run time.
+    return n * 16 + (size_t)(8 << 20);
+}
+
+int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv, int* sat,
+                          int* sat_tmp, hipStream_t s) {
+    const size_t RR = g.RR();
+    if (ref != nullptr)
+        hipLaunchKernelGGL(k_prep_refv, dim3(grid_blocks(RR, 256)), dim3(256), 0, s, ref, wsum,
+                           (int)RR, refv);
+    if (sat != nullptr) {
+        hipLaunchKernelGGL(k_sat_rows, dim3(g.Rs), dim3(256), 0, s, refv, g.Rs, g.Rf, sat_tmp);
+        hipLaunchKernelGGL(k_sat_cols, dim3(g.Rf), dim3(256), 0, s, sat_tmp, g.Rs, g.Rf, sat);
+    }
+    return check_hip(hipGetLastError(), "prepare reference");
+}
+
+// Builds the inverted map (sorted cells) of u; shared by the reference update and
+// the reference-plane error.
+static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u, char* ws,
+                             const Layout& L, hipStream_t s) {
+    const int HW = (int)g.HW();
+    const int GH = grid_h(g), GW = grid_w(g);
+    GridInfo* gi = (GridInfo*)(ws + L.ginfo);
+    unsigned* keys = (unsigned*)(ws + L.keys);
+    unsigned* keys2 = (unsigned*)(ws + L.keys2);
+    unsigned* vals = (unsigned*)(ws + L.vals);
+    unsigned* vals2 = (unsigned*)(ws + L.vals2);
+    unsigned* cstart = (unsigned*)(ws + L.cstart);
+    hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, gi);
+    hipLaunchKernelGGL(k_grid_bbox, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW,
+                       g.o0, g.o1, gi);
+    hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(64), 0, s, gi, GH, GW);
+    hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
+                       g.o1, gi, GH, GW, keys, vals);
+    const unsigned ncells = (unsigned)GH * (unsigned)GW;
+    unsigned bits = 1;
+    while (bits < 32 && ((1ull << bits) <= (unsigned long long)ncells + 1)) ++bits;
+    size_t tb = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, vals, vals2, (size_t)HW, 0,
+                                             bits, s);
+    if (e != hipSuccess) return check_hip(e, "radix sort size query");
+    if (tb > L.sort_tmp_bytes) {
+        set_error("internal: radix sort needs %zu scratch bytes, %zu reserved", tb, L.sort_tmp_bytes);
+        return PXST_EWORKSPACE;
+    }
+    e = rocprim::radix_sort_pairs(ws + L.sort_tmp, tb, keys, keys2, vals, vals2, (size_t)HW, 0, bits,
+                                  s);
+    if (e != hipSuccess) return check_hip(e, "radix sort");
+    hipLaunchKernelGGL(k_cell_start, dim3(grid_blocks((size_t)ncells + 3, 256)), dim3(256), 0, s,
+                       keys2, HW, ncells + 2, cstart);
+    hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals2,
+                       HW, HW, g.o0, g.o1, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
+    return check_hip(hipGetLastError(), "inverse map");
+}
+
+int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
+                            hipStream_t s) {
+    int rc = build_inverse_map(g, sc, u, ws, L, s);
+    if (rc) return rc;
+    GatherArgs a{};
+    a.frames = sc.frames;
+    a.dx = dx;
+    a.u = u;
+    a.cstart = (const unsigned*)(ws + L.cstart);
+    a.pdata = (const float4*)(ws + L.pdata);
+    a.bsort = (const int2*)(ws + L.bsort);
+    a.gi = (const GridInfo*)(ws + L.ginfo);
+    a.N = g.N;
+    a.H = g.H;
+    a.W = g.W;
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.o0 = g.o0;
+    a.o1 = g.o1;
+    a.GH = grid_h(g);
+    a.GW = grid_w(g);
+    a.out = ref;
+    a.wsum = wsum;
+    a.refv_out = refv;
+    dim3 grid((g.Rf + 15) / 16, (g.Rs + 15) / 16);
+    profile_begin("ref_gather", s);
+    hipLaunchKernelGGL(k_ref_gather<0>, grid, dim3(256), 0, s, a);
+    profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
+    return check_hip(hipGetLastError(), "reference gather");
+}
+
+int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                           const float* refv, float* ref_err, char* ws, const Layout& L,
+                           hipStream_t s) {
+    int rc = build_inverse_map(g, sc, u, ws, L, s);
+    if (rc) return rc;
+    GatherArgs a{};
+    a.frames = sc.frames;
+    a.dx = dx;
+    a.u = u;
+    a.refv_in = refv;
+    a.s2 = (const float*)(ws + L.s2);
+    a.cstart = (const unsigned*)(ws + L.cstart);
+    a.pdata = (const float4*)(ws + L.pdata);
+    a.bsort = (const int2*)(ws + L.bsort);
+    a.gi = (const GridInfo*)(ws + L.ginfo);
+    a.N = g.N;
+    a.H = g.H;
+    a.W = g.W;
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.o0 = g.o0;
+    a.o1 = g.o1;
+    a.GH = grid_h(g);
+    a.GW = grid_w(g);
+    a.out = ref_err;
+    dim3 grid((g.Rf + 15) / 16, (g.Rs + 15) / 16);
+    hipLaunchKernelGGL(k_ref_gather<1>, grid, dim3(256), 0, s, a);
+    return check_hip(hipGetLastError(), "reference-plane error");
+}
+
+}  // namespace pxst

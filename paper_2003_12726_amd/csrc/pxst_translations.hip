@@ -1,0 +1,242 @@
+// Translation search (Sec. 2.2.3): for each frame, the error integrated over the
+// detector for integer shifts of that frame's translation, first minimum and
+// paraboloid refinement.
+//
+// Pass 1 (grid: pixel blocks x frames): a thread walks 16 pixels of one frame; for
+// each it loads the (2Tx+2) x (2Ty+2) reference neighbourhood of u - dx_n - origin
+// once and forms all shifted lookups from it (the bilinear fractions do not depend on
+// the integer shift).  Per-shift sums are reduced over the work-group and written as
+// per-block partials.  Pass 2 (one thread per frame) adds the partials in block order
+// with compensated float32 sums, normalises, takes the first minimum and refines.
+#include "pxst_device.hpp"
+#include "pxst_internal.hpp"
+
+namespace pxst {
+
+namespace {
+
+struct TrArgs {
+    const uint16_t* frames;
+    const float* white;
+    const uint8_t* mask;
+    const float* refv;
+    const float* u;
+    const float* dx_in;
+    float* dx_out;
+    float* err_out;
+    int* arg_out;
+    float* part;      // [N][nblk][Ct][3]
+    int N, H, W, Rs, Rf, o0, o1;
+    int nblk, refine;
+};
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
+    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
+    constexpr int CR = 2 * TY + 2;   // neighbourhood columns
+    const int blk = blockIdx.x, n = blockIdx.y;
+    const size_t HW = (size_t)a.H * a.W;
+    const float d0 = a.dx_in[2 * n], d1 = a.dx_in[2 * n + 1];
+    const float s0 = floorf(d0), s1 = floorf(d1);
+    const float fd0 = d0 - s0, fd1 = d1 - s1;
+    const uint16_t* fr = a.frames + (size_t)n * HW;
+
+    float err[CT], var[CT];
+    int cnt[CT];
+#pragma unroll
+    for (int s = 0; s < CT; ++s) {
+        err[s] = 0.f;
+        var[s] = 0.f;
+        cnt[s] = 0;
+    }
+    const size_t p_begin = (size_t)blk * TR_PIX_PER_BLOCK;
+    for (int m = 0; m < TR_PIX_PER_BLOCK / TR_THREADS; ++m) {
+        const size_t pix = p_begin + (size_t)m * TR_THREADS + threadIdx.x;
+        if (pix >= HW || a.mask[pix] == 0) continue;
+        const float u0 = a.u[pix], u1 = a.u[HW + pix];
+        const float f0 = floorf(u0), f1 = floorf(u1);
+        const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
+        const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
+        const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
+        const float fa = t0 < 0.f ? t0 + 1.f : t0, fb = t1 < 0.f ? t1 + 1.f : t1;
+        const float Wp = a.white[pix];
+        const float I = (float)fr[pix];
+        const float v = I - Wp, v2 = v * v;
+        // neighbourhood rows a0 - TX .. a0 + TX + 1, columns b0 - TY .. b0 + TY + 1
+        float rowA[CR], rowB[CR];
+        auto load_row = [&](float* row, int rr) {
+            const bool rin = rr >= 0 && rr < a.Rs;
+#pragma unroll
+            for (int c = 0; c < CR; ++c) {
+                const int cc = b0 - TY + c;
+                row[c] = (rin && cc >= 0 && cc < a.Rf) ? a.refv[(size_t)rr * a.Rf + cc] : qnan();
+            }
+        };
+        // shift sx looks up corner rows a0 - sx and a0 - sx + 1: iterate sx from +TX down
+        load_row(rowA, a0 - TX);
+#pragma unroll
+        for (int ix = 0; ix < NXs; ++ix) {
+            const int sx = TX - ix;              // row a0 - sx = a0 - TX + ix
+            load_row(rowB, a0 - sx + 1);
+#pragma unroll
+            for (int iy = 0; iy < NYs; ++iy) {
+                const int sy = TY - iy;          // column b0 - sy = b0 - TY + iy
+                const int c = iy;
+                const float v00 = rowA[c], v01 = rowA[c + 1], v10 = rowB[c], v11 = rowB[c + 1];
+                float g;
+                if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
+                    g = bilinear4(v00, v01, v10, v11, fa, fb);
+                } else {
+                    const float ga = 1.f - fa, gb = 1.f - fb;
+                    float num = 0.f, den = 0.f;
+                    if (valid(v00)) { num = fmaf(ga * gb, v00, num); den += ga * gb; }
+                    if (valid(v01)) { num = fmaf(ga * fb, v01, num); den += ga * fb; }
+                    if (valid(v10)) { num = fmaf(fa * gb, v10, num); den += fa * gb; }
+                    if (valid(v11)) { num = fmaf(fa * fb, v11, num); den += fa * fb; }
+                    g = den > 0.f ? num / den : qnan();
+                }
+                // candidate index: (sx + TX) * NYs + (sy + TY)
+                const int s = (sx + TX) * NYs + (sy + TY);
+                if (valid(g)) {
+                    const float rr = fmaf(-Wp, g, I);
+                    err[s] = fmaf(rr, rr, err[s]);
+                    var[s] += v2;
+                    cnt[s] += 1;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CR; ++c) rowA[c] = rowB[c];
+        }
+    }
+    // work-group reduction of every per-shift sum
+    __shared__ float red[TR_THREADS / 64][CT * 3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 0; s < CT; ++s) {
+        const float e = wave_sum<float>(err[s]);
+        const float vv = wave_sum<float>(var[s]);
+        const int c = wave_sum<int>(cnt[s]);
+        if (lane == 0) {
+            red[wave][3 * s] = e;
+            red[wave][3 * s + 1] = vv;
+            red[wave][3 * s + 2] = (float)c;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < CT * 3; q += TR_THREADS) {
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < TR_THREADS / 64; ++w) acc += red[w][q];
+        a.part[((size_t)n * a.nblk + blk) * (CT * 3) + q] = acc;
+    }
+}
+
+template <int TX, int TY>
+__global__ void k_tr_final(TrArgs a) {
+    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.N) return;
+    float E[CT];
+    float be = INFINITY;
+    int bk = -1;
+    for (int s = 0; s < CT; ++s) {
+        float eS = 0.f, eC = 0.f, vS = 0.f, vC = 0.f;
+        long long c = 0;
+        for (int b = 0; b < a.nblk; ++b) {
+            const float* p = a.part + ((size_t)n * a.nblk + b) * (CT * 3) + 3 * s;
+            kahan_add(eS, eC, p[0]);
+            kahan_add(vS, vC, p[1]);
+            c += (long long)p[2];
+        }
+        E[s] = normalised_error(eS, vS, c > 0 ? 1 : 0);
+        if (E[s] < be) {
+            be = E[s];
+            bk = s;
+        }
+    }
+    const float d0 = a.dx_in[2 * n], d1 = a.dx_in[2 * n + 1];
+    if (bk < 0) {
+        a.dx_out[2 * n] = d0;
+        a.dx_out[2 * n + 1] = d1;
+        if (a.err_out) a.err_out[n] = INFINITY;
+        if (a.arg_out) a.arg_out[n] = -1;
+        return;
+    }
+    const int bx = bk / NYs, by = bk - bx * NYs;
+    float ox = 0.f, oy = 0.f;
+    if (a.refine) {
+        float st[9];
+        for (int q = 0; q < 9; ++q) {
+            const int kx = bx + q / 3 - 1, ky = by + q % 3 - 1;
+            st[q] = (kx >= 0 && kx < NXs && ky >= 0 && ky < NYs) ? E[kx * NYs + ky] : INFINITY;
+        }
+        refine_at(st, bx, by, NXs, NYs, ox, oy);
+    }
+    a.dx_out[2 * n] = d0 + (float)(bx - TX) + ox;
+    a.dx_out[2 * n + 1] = d1 + (float)(by - TY) + oy;
+    if (a.err_out) a.err_out[n] = be;
+    if (a.arg_out) a.arg_out[n] = bk;
+}
+
+typedef void (*TrKernel)(TrArgs);
+
+template <int TX, int TY>
+void pick(TrKernel& p, TrKernel& f) {
+    p = k_tr_partial<TX, TY>;
+    f = k_tr_final<TX, TY>;
+}
+
+bool pick_tr(int tx, int ty, TrKernel& p, TrKernel& f) {
+    switch (tx * 3 + ty) {
+        case 0: pick<0, 0>(p, f); return true;
+        case 1: pick<0, 1>(p, f); return true;
+        case 2: pick<0, 2>(p, f); return true;
+        case 3: pick<1, 0>(p, f); return true;
+        case 4: pick<1, 1>(p, f); return true;
+        case 5: pick<1, 2>(p, f); return true;
+        case 6: pick<2, 0>(p, f); return true;
+        case 7: pick<2, 1>(p, f); return true;
+        case 8: pick<2, 2>(p, f); return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
+                        const float* dx_in, const pxst_window& win, float* dx_out, float* err_min,
+                        int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+    TrKernel kp = nullptr, kf = nullptr;
+    if (!pick_tr(win.r_ss, win.r_fs, kp, kf)) {
+        set_error("translation window radii must be in 0..%d", PXST_MAX_TR_RADIUS);
+        return PXST_EUNSUPPORTED;
+    }
+    TrArgs a{};
+    a.frames = sc.frames;
+    a.white = sc.white;
+    a.mask = sc.mask;
+    a.refv = refv;
+    a.u = u;
+    a.dx_in = dx_in;
+    a.dx_out = dx_out;
+    a.err_out = err_min;
+    a.arg_out = argmin;
+    a.part = (float*)(ws + L.tr_part);
+    a.N = g.N;
+    a.H = g.H;
+    a.W = g.W;
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.o0 = g.o0;
+    a.o1 = g.o1;
+    a.nblk = (int)((g.HW() + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK);
+    a.refine = win.refine != 0;
+    profile_begin("tr_partial", s);
+    hipLaunchKernelGGL(kp, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
+    profile_end("tr_partial", s,
+                (long long)g.HW() * g.N * (2 * win.r_ss + 1) * (2 * win.r_fs + 1), nullptr, 0);
+    hipLaunchKernelGGL(kf, dim3((g.N + 63) / 64), dim3(64), 0, s, a);
+    return check_hip(hipGetLastError(), "translation search");
+}
+
+}  // namespace pxst

@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol of
+include/pxst.h, sizes workspaces, and rejects bad arguments before any GPU work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2003_12726_amd as pxst
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(HERE, "..", "include", "pxst.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pxst.LIB_PATH):
+        from paper_2003_12726_amd import build
+        build.build(verbose=False)
+    return pxst.load_library()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pxst_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pxst.SYMBOLS)
+    assert pxst.abi_version() == 1
+
+
+def test_workspace_bytes_grows_with_problem(lib):
+    g1 = pxst.make_geom(32, (64, 64), (128, 128), (-37, -37))
+    g2 = pxst.make_geom(121, (256, 1024), (512, 1536), (-141, -269))
+    o = pxst.make_opts(3, (4, 4))
+    a, b = pxst.workspace_bytes(g1, o), pxst.workspace_bytes(g2, o)
+    assert 0 < a < b
+    assert pxst.workspace_bytes(g1, None) > 0
+
+
+def test_invalid_geometry_rejected(lib):
+    g = pxst.make_geom(0, (64, 64), (128, 128), (0, 0))
+    assert lib.pxst_workspace_bytes(ctypes.byref(g), None) == 0
+    assert "positive" in pxst.last_error()
+    o = pxst.make_opts(3, (16, 4))
+    g = pxst.make_geom(4, (64, 64), (128, 128), (0, 0))
+    assert lib.pxst_workspace_bytes(ctypes.byref(g), ctypes.byref(o)) == 0
+
+
+def _scan(frames=0x1000, white=0x2000, mask=0x3000, geom=None):
+    geom = geom or pxst.make_geom(4, (16, 16), (40, 40), (-10, -10))
+    return pxst.CScan(frames, white, mask, geom)
+
+
+def test_error_paths_return_before_gpu_work(lib):
+    """Fake (never dereferenced) addresses: validation must fail before any launch."""
+    sc = _scan()
+    win = pxst.make_window(3, 3)
+    P = 0x4000
+    # null frames
+    bad = _scan(frames=None)
+    assert lib.pxst_update_reference(ctypes.byref(bad), P, P, P, P, P, 1 << 30, None) == pxst.PXST_EINVAL
+    # null output
+    assert lib.pxst_update_reference(ctypes.byref(sc), P, P, None, P, P, 1 << 30, None) == pxst.PXST_EINVAL
+    # misaligned double pointer
+    assert lib.pxst_update_reference(ctypes.byref(sc), P, P, P, P + 4, P, 1 << 30, None) == pxst.PXST_EINVAL
+    # workspace too small
+    assert lib.pxst_update_reference(ctypes.byref(sc), P, P, P, P, 0x100000, 16, None) == pxst.PXST_EWORKSPACE
+    assert "workspace" in pxst.last_error()
+    # misaligned workspace
+    assert lib.pxst_update_reference(ctypes.byref(sc), P, P, P, P, 0x100010, 1 << 30, None) == pxst.PXST_EINVAL
+    # window too large
+    big = pxst.make_window(16, 2)
+    assert lib.pxst_update_pixel_map(ctypes.byref(sc), P, P, P, P, big, P, None, None, P, 1 << 30,
+                                     None) == pxst.PXST_EUNSUPPORTED
+    neg = pxst.make_window(-1, 2)
+    assert lib.pxst_update_pixel_map(ctypes.byref(sc), P, P, P, P, neg, P, None, None, P, 1 << 30,
+                                     None) == pxst.PXST_EINVAL
+    # translation window too large
+    assert lib.pxst_update_translations(ctypes.byref(sc), P, P, P, P, pxst.make_window(3, 1), P, None,
+                                        None, P, 1 << 30, None) == pxst.PXST_EUNSUPPORTED
+    # error: total is required
+    assert lib.pxst_error(ctypes.byref(sc), P, P, P, P, None, None, None, None, P, 1 << 30,
+                          None) == pxst.PXST_EINVAL
+    # solve: null options, negative iterations
+    assert lib.pxst_solve(ctypes.byref(sc), None, P, P, P, P, None, P, 1 << 30, None) == pxst.PXST_EINVAL
+    o = pxst.make_opts(-1, (3, 3))
+    assert lib.pxst_solve(ctypes.byref(sc), ctypes.byref(o), P, P, P, P, None, P, 1 << 30,
+                          None) == pxst.PXST_EINVAL
+    # oversized detector
+    huge = _scan(geom=pxst.make_geom(4, (8192, 4096), (40, 40), (0, 0)))
+    assert lib.pxst_update_reference(ctypes.byref(huge), P, P, P, P, P, 1 << 40, None) == pxst.PXST_EUNSUPPORTED
+
+
+def test_batch_rejects_bad_jobs(lib):
+    job = pxst.CJob()
+    job.scan = _scan()
+    job.opts = pxst.make_opts(2, (2, 2))
+    job.iter = 5            # > n_iter
+    job.ws = 0x100000
+    job.ws_bytes = 1 << 30
+    arr = (pxst.CJob * 1)(job)
+    assert lib.pxst_batch_iterate(arr, 1, None, 0, None) == pxst.PXST_EINVAL
+    assert lib.pxst_batch_iterate(None, 2, None, 0, None) == pxst.PXST_EINVAL
+
+
+def test_product_path_does_not_import_oracle():
+    """The package and its sources never reference the oracle."""
+    root = os.path.dirname(pxst.__file__)
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
