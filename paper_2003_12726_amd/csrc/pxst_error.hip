@@ -1,7 +1,7 @@
 // Figures of merit (Sec. 2.2.4, integrand of Eq. 2) and the per-pixel variance.
 //
 // sigma2 = (1/N) sum_n M (I - W)^2 per pixel.  The error pass streams the frames
-// once: every thread owns 4 pixels, forms eps = M (I - W g)^2 / sigma2 with the
+// once: every thread owns one pixel, forms eps = M (I - W g)^2 / sigma2 with the
 // masked bilinear lookup at u - dx_n - origin, accumulates the pixel error with
 // compensated float32 sums and adds the frame error in float64 per wave; the final
 // pass adds the per-block frame partials in block order and the frames in frame
@@ -13,7 +13,7 @@ namespace pxst {
 
 namespace {
 
-constexpr int ERR_PIX_PER_THREAD = 4;
+constexpr int ERR_PIX_PER_THREAD = ERR_PIX_PER_THREAD_CFG;
 
 __global__ void k_sigma2(const uint16_t* __restrict__ frames, const float* __restrict__ white,
                          const uint8_t* __restrict__ mask, int N, size_t HW, float* __restrict__ s2) {

@@ -31,6 +31,7 @@ constexpr int TR_THREADS = 256;
 constexpr int TR_CT_MAX = (2 * PXST_MAX_TR_RADIUS + 1) * (2 * PXST_MAX_TR_RADIUS + 1);
 // Error evaluation: pixels per work-group.
 constexpr int ERR_THREADS = 256;
+constexpr int ERR_PIX_PER_THREAD_CFG = 1;
 
 // Inverse-map (reference gather) cell grid: capacity per axis.
 inline int grid_h(const Geom& g) { return 2 * (g.H > g.Rs ? g.H : g.Rs) + 8; }
@@ -45,12 +46,19 @@ struct GridInfo {
     long long sum0, sum1;             // sums of the cell coordinates (for a centred origin)
 };
 
+// Per-block partial of the bounding-box reduction.
+struct GridPart {
+    int bmin0, bmin1, bmax0, bmax1, n_good, pad0;
+    long long sum0, sum1;
+};
+constexpr int GRID_THREADS = 256;
+
 // Workspace layout: every section at a 256-byte aligned offset.
 struct Layout {
     // common
     size_t refv, sat, sat_tmp, s2;
     // reference update
-    size_t ginfo, keys, keys2, vals, vals2, cstart, pdata, bsort, sort_tmp;
+    size_t ginfo, gpart, keys, keys2, vals, vals2, cstart, pdata, bsort, sort_tmp;
     size_t sort_tmp_bytes;
     // pixel map
     size_t tiles, lists, counters;

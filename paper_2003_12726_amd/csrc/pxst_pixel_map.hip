@@ -352,27 +352,25 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
     }
 }
 
-// EDGE kernel (general staging with validity bookkeeping).
-//
-// Thread layout: lane -> (pixel of the current pass, sub-group); a candidate block is
-// KR window rows x CW window columns; block index = wave * sub + sub-group.  Rows and
-// columns past the window are clamped to its last row / column so the hot loop is
-// straight-line code; those candidates are dropped when the minimum is taken.
-// EDGE adds per-candidate variance and frame counts for frames with invalid lookups.
-template <int CW, int KR, bool EDGE>
-__global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
-    static_assert(EDGE, "general kernel is the edge variant");
+// EDGE kernel: some staged lookups are invalid (NaN) in some frames.  Same thread
+// layout as the FAST kernel.  A frame whose staged region holds no invalid value is a
+// "fast frame": every candidate is valid, so the variance and frame count are common
+// to all candidates of a pixel.  In the other ("slow") frames each candidate adds its
+// squared residual and (I - W)^2 only when its lookup is valid; the per-candidate
+// variance of slow frames starts at -0.0, so its sign bit records whether any slow
+// frame was valid (-0.0 + x is +0.0 or positive for every x >= +0.0).
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
     extern __shared__ float smem[];
-    const int cls = EDGE ? CNT_EDGE : CNT_FAST;
-    if ((int)blockIdx.x >= a.counters[cls]) return;
-    const int tile = a.lists[cls * a.ntiles + blockIdx.x];
+    if ((int)blockIdx.x >= a.counters[CNT_EDGE]) return;
+    const int tile = a.lists[CNT_EDGE * a.ntiles + blockIdx.x];
     const TileDesc td = a.tiles[tile];
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int RH = td.rh, RW = td.rw, P = lds_pitch(RW);
     const int T0 = td.cmin0 - a.rx, T1 = td.cmin1 - a.ry;
     const int bufsz = RH * P;
     const int nel = RH * RW;
-    const int NX = a.NX, NY = a.NY, N = a.N, Rf = a.Rf;
+    const int NX = a.NX, N = a.N, Rf = a.Rf;
 
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -380,27 +378,13 @@ __global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
     const int pip = lane & (ppp - 1);
     const int blk = wave * a.sub + lane / ppp;
     const bool blk_ok = blk < a.nblocks;
-    const int rb = blk / a.nchunks, cb = blk - rb * a.nchunks;
-    const int kx0 = rb * KR, ky0 = cb * CW;
+    const int kx0 = blk * KR;
     const size_t HW = (size_t)a.H * a.W;
+    const float* __restrict__ refv = a.refv;
 
-    // LDS offsets of this thread's window rows and columns (clamped to the window)
     int rowoff[KR];
 #pragma unroll
     for (int r = 0; r < KR; ++r) rowoff[r] = min(kx0 + r, NX - 1) * P;
-    int coloff[EDGE ? CW : 1];
-#pragma unroll
-    for (int m = 0; m < (EDGE ? CW : 1); ++m) coloff[m] = min(ky0 + m, NY - 1);
-
-    // staged elements whose loads are issued before the frame's compute
-    int pf_lds[PF], pf_glb[PF];
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-        const int e = tid + s * nthr;
-        const int r = e < nel ? e / RW : 0, q = e < nel ? e - (e / RW) * RW : 0;
-        pf_lds[s] = e < nel ? r * P + q : -1;
-        pf_glb[s] = (T0 + r) * Rf + (T1 + q);
-    }
 
     for (int pass = 0; pass < a.sub; ++pass) {
         const int pidx = pass * ppp + pip;
@@ -417,95 +401,51 @@ __global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
             Wp = a.white[pix];
         }
         const float nW = -Wp;
-        const int base = (c0 - td.cmin0) * P + (c1 - td.cmin1) + (EDGE ? 0 : ky0);
+        const int base = (c0 - td.cmin0) * P + (c1 - td.cmin1);
 
-        float eS[KR][CW], eP[KR][CW];
-        float vK[EDGE ? KR : 1][EDGE ? CW : 1];
-        int nK[EDGE ? KR : 1][EDGE ? CW : 1];
+        float eS[KR][CW], eP[KR][CW], vK[KR][CW];
 #pragma unroll
         for (int r = 0; r < KR; ++r)
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
                 eS[r][m] = 0.f;
                 eP[r][m] = 0.f;
-                if (EDGE) {
-                    vK[EDGE ? r : 0][EDGE ? m : 0] = 0.f;
-                    nK[EDGE ? r : 0][EDGE ? m : 0] = 0;
-                }
+                vK[r][m] = -0.f;
             }
         float vS = 0.f, vP = 0.f;
         int nfast = 0;
 
         // stage frame 0 into buffer 0
-        int slow_cur = 0;
+        int slow_cur;
         {
             const AxisShift s0 = axis_shift(a.dx[0], a.o0), s1 = axis_shift(a.dx[1], a.o1);
             int mine = 0;
             for (int e = tid; e < nel; e += nthr) {
                 const int r = e / RW, q = e - r * RW;
-                float g;
-                if (EDGE) {
-                    g = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - s0.e, T1 + q - s1.e, s0.t, s1.t);
-                    mine |= valid(g) ? 0 : 1;
-                } else {
-                    const float* p = a.refv + ((T0 + r - s0.e) * Rf + (T1 + q - s1.e));
-                    g = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
-                }
+                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - s0.e, T1 + q - s1.e, s0.t, s1.t);
                 smem[r * P + q] = g;
+                mine |= valid(g) ? 0 : 1;
             }
-            if (EDGE) slow_cur = __syncthreads_or(mine);
-            else __syncthreads();
+            slow_cur = __syncthreads_or(mine);
         }
 
-        unsigned short inext = pgood ? a.frames[pix] : 0;
+        const uint16_t* fp = a.frames + pix;
+        float I = (float)fp[0];
         for (int n = 0; n < N; ++n) {
+            const int n1 = min(n + 1, N - 1);
             const float* G = smem + (n & 1) * bufsz + base;
             float* Gn = smem + ((n + 1) & 1) * bufsz;
-            const bool has_next = n + 1 < N;
-            const float I = (float)inext;
-            if (has_next && pgood) inext = a.frames[(size_t)(n + 1) * HW + pix];
-
-            // issue the first staging loads of frame n + 1
-            AxisShift s0n{0, 0.f}, s1n{0, 0.f};
-            float pv[PF][4];
-            if (has_next) {
-                s0n = axis_shift(a.dx[2 * (n + 1)], a.o0);
-                s1n = axis_shift(a.dx[2 * (n + 1) + 1], a.o1);
-                const int goff = s0n.e * Rf + s1n.e;
-#pragma unroll
-                for (int s = 0; s < PF; ++s) {
-                    if (pf_lds[s] >= 0) {
-                        if (EDGE) {
-                            const int t0 = pf_glb[s] / Rf;   // not the hot path
-                            pv[s][0] = (float)t0;
-                        } else {
-                            const float* p = a.refv + (pf_glb[s] - goff);
-                            pv[s][0] = p[0];
-                            pv[s][1] = p[1];
-                            pv[s][2] = p[Rf];
-                            pv[s][3] = p[Rf + 1];
-                        }
-                    }
-                }
-            }
-
-            __builtin_amdgcn_sched_barrier(0);
-            // evaluate this thread's candidates for frame n
+            const float Inext = (float)fp[(size_t)n1 * HW];
             const float v = I - Wp;
-            if (!EDGE || !slow_cur) {
-                // rows are software-pipelined: the loads of row r + 1 are issued before
-                // the FMAs of row r, and scheduling barriers keep at most two rows live
+            if (!slow_cur) {
                 float cur[CW], nxt[CW];
 #pragma unroll
-                for (int m = 0; m < CW; ++m)
-                    cur[m] = EDGE ? G[rowoff[0] + coloff[EDGE ? m : 0]] : G[rowoff[0] + m];
+                for (int m = 0; m < CW; ++m) cur[m] = G[rowoff[0] + m];
 #pragma unroll
                 for (int r = 0; r < KR; ++r) {
                     if (r + 1 < KR) {
 #pragma unroll
-                        for (int m = 0; m < CW; ++m)
-                            nxt[m] = EDGE ? G[rowoff[r + 1] + coloff[EDGE ? m : 0]]
-                                          : G[rowoff[r + 1] + m];
+                        for (int m = 0; m < CW; ++m) nxt[m] = G[rowoff[r + 1] + m];
                     }
 #pragma unroll
                     for (int m = 0; m < CW; ++m) {
@@ -526,43 +466,29 @@ __global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
                 for (int r = 0; r < KR; ++r) {
 #pragma unroll
                     for (int m = 0; m < CW; ++m) {
-                        const float gv = G[rowoff[r] + coloff[EDGE ? m : 0]];
+                        const float gv = G[rowoff[r] + m];
                         const bool ok = valid(gv);
                         const float rr = ok ? fmaf(nW, gv, I) : 0.f;
                         eP[r][m] = fmaf(rr, rr, eP[r][m]);
-                        vK[EDGE ? r : 0][EDGE ? m : 0] += ok ? v2 : 0.f;
-                        nK[EDGE ? r : 0][EDGE ? m : 0] += ok ? 1 : 0;
+                        vK[r][m] += ok ? v2 : -0.f;
                     }
                 }
             }
-
             __builtin_amdgcn_sched_barrier(0);
-            // finish staging frame n + 1
+
+            // stage frame n + 1 (the last frame is staged again harmlessly)
+            const AxisShift s0n = axis_shift(a.dx[2 * n1], a.o0);
+            const AxisShift s1n = axis_shift(a.dx[2 * n1 + 1], a.o1);
             int mine = 0;
-            if (has_next) {
-                if (!EDGE) {
-#pragma unroll
-                    for (int s = 0; s < PF; ++s)
-                        if (pf_lds[s] >= 0)
-                            Gn[pf_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t,
-                                                      s1n.t);
-                    for (int e = tid + PF * nthr; e < nel; e += nthr) {
-                        const int r = e / RW, q = e - r * RW;
-                        const float* p = a.refv + ((T0 + r - s0n.e) * Rf + (T1 + q - s1n.e));
-                        Gn[r * P + q] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0n.t, s1n.t);
-                    }
-                } else {
-                    for (int e = tid; e < nel; e += nthr) {
-                        const int r = e / RW, q = e - r * RW;
-                        const float g = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - s0n.e,
-                                                        T1 + q - s1n.e, s0n.t, s1n.t);
-                        Gn[r * P + q] = g;
-                        mine |= valid(g) ? 0 : 1;
-                    }
-                }
+            for (int e = tid; e < nel; e += nthr) {
+                const int r = e / RW, q = e - r * RW;
+                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - s0n.e, T1 + q - s1n.e, s0n.t,
+                                                s1n.t);
+                Gn[r * P + q] = g;
+                mine |= valid(g) ? 0 : 1;
             }
-            if (EDGE) slow_cur = __syncthreads_or(mine);
-            else __syncthreads();
+            I = Inext;
+            slow_cur = __syncthreads_or(mine);
 
             if (((n + 1) % FOLD) == 0) {
 #pragma unroll
@@ -573,8 +499,6 @@ __global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
             }
         }
 
-        // per-thread first minimum over its candidates (index order); the normalised
-        // errors replace the running sums in eS
         float bestE = INFINITY;
         int bestK = INT_MAX;
         const float vcommon = vS + vP;
@@ -583,23 +507,18 @@ __global__ __launch_bounds__(512) void k_pm_lds(const PmArgs a) {
 #pragma unroll
             for (int m = 0; m < CW; ++m) {
                 float E = INFINITY;
-                if (good && kx0 + r < NX && ky0 + m < NY) {
-                    const float err = eS[r][m] + eP[r][m];
-                    if (EDGE)
-                        E = normalised_error(err, vcommon + vK[EDGE ? r : 0][EDGE ? m : 0],
-                                             nfast + nK[EDGE ? r : 0][EDGE ? m : 0]);
-                    else
-                        E = normalised_error(err, vcommon, N);
+                if (good && kx0 + r < NX) {
+                    const bool any = nfast > 0 || !signbit(vK[r][m]);
+                    E = normalised_error(eS[r][m] + eP[r][m], vcommon + vK[r][m], any ? 1 : 0);
                     if (E < bestE) {
                         bestE = E;
-                        bestK = (kx0 + r) * NY + (ky0 + m);
+                        bestK = (kx0 + r) * CW + m;
                     }
                 }
                 eS[r][m] = E;
             }
-
         finish_pixel<KR, CW>(a, smem, eS, bestE, bestK, good, pgood, inb, pix, HW, c0, c1, blk, blk_ok,
-                             pip, ppp, kx0, ky0);
+                             pip, ppp, kx0, 0);
     }
 }
 
@@ -715,7 +634,7 @@ struct LdsShape {
 template <int CW, int KR>
 constexpr LdsShape fast_shape() { return LdsShape{k_pm_fast<CW, KR>, CW, KR}; }
 template <int CW, int KR>
-constexpr LdsShape edge_shape() { return LdsShape{k_pm_lds<CW, KR, true>, CW, KR}; }
+constexpr LdsShape edge_shape() { return LdsShape{k_pm_edge<CW, KR>, CW, KR}; }
 
 // FAST: full window rows per thread (CW = 2 r_fs + 1), rows per thread chosen so that
 // two accumulators per candidate stay within about 100 registers.
@@ -740,14 +659,26 @@ LdsShape pick_fast(int ny) {
     }
 }
 
-// EDGE: four registers per candidate; column chunks of up to 8.
+// EDGE: three registers per candidate (two for the compensated error, one for the
+// variance of frames with invalid lookups), full window rows.
 LdsShape pick_edge(int ny) {
     switch (ny) {
         case 1: return edge_shape<1, 8>();
-        case 3: return edge_shape<3, 4>();
-        case 5: return edge_shape<5, 3>();
-        case 7: return edge_shape<7, 2>();
-        default: return edge_shape<8, 2>();
+        case 3: return edge_shape<3, 8>();
+        case 5: return edge_shape<5, 8>();
+        case 7: return edge_shape<7, 5>();
+        case 9: return edge_shape<9, 4>();
+        case 11: return edge_shape<11, 3>();
+        case 13: return edge_shape<13, 3>();
+        case 15: return edge_shape<15, 2>();
+        case 17: return edge_shape<17, 2>();
+        case 19: return edge_shape<19, 2>();
+        case 21: return edge_shape<21, 2>();
+        case 23: return edge_shape<23, 1>();
+        case 25: return edge_shape<25, 1>();
+        case 27: return edge_shape<27, 1>();
+        case 29: return edge_shape<29, 1>();
+        default: return edge_shape<31, 1>();
     }
 }
 

@@ -19,34 +19,18 @@ namespace {
 constexpr unsigned KEY_INVALID_OFF = 1;  // key = ncells + 1: bad pixel
 constexpr unsigned KEY_OVERFLOW_OFF = 0;  // key = ncells: good pixel outside the grid
 
-__global__ void k_fill_i32(int* p, int v, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
-__global__ void k_grid_init(GridInfo* gi) {
-    if (threadIdx.x == 0) {
-        gi->bmin0 = INT_MAX;
-        gi->bmin1 = INT_MAX;
-        gi->bmax0 = INT_MIN;
-        gi->bmax1 = INT_MIN;
-        gi->g0 = 0;
-        gi->g1 = 0;
-        gi->n_good = 0;
-        gi->sum0 = 0;
-        gi->sum1 = 0;
-    }
-}
-
-// Cell of a pixel: floor(u) - origin, clamped far outside any sensible grid.
+// Bounding box, sum and count of the cells of the good pixels: one partial per block
+// (no atomics), then one block reduces the partials in block order.
 __device__ inline int cell_coord(float u, int o) {
     float f = floorf(u);
     f = fminf(fmaxf(f, -1.0e9f), 1.0e9f);
     return (int)f - o;
 }
 
-__global__ void k_grid_bbox(const float* __restrict__ u, const uint8_t* __restrict__ mask, int HW,
-                            int o0, int o1, GridInfo* gi) {
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restrict__ u,
+                                                            const uint8_t* __restrict__ mask, int HW,
+                                                            int o0, int o1, GridPart* __restrict__ part) {
+    __shared__ GridPart wp[GRID_THREADS / 64];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const bool good = k < HW && mask[k] != 0;
     int b0 = 0, b1 = 0;
@@ -54,35 +38,84 @@ __global__ void k_grid_bbox(const float* __restrict__ u, const uint8_t* __restri
         b0 = cell_coord(u[k], o0);
         b1 = cell_coord(u[HW + k], o1);
     }
-    const int mn0 = wave_min_i(good ? b0 : INT_MAX), mx0 = wave_max_i(good ? b0 : INT_MIN);
-    const int mn1 = wave_min_i(good ? b1 : INT_MAX), mx1 = wave_max_i(good ? b1 : INT_MIN);
-    const long long s0 = wave_sum<long long>(good ? (long long)b0 : 0);
-    const long long s1 = wave_sum<long long>(good ? (long long)b1 : 0);
-    const int cnt = wave_sum<int>(good ? 1 : 0);
-    if ((threadIdx.x & 63) == 0 && cnt > 0) {
-        atomicMin(&gi->bmin0, mn0);
-        atomicMax(&gi->bmax0, mx0);
-        atomicMin(&gi->bmin1, mn1);
-        atomicMax(&gi->bmax1, mx1);
-        atomicAdd((unsigned long long*)&gi->sum0, (unsigned long long)s0);
-        atomicAdd((unsigned long long*)&gi->sum1, (unsigned long long)s1);
-        atomicAdd(&gi->n_good, cnt);
+    GridPart g;
+    g.bmin0 = wave_min_i(good ? b0 : INT_MAX);
+    g.bmax0 = wave_max_i(good ? b0 : INT_MIN);
+    g.bmin1 = wave_min_i(good ? b1 : INT_MAX);
+    g.bmax1 = wave_max_i(good ? b1 : INT_MIN);
+    g.sum0 = wave_sum<long long>(good ? (long long)b0 : 0);
+    g.sum1 = wave_sum<long long>(good ? (long long)b1 : 0);
+    g.n_good = wave_sum<int>(good ? 1 : 0);
+    g.pad0 = 0;
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wp[w] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GridPart t = wp[0];
+        for (int q = 1; q < GRID_THREADS / 64; ++q) {
+            t.bmin0 = min(t.bmin0, wp[q].bmin0);
+            t.bmax0 = max(t.bmax0, wp[q].bmax0);
+            t.bmin1 = min(t.bmin1, wp[q].bmin1);
+            t.bmax1 = max(t.bmax1, wp[q].bmax1);
+            t.sum0 += wp[q].sum0;
+            t.sum1 += wp[q].sum1;
+            t.n_good += wp[q].n_good;
+        }
+        part[blockIdx.x] = t;
     }
 }
 
-// Grid origin: the bounding box (plus a one-cell margin) when it fits the capacity,
-// else a window of the capacity centred on the mean cell.
-__global__ void k_grid_origin(GridInfo* gi, int GH, int GW) {
+// Reduces the partials and sets the grid origin: the bounding box (plus a one-cell
+// margin) when it fits the capacity, else a window of the capacity centred on the
+// mean cell.
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __restrict__ part,
+                                                              int nparts, GridInfo* gi, int GH,
+                                                              int GW) {
+    __shared__ GridPart wp[GRID_THREADS];
+    GridPart t;
+    t.bmin0 = t.bmin1 = INT_MAX;
+    t.bmax0 = t.bmax1 = INT_MIN;
+    t.sum0 = t.sum1 = 0;
+    t.n_good = 0;
+    t.pad0 = 0;
+    for (int q = threadIdx.x; q < nparts; q += GRID_THREADS) {
+        const GridPart p = part[q];
+        t.bmin0 = min(t.bmin0, p.bmin0);
+        t.bmax0 = max(t.bmax0, p.bmax0);
+        t.bmin1 = min(t.bmin1, p.bmin1);
+        t.bmax1 = max(t.bmax1, p.bmax1);
+        t.sum0 += p.sum0;
+        t.sum1 += p.sum1;
+        t.n_good += p.n_good;
+    }
+    wp[threadIdx.x] = t;
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    if (gi->n_good == 0) {
+    for (int q = 1; q < GRID_THREADS; ++q) {
+        t.bmin0 = min(t.bmin0, wp[q].bmin0);
+        t.bmax0 = max(t.bmax0, wp[q].bmax0);
+        t.bmin1 = min(t.bmin1, wp[q].bmin1);
+        t.bmax1 = max(t.bmax1, wp[q].bmax1);
+        t.sum0 += wp[q].sum0;
+        t.sum1 += wp[q].sum1;
+        t.n_good += wp[q].n_good;
+    }
+    gi->bmin0 = t.bmin0;
+    gi->bmin1 = t.bmin1;
+    gi->bmax0 = t.bmax0;
+    gi->bmax1 = t.bmax1;
+    gi->sum0 = t.sum0;
+    gi->sum1 = t.sum1;
+    gi->n_good = t.n_good;
+    if (t.n_good == 0) {
         gi->g0 = 0;
         gi->g1 = 0;
         return;
     }
-    const long long e0 = (long long)gi->bmax0 - gi->bmin0 + 3;
-    const long long e1 = (long long)gi->bmax1 - gi->bmin1 + 3;
-    gi->g0 = e0 <= GH ? gi->bmin0 - 1 : (int)(gi->sum0 / gi->n_good) - GH / 2;
-    gi->g1 = e1 <= GW ? gi->bmin1 - 1 : (int)(gi->sum1 / gi->n_good) - GW / 2;
+    const long long e0 = (long long)t.bmax0 - t.bmin0 + 3;
+    const long long e1 = (long long)t.bmax1 - t.bmin1 + 3;
+    gi->g0 = e0 <= GH ? t.bmin0 - 1 : (int)(t.sum0 / t.n_good) - GH / 2;
+    gi->g1 = e1 <= GW ? t.bmin1 - 1 : (int)(t.sum1 / t.n_good) - GW / 2;
 }
 
 __global__ void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask, int HW, int o0,
@@ -362,10 +395,12 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     unsigned* vals = (unsigned*)(ws + L.vals);
     unsigned* vals2 = (unsigned*)(ws + L.vals2);
     unsigned* cstart = (unsigned*)(ws + L.cstart);
-    hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, gi);
-    hipLaunchKernelGGL(k_grid_bbox, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW,
-                       g.o0, g.o1, gi);
-    hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(64), 0, s, gi, GH, GW);
+    const unsigned nparts = grid_blocks(HW, GRID_THREADS);
+    GridPart* gpart = (GridPart*)(ws + L.gpart);
+    hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, HW, g.o0,
+                       g.o1, gpart);
+    hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(GRID_THREADS), 0, s, gpart, (int)nparts, gi, GH,
+                       GW);
     hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
                        g.o1, gi, GH, GW, keys, vals);
     const unsigned ncells = (unsigned)GH * (unsigned)GW;

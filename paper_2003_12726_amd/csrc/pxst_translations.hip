@@ -6,8 +6,8 @@
 // each it loads the (2Tx+2) x (2Ty+2) reference neighbourhood of u - dx_n - origin
 // once and forms all shifted lookups from it (the bilinear fractions do not depend on
 // the integer shift).  Per-shift sums are reduced over the work-group and written as
-// per-block partials.  Pass 2 (one thread per frame) adds the partials in block order
-// with compensated float32 sums, normalises, takes the first minimum and refines.
+// per-block partials.  Pass 2 (one wave per frame) adds the partials with compensated
+// float32 sums in a fixed order, normalises, takes the first minimum and refines.
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
 
@@ -131,26 +131,34 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
     }
 }
 
+// One wave per frame: lanes add the block partials of each shift (compensated, blocks
+// in lane-strided order), a fixed butterfly combines the lanes, lane 0 decides.
 template <int TX, int TY>
-__global__ void k_tr_final(TrArgs a) {
+__global__ __launch_bounds__(64) void k_tr_final(TrArgs a) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= a.N) return;
-    float E[CT];
-    float be = INFINITY;
-    int bk = -1;
+    __shared__ float Es[CT];
+    const int n = blockIdx.x;
+    const int lane = threadIdx.x;
     for (int s = 0; s < CT; ++s) {
-        float eS = 0.f, eC = 0.f, vS = 0.f, vC = 0.f;
-        long long c = 0;
-        for (int b = 0; b < a.nblk; ++b) {
+        float eS = 0.f, eC = 0.f, vS = 0.f, vC = 0.f, c = 0.f;
+        for (int b = lane; b < a.nblk; b += 64) {
             const float* p = a.part + ((size_t)n * a.nblk + b) * (CT * 3) + 3 * s;
             kahan_add(eS, eC, p[0]);
             kahan_add(vS, vC, p[1]);
-            c += (long long)p[2];
+            c += p[2];
         }
-        E[s] = normalised_error(eS, vS, c > 0 ? 1 : 0);
-        if (E[s] < be) {
-            be = E[s];
+        const float e = wave_sum<float>(eS);
+        const float v = wave_sum<float>(vS);
+        const float cnt = wave_sum<float>(c);
+        if (lane == 0) Es[s] = normalised_error(e, v, cnt > 0.f ? 1 : 0);
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    float be = INFINITY;
+    int bk = -1;
+    for (int s = 0; s < CT; ++s) {
+        if (Es[s] < be) {
+            be = Es[s];
             bk = s;
         }
     }
@@ -168,7 +176,7 @@ __global__ void k_tr_final(TrArgs a) {
         float st[9];
         for (int q = 0; q < 9; ++q) {
             const int kx = bx + q / 3 - 1, ky = by + q % 3 - 1;
-            st[q] = (kx >= 0 && kx < NXs && ky >= 0 && ky < NYs) ? E[kx * NYs + ky] : INFINITY;
+            st[q] = (kx >= 0 && kx < NXs && ky >= 0 && ky < NYs) ? Es[kx * NYs + ky] : INFINITY;
         }
         refine_at(st, bx, by, NXs, NYs, ox, oy);
     }
@@ -235,7 +243,7 @@ int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, c
     hipLaunchKernelGGL(kp, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
     profile_end("tr_partial", s,
                 (long long)g.HW() * g.N * (2 * win.r_ss + 1) * (2 * win.r_fs + 1), nullptr, 0);
-    hipLaunchKernelGGL(kf, dim3((g.N + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(kf, dim3(g.N), dim3(64), 0, s, a);
     return check_hip(hipGetLastError(), "translation search");
 }
 
