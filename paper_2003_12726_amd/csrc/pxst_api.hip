@@ -127,6 +127,18 @@ Layout make_layout(const Geom& g, int tr_ct) {
     L.cstart = take((ncells + 3) * 4);
     L.pdata = take(HW * 16);
     L.bsort = take(HW * 8);
+    L.fsort = take((size_t)g.N * HW * sizeof(uint16_t));
+    {
+        // frame chunks of the reference gather: enough (pixel, chunk) work items to fill
+        // the device, bounded by the partial-result buffer
+        const size_t RRs = RR > 0 ? RR : 1;
+        size_t chunks = (size_t)(4u << 20) / RRs;
+        if (chunks > REF_PART_MAX / RRs) chunks = REF_PART_MAX / RRs;
+        if (chunks > (size_t)g.N) chunks = (size_t)g.N;
+        if (chunks < 1) chunks = 1;
+        L.ref_chunks = (int)chunks;
+        L.rpart = take(chunks > 1 ? chunks * RRs * sizeof(RefPart) : 1);
+    }
     L.sort_tmp_bytes = sort_temp_bound(HW);
     L.sort_tmp = take(L.sort_tmp_bytes);
     const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);

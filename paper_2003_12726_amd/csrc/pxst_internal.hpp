@@ -52,13 +52,21 @@ struct GridPart {
     long long sum0, sum1;
 };
 constexpr int GRID_THREADS = 256;
+// Reference gather: partial results of at most this many (pixel, frame-chunk) pairs.
+constexpr size_t REF_PART_MAX = (size_t)8 << 20;
+
+struct RefPart {
+    float s, c;     // compensated float32 numerator of the chunk
+    double den;     // float64 weight sum of the chunk
+};
 
 // Workspace layout: every section at a 256-byte aligned offset.
 struct Layout {
     // common
     size_t refv, sat, sat_tmp, s2;
     // reference update
-    size_t ginfo, gpart, keys, keys2, vals, vals2, cstart, pdata, bsort, sort_tmp;
+    size_t ginfo, gpart, keys, keys2, vals, vals2, cstart, pdata, bsort, fsort, rpart, sort_tmp;
+    int ref_chunks;   // frame chunks of the reference gather
     size_t sort_tmp_bytes;
     // pixel map
     size_t tiles, lists, counters;

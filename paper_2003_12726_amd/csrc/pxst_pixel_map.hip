@@ -180,6 +180,33 @@ __device__ inline void finish_pixel(const PmArgs& a, float* smem, const float (&
     __syncthreads();
 }
 
+// Squared residuals of KR window rows of CW candidates for one frame, accumulated into
+// acc.  Rows are software-pipelined through two register buffers chosen by the row's
+// parity at compile time: the LDS reads of row r + 1 are issued before the FMAs of
+// row r, and a scheduling barrier per row keeps at most two rows of loads live.
+template <int KR, int CW>
+__device__ inline void eval_rows(const float* G, const int (&rowoff)[KR], float nW, float I,
+                                 float (&acc)[KR][CW]) {
+    float b0[CW], b1[CW];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) b0[m] = G[rowoff[0] + m];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        float(&cur)[CW] = (r & 1) ? b1 : b0;
+        float(&nxt)[CW] = (r & 1) ? b0 : b1;
+        if (r + 1 < KR) {
+#pragma unroll
+            for (int m = 0; m < CW; ++m) nxt[m] = G[rowoff[r + 1] + m];
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+            const float rr = fmaf(nW, cur[m], I);
+            acc[r][m] = fmaf(rr, rr, acc[r][m]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // --------------------------------------------------------------- LDS-staged search
 //
 // FAST kernel: every staged value of every frame is a valid lookup.  Thread layout:
@@ -220,6 +247,7 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
 
     // staged elements of this thread: LDS offset (a dump slot past both buffers when
     // the element does not exist) and reference offset relative to the frame shift
+    const int nst = (nel + nthr - 1) / nthr;   // <= PFS (checked by the classification)
     int st_lds[PFS], st_glb[PFS];
 #pragma unroll
     for (int s = 0; s < PFS; ++s) {
@@ -262,8 +290,10 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
             const int goff = s0.e * Rf + s1.e;
 #pragma unroll
             for (int s = 0; s < PFS; ++s) {
-                const float* p = refv + (st_glb[s] - goff);
-                smem[st_lds[s]] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
+                if (s < nst) {
+                    const float* p = refv + (st_glb[s] - goff);
+                    smem[st_lds[s]] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
+                }
             }
             __syncthreads();
         }
@@ -281,41 +311,25 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
             float pv[PFS][4];
 #pragma unroll
             for (int s = 0; s < PFS; ++s) {
-                const float* p = refv + (st_glb[s] - goff);
-                pv[s][0] = p[0];
-                pv[s][1] = p[1];
-                pv[s][2] = p[Rf];
-                pv[s][3] = p[Rf + 1];
+                if (s < nst) {
+                    const float* p = refv + (st_glb[s] - goff);
+                    pv[s][0] = p[0];
+                    pv[s][1] = p[1];
+                    pv[s][2] = p[Rf];
+                    pv[s][3] = p[Rf + 1];
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
 
-            float cur[CW], nxt[CW];
-#pragma unroll
-            for (int m = 0; m < CW; ++m) cur[m] = G[rowoff[0] + m];
-#pragma unroll
-            for (int r = 0; r < KR; ++r) {
-                if (r + 1 < KR) {
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) nxt[m] = G[rowoff[r + 1] + m];
-                }
-#pragma unroll
-                for (int m = 0; m < CW; ++m) {
-                    const float rr = fmaf(nW, cur[m], I);
-                    eP[r][m] = fmaf(rr, rr, eP[r][m]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                if (r + 1 < KR) {
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) cur[m] = nxt[m];
-                }
-            }
+            eval_rows<KR, CW>(G, rowoff, nW, I, eP);
             const float v = I - Wp;
             vP = fmaf(v, v, vP);
             __builtin_amdgcn_sched_barrier(0);
 
 #pragma unroll
             for (int s = 0; s < PFS; ++s)
-                Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t, s1n.t);
+                if (s < nst)
+                    Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t, s1n.t);
             I = Inext;
             __syncthreads();
 
@@ -438,26 +452,7 @@ __global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
             const float Inext = (float)fp[(size_t)n1 * HW];
             const float v = I - Wp;
             if (!slow_cur) {
-                float cur[CW], nxt[CW];
-#pragma unroll
-                for (int m = 0; m < CW; ++m) cur[m] = G[rowoff[0] + m];
-#pragma unroll
-                for (int r = 0; r < KR; ++r) {
-                    if (r + 1 < KR) {
-#pragma unroll
-                        for (int m = 0; m < CW; ++m) nxt[m] = G[rowoff[r + 1] + m];
-                    }
-#pragma unroll
-                    for (int m = 0; m < CW; ++m) {
-                        const float rr = fmaf(nW, cur[m], I);
-                        eP[r][m] = fmaf(rr, rr, eP[r][m]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (r + 1 < KR) {
-#pragma unroll
-                        for (int m = 0; m < CW; ++m) cur[m] = nxt[m];
-                    }
-                }
+                eval_rows<KR, CW>(G, rowoff, nW, I, eP);
                 vP = fmaf(v, v, vP);
                 ++nfast;
             } else {

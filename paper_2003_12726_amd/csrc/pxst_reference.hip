@@ -4,9 +4,12 @@
 // scattering with atomics, the pixels are binned by floor(u) - origin into a cell
 // grid (a stable radix sort of cell keys gives each cell its pixels in index order),
 // and every reference pixel p then gathers, frame by frame, from the 3x3 cells around
-// p + floor(dx_n): only those can put a bilinear corner on p.  The per-frame partial
-// is added with compensated float32 summation; the weight sum is float64.  The order
-// of every sum is fixed, so the result is bitwise reproducible.
+// p + floor(dx_n): only those can put a bilinear corner on p.  The frames are copied
+// into sorted-entry order first, so an entry's frame value is read at the entry's own
+// index.  The frames are split into chunks (grid z) to keep enough gathers in flight;
+// per-frame partials are added with compensated float32 summation and float64 weight
+// sums, and the chunks are combined in chunk order, so every sum has a fixed order and
+// the result is bitwise reproducible.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "pxst_device.hpp"
@@ -177,8 +180,9 @@ __device__ inline float splat_weight(int p, int base, float t) {
 
 struct GatherArgs {
     const uint16_t* frames;
+    const uint16_t* fsort;    // frames permuted into sorted-entry order: [N][HW]
     const float* dx;
-    const float* u;           // for entries outside the grid
+    const float* u;           // error mode: map for the lookups of eps
     const float* refv_in;     // error mode: reference for the lookups
     const float* s2;          // error mode: sigma^2
     const unsigned* cstart;
@@ -186,118 +190,138 @@ struct GatherArgs {
     const int2* bsort;
     const GridInfo* gi;
     int N, H, W, Rs, Rf, o0, o1, GH, GW;
+    int nchunks;              // frame chunks (grid z); partials go to part when > 1
+    RefPart* part;            // [nchunks][Rs * Rf]
     float* out;               // ref (or ref_err)
     double* wsum;             // weight sums (reference mode)
     float* refv_out;          // reference mode: ref with NaN for invalid (may be null)
 };
 
+// fsort[n][e] = frames[n][vals[e]]: a frame value of a sorted entry is then read at the
+// entry's own index, not through its pixel index.
+__global__ void k_sort_frames(const uint16_t* __restrict__ frames, const unsigned* __restrict__ vals,
+                              int HW, uint16_t* __restrict__ fsort) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n = blockIdx.y;
+    if (e < HW) fsort[n * HW + e] = frames[n * HW + vals[e]];
+}
+
+// Contribution of sorted entry e in frame n to reference pixel (p0, p1): value and weight.
+template <int MODE>
+__device__ inline void gather_entry(const GatherArgs& a, unsigned e, int n, size_t HW, int p0, int p1,
+                                    int s0, int s1, float fd0, float fd1, float& part, double& dpart) {
+    const float4 pd = a.pdata[e];
+    const int2 b = a.bsort[e];
+    const float w0 = splat_weight(p0, b.x - s0, pd.x - fd0);
+    const float w1 = splat_weight(p1, b.y - s1, pd.y - fd1);
+    const float w = w0 * w1;
+    if (w == 0.f) return;
+    const float I = (float)a.fsort[(size_t)n * HW + e];
+    if (MODE == 0) {
+        const float wi = w * pd.z;
+        part = fmaf(wi, I, part);
+        dpart += (double)wi * (double)pd.z;
+    } else {
+        const unsigned k = __float_as_uint(pd.w);
+        const float u0 = a.u[k], u1 = a.u[HW + k];
+        const float f0 = floorf(u0), f1 = floorf(u1);
+        const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
+        const int a0 = (int)f0 - s0 - a.o0 - (t0 < 0.f ? 1 : 0);
+        const int b0 = (int)f1 - s1 - a.o1 - (t1 < 0.f ? 1 : 0);
+        const float g = masked_bilinear(a.refv_in, a.Rs, a.Rf, a0, b0, t0 < 0.f ? t0 + 1.f : t0,
+                                        t1 < 0.f ? t1 + 1.f : t1);
+        const float s2 = a.s2[k];
+        float eps = 0.f;
+        if (valid(g) && s2 > 0.f) {
+            const float rr = fmaf(-pd.z, g, I);
+            eps = rr * rr / s2;
+        }
+        part = fmaf(w, eps, part);
+        dpart += (double)w;
+    }
+}
+
+__device__ inline void write_reference(const GatherArgs& a, size_t p, float S, float C, double den,
+                                       int mode) {
+    const float num = S - C;
+    const float val = den > 0.0 ? (float)((double)num / den) : 0.f;
+    a.out[p] = val;
+    if (mode == 0) {
+        a.wsum[p] = den;
+        if (a.refv_out) a.refv_out[p] = den > 0.0 ? val : qnan();
+    }
+}
+
 // MODE 0: reference update (value M W I, weight M W^2).
 // MODE 1: reference-plane error (value M eps, weight M).
+// Grid: 16 x 16 reference pixels per work-group, frame chunk in z.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_ref_gather(GatherArgs a) {
     const int p1 = blockIdx.x * 16 + (threadIdx.x & 15);
     const int p0 = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const bool inside = p0 < a.Rs && p1 < a.Rf;
+    if (p0 >= a.Rs || p1 >= a.Rf) return;
     const GridInfo gi = *a.gi;
     const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
     const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
     const size_t HW = (size_t)a.H * a.W;
+    const int F = (a.N + a.nchunks - 1) / a.nchunks;
+    const int n_begin = blockIdx.z * F, n_end = min(a.N, n_begin + F);
     float S = 0.f, C = 0.f;      // compensated numerator over frames
     double den = 0.0;
-    if (inside) {
-        for (int n = 0; n < a.N; ++n) {
-            const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
-            const float s0 = floorf(d0), s1 = floorf(d1);
-            const float fd0 = d0 - s0, fd1 = d1 - s1;
-            const int q0 = p0 + (int)s0, q1 = p1 + (int)s1;   // cell of a point landing on p
-            if (q0 < gi.bmin0 - 1 || q0 > gi.bmax0 + 1 || q1 < gi.bmin1 - 1 || q1 > gi.bmax1 + 1)
-                continue;
-            const uint16_t* fr = a.frames + (size_t)n * HW;
-            float part = 0.f;
-            double dpart = 0.0;
-            for (int d = -1; d <= 1; ++d) {
-                const int r = q0 + d - gi.g0;
-                if (r < 0 || r >= a.GH) continue;
-                const int c_lo = max(q1 - 1 - gi.g1, 0), c_hi = min(q1 + 1 - gi.g1, a.GW - 1);
-                if (c_lo > c_hi) continue;
-                const unsigned e_begin = a.cstart[(unsigned)r * a.GW + c_lo];
-                const unsigned e_end = a.cstart[(unsigned)r * a.GW + c_hi + 1];
-                for (unsigned e = e_begin; e < e_end; ++e) {
-                    const float4 pd = a.pdata[e];
-                    const int2 b = a.bsort[e];
-                    const float w0 = splat_weight(p0, b.x - (int)s0, pd.x - fd0);
-                    const float w1 = splat_weight(p1, b.y - (int)s1, pd.y - fd1);
-                    const float w = w0 * w1;
-                    if (w == 0.f) continue;
-                    const unsigned k = __float_as_uint(pd.w);
-                    if (MODE == 0) {
-                        const float wi = w * pd.z;
-                        part = fmaf(wi, (float)fr[k], part);
-                        dpart += (double)wi * (double)pd.z;
-                    } else {
-                        // eps of pixel k in frame n
-                        const float u0 = a.u[k], u1 = a.u[HW + k];
-                        const float f0 = floorf(u0), f1 = floorf(u1);
-                        const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
-                        const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
-                        const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
-                        const float g = masked_bilinear(a.refv_in, a.Rs, a.Rf, a0, b0,
-                                                        t0 < 0.f ? t0 + 1.f : t0,
-                                                        t1 < 0.f ? t1 + 1.f : t1);
-                        const float s2 = a.s2[k];
-                        float eps = 0.f;
-                        if (valid(g) && s2 > 0.f) {
-                            const float rr = fmaf(-pd.z, g, (float)fr[k]);
-                            eps = rr * rr / s2;
-                        }
-                        part = fmaf(w, eps, part);
-                        dpart += (double)w;
-                    }
-                }
+    for (int n = n_begin; n < n_end; ++n) {
+        const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+        const float fs0 = floorf(d0), fs1 = floorf(d1);
+        const float fd0 = d0 - fs0, fd1 = d1 - fs1;
+        const int s0 = (int)fs0, s1 = (int)fs1;
+        const int q0 = p0 + s0, q1 = p1 + s1;   // cell of a point landing on p
+        if (q0 < gi.bmin0 - 1 || q0 > gi.bmax0 + 1 || q1 < gi.bmin1 - 1 || q1 > gi.bmax1 + 1)
+            continue;
+        float part = 0.f;
+        double dpart = 0.0;
+        // the three cell rows around q0; in each, the cells q1-1 .. q1+1 are contiguous
+        unsigned eb[3], ee[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int r = q0 + d - 1 - gi.g0;
+            const int c_lo = max(q1 - 1 - gi.g1, 0), c_hi = min(q1 + 1 - gi.g1, a.GW - 1);
+            eb[d] = ee[d] = 0;
+            if (r >= 0 && r < a.GH && c_lo <= c_hi) {
+                eb[d] = a.cstart[(unsigned)r * a.GW + c_lo];
+                ee[d] = a.cstart[(unsigned)r * a.GW + c_hi + 1];
             }
-            // good pixels outside the cell grid (none for a sensible map)
-            for (unsigned e = ov_begin; e < ov_end; ++e) {
-                const float4 pd = a.pdata[e];
-                const int2 b = a.bsort[e];
-                const float w0 = splat_weight(p0, b.x - (int)s0, pd.x - fd0);
-                const float w1 = splat_weight(p1, b.y - (int)s1, pd.y - fd1);
-                const float w = w0 * w1;
-                if (w == 0.f) continue;
-                const unsigned k = __float_as_uint(pd.w);
-                if (MODE == 0) {
-                    const float wi = w * pd.z;
-                    part = fmaf(wi, (float)fr[k], part);
-                    dpart += (double)wi * (double)pd.z;
-                } else {
-                    const float u0 = a.u[k], u1 = a.u[HW + k];
-                    const float f0 = floorf(u0), f1 = floorf(u1);
-                    const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
-                    const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
-                    const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
-                    const float g = masked_bilinear(a.refv_in, a.Rs, a.Rf, a0, b0,
-                                                    t0 < 0.f ? t0 + 1.f : t0,
-                                                    t1 < 0.f ? t1 + 1.f : t1);
-                    const float s2 = a.s2[k];
-                    float eps = 0.f;
-                    if (valid(g) && s2 > 0.f) {
-                        const float rr = fmaf(-pd.z, g, (float)fr[k]);
-                        eps = rr * rr / s2;
-                    }
-                    part = fmaf(w, eps, part);
-                    dpart += (double)w;
-                }
-            }
-            kahan_add(S, C, part);
-            den += dpart;
         }
-        const size_t p = (size_t)p0 * a.Rf + p1;
-        const float val = den > 0.0 ? (float)((double)S / den) : 0.f;
-        a.out[p] = val;
-        if (MODE == 0) {
-            a.wsum[p] = den;
-            if (a.refv_out) a.refv_out[p] = den > 0.0 ? val : qnan();
-        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            for (unsigned e = eb[d]; e < ee[d]; ++e)
+                gather_entry<MODE>(a, e, n, HW, p0, p1, s0, s1, fd0, fd1, part, dpart);
+        // good pixels outside the cell grid (none for a sensible map)
+        for (unsigned e = ov_begin; e < ov_end; ++e)
+            gather_entry<MODE>(a, e, n, HW, p0, p1, s0, s1, fd0, fd1, part, dpart);
+        kahan_add(S, C, part);
+        den += dpart;
     }
+    const size_t p = (size_t)p0 * a.Rf + p1;
+    if (a.nchunks == 1) {
+        write_reference(a, p, S, C, den, MODE);
+    } else {
+        a.part[(size_t)blockIdx.z * ((size_t)a.Rs * a.Rf) + p] = RefPart{S, C, den};
+    }
+}
+
+// Adds the frame-chunk partials of every reference pixel in chunk order.
+__global__ void k_ref_combine(GatherArgs a, int mode) {
+    const size_t RR = (size_t)a.Rs * a.Rf;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= RR) return;
+    float S = 0.f, C = 0.f;
+    double den = 0.0;
+    for (int c = 0; c < a.nchunks; ++c) {
+        const RefPart q = a.part[(size_t)c * RR + p];
+        kahan_add(S, C, q.s);
+        kahan_add(S, C, -q.c);
+        den += q.den;
+    }
+    write_reference(a, p, S, C, den, mode);
 }
 
 __global__ void k_prep_refv(const float* __restrict__ ref, const double* __restrict__ wsum, int n,
@@ -421,16 +445,16 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
                        keys2, HW, ncells + 2, cstart);
     hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals2,
                        HW, HW, g.o0, g.o1, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
+    hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), g.N), dim3(256), 0, s, sc.frames,
+                       vals2, HW, (uint16_t*)(ws + L.fsort));
     return check_hip(hipGetLastError(), "inverse map");
 }
 
-int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
-                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s) {
-    int rc = build_inverse_map(g, sc, u, ws, L, s);
-    if (rc) return rc;
+static GatherArgs gather_args(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                              char* ws, const Layout& L) {
     GatherArgs a{};
     a.frames = sc.frames;
+    a.fsort = (const uint16_t*)(ws + L.fsort);
     a.dx = dx;
     a.u = u;
     a.cstart = (const unsigned*)(ws + L.cstart);
@@ -446,12 +470,32 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     a.o1 = g.o1;
     a.GH = grid_h(g);
     a.GW = grid_w(g);
+    a.nchunks = L.ref_chunks;
+    a.part = (RefPart*)(ws + L.rpart);
+    return a;
+}
+
+static void launch_gather(const GatherArgs& a, int mode, const Geom& g, hipStream_t s) {
+    dim3 grid((g.Rf + 15) / 16, (g.Rs + 15) / 16, a.nchunks);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_ref_gather<0>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_ref_gather<1>, grid, dim3(256), 0, s, a);
+    if (a.nchunks > 1)
+        hipLaunchKernelGGL(k_ref_combine, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, a, mode);
+}
+
+int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
+                            hipStream_t s) {
+    int rc = build_inverse_map(g, sc, u, ws, L, s);
+    if (rc) return rc;
+    GatherArgs a = gather_args(g, sc, u, dx, ws, L);
     a.out = ref;
     a.wsum = wsum;
     a.refv_out = refv;
-    dim3 grid((g.Rf + 15) / 16, (g.Rs + 15) / 16);
     profile_begin("ref_gather", s);
-    hipLaunchKernelGGL(k_ref_gather<0>, grid, dim3(256), 0, s, a);
+    launch_gather(a, 0, g, s);
     profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
     return check_hip(hipGetLastError(), "reference gather");
 }
@@ -461,28 +505,11 @@ int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, c
                            hipStream_t s) {
     int rc = build_inverse_map(g, sc, u, ws, L, s);
     if (rc) return rc;
-    GatherArgs a{};
-    a.frames = sc.frames;
-    a.dx = dx;
-    a.u = u;
+    GatherArgs a = gather_args(g, sc, u, dx, ws, L);
     a.refv_in = refv;
     a.s2 = (const float*)(ws + L.s2);
-    a.cstart = (const unsigned*)(ws + L.cstart);
-    a.pdata = (const float4*)(ws + L.pdata);
-    a.bsort = (const int2*)(ws + L.bsort);
-    a.gi = (const GridInfo*)(ws + L.ginfo);
-    a.N = g.N;
-    a.H = g.H;
-    a.W = g.W;
-    a.Rs = g.Rs;
-    a.Rf = g.Rf;
-    a.o0 = g.o0;
-    a.o1 = g.o1;
-    a.GH = grid_h(g);
-    a.GW = grid_w(g);
     a.out = ref_err;
-    dim3 grid((g.Rf + 15) / 16, (g.Rs + 15) / 16);
-    hipLaunchKernelGGL(k_ref_gather<1>, grid, dim3(256), 0, s, a);
+    launch_gather(a, 1, g, s);
     return check_hip(hipGetLastError(), "reference-plane error");
 }
 
