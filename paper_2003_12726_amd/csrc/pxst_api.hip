@@ -101,6 +101,31 @@ void profile_end(const char* family, hipStream_t s, long long work, const int* d
     f.open = nullptr;
 }
 
+// -------------------------------------------------------------------- batch staging
+namespace {
+std::mutex g_batch_mu;
+char* g_batch_host = nullptr;      // pinned staging buffer of argument tables
+size_t g_batch_cap = 0;
+hipEvent_t g_batch_done = nullptr; // recorded after the last batch's table copies
+}  // namespace
+
+static size_t align256(size_t x);
+
+BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const std::vector<int>& off) {
+    const size_t a_bytes = align256(bytes), o_bytes = align256(off.size() * sizeof(int));
+    if (ar.overflow || ar.used + a_bytes + o_bytes > ar.cap) {
+        ar.overflow = true;
+        return BatchUpload{};
+    }
+    char* h = ar.host + ar.used;
+    char* d = ar.dev + ar.used;
+    std::memcpy(h, args, bytes);
+    std::memcpy(h + a_bytes, off.data(), off.size() * sizeof(int));
+    hipMemcpyAsync(d, h, a_bytes + o_bytes, hipMemcpyHostToDevice, ar.stream);
+    ar.used += a_bytes + o_bytes;
+    return BatchUpload{d, (const int*)(d + a_bytes)};
+}
+
 // --------------------------------------------------------------------------- layout
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -431,13 +456,12 @@ size_t pxst_batch_workspace_bytes(int32_t n_jobs) {
         set_error("n_jobs must be >= 0");
         return 0;
     }
-    return 256;
+    // argument tables: one classification table plus three per window group
+    return (size_t)(n_jobs + 1) * 4 * (align256(sizeof(PmJobDesc) * 4) + 1024) + 65536;
 }
 
 int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, size_t batch_ws_bytes,
                        hipStream_t stream) {
-    (void)batch_ws;
-    (void)batch_ws_bytes;
     if (n_jobs < 0 || (n_jobs > 0 && !jobs)) {
         set_error("bad job list");
         return PXST_EINVAL;
@@ -451,38 +475,105 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
             set_error("job %d: iter %d outside 0..n_iter", j, J.iter);
             return PXST_EINVAL;
         }
+        if ((rc = check_window(J.opts.pm, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
+        if (J.opts.update_dx && (rc = check_window(J.opts.tr, PXST_MAX_TR_RADIUS, "translation")))
+            return rc;
+        if ((rc = check_ptr(J.u, 4, "u")) || (rc = check_ptr(J.dx, 4, "dx")) ||
+            (rc = check_ptr(J.ref, 4, "ref")) || (rc = check_ptr(J.wsum, 8, "wsum")) ||
+            (rc = check_ptr(J.err_hist, 8, "err_hist", false)))
+            return rc;
         const Layout L = make_layout(geom_of(J.scan.geom), tr_ct_of(&J.opts));
         if ((rc = check_ws(J.ws, J.ws_bytes, L.total))) return rc;
     }
-    for (int j = 0; j < n_jobs; ++j) {
-        const pxst_job& J = jobs[j];
-        const Geom g = geom_of(J.scan.geom);
-        const Layout L = make_layout(g, tr_ct_of(&J.opts));
-        char* w = (char*)J.ws;
-        float* refv = (float*)(w + L.refv);
+    if (n_jobs == 0) return PXST_OK;
+    {
+        const size_t need = pxst_batch_workspace_bytes(n_jobs);
         int rc;
-        if (J.iter == J.opts.n_iter) {
-            rc = launch_update_reference(g, J.scan, J.u, J.dx, J.ref, J.wsum, refv, w, L, stream);
-        } else {
-            if (J.iter == 0 && (rc = launch_sigma2(g, J.scan, (float*)(w + L.s2), stream))) return rc;
-            rc = launch_update_reference(g, J.scan, J.u, J.dx, J.ref, J.wsum, refv, w, L, stream);
-            if (!rc)
-                rc = launch_prep_reference(g, nullptr, nullptr, refv, (int*)(w + L.sat),
-                                           (int*)(w + L.sat_tmp), stream);
-            if (!rc)
-                rc = launch_pixel_map(g, J.scan, refv, (int*)(w + L.sat), J.dx, J.u, J.opts.pm, J.u,
-                                      nullptr, nullptr, w, L, stream);
-            if (!rc && J.opts.update_dx)
-                rc = launch_translations(g, J.scan, refv, J.u, J.dx, J.opts.tr, J.dx, nullptr,
-                                         nullptr, w, L, stream);
-            if (!rc)
-                rc = launch_error(g, J.scan, refv, (float*)(w + L.s2), J.u, J.dx, nullptr, nullptr,
-                                  J.err_hist ? J.err_hist + J.iter : (double*)(w + L.err_pix) + g.N,
-                                  w, L, stream);
-        }
-        if (rc) return rc;
+        if ((rc = check_ws(batch_ws, batch_ws_bytes, need))) return rc;
     }
-    return PXST_OK;
+
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (g_batch_done) hipEventSynchronize(g_batch_done);   // previous tables copied
+    if (g_batch_cap < batch_ws_bytes) {
+        if (g_batch_host) hipHostFree(g_batch_host);
+        g_batch_host = nullptr;
+        g_batch_cap = 0;
+        if (hipHostMalloc((void**)&g_batch_host, batch_ws_bytes, hipHostMallocDefault) != hipSuccess) {
+            g_batch_host = nullptr;
+            set_error("cannot allocate %zu bytes of pinned staging memory", batch_ws_bytes);
+            return PXST_EHIP;
+        }
+        g_batch_cap = batch_ws_bytes;
+    }
+    if (!g_batch_done && hipEventCreateWithFlags(&g_batch_done, hipEventDisableTiming) != hipSuccess) {
+        set_error("cannot create an event");
+        return PXST_EHIP;
+    }
+    BatchArena ar;
+    ar.host = g_batch_host;
+    ar.dev = (char*)batch_ws;
+    ar.cap = batch_ws_bytes;
+    ar.stream = stream;
+
+    struct JobState {
+        Geom g;
+        Layout L;
+        char* w;
+        float* refv;
+    };
+    std::vector<JobState> st(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        st[j].g = geom_of(jobs[j].scan.geom);
+        st[j].L = make_layout(st[j].g, tr_ct_of(&jobs[j].opts));
+        st[j].w = (char*)jobs[j].ws;
+        st[j].refv = (float*)(st[j].w + st[j].L.refv);
+    }
+    int rc = PXST_OK;
+    // (i) reference update of every job; variance once per job
+    for (int j = 0; j < n_jobs && !rc; ++j) {
+        const pxst_job& J = jobs[j];
+        if (J.iter == 0) rc = launch_sigma2(st[j].g, J.scan, (float*)(st[j].w + st[j].L.s2), stream);
+        if (!rc)
+            rc = launch_update_reference(st[j].g, J.scan, J.u, J.dx, J.ref, J.wsum, st[j].refv, st[j].w,
+                                         st[j].L, stream);
+        if (!rc && J.iter < J.opts.n_iter)
+            rc = launch_prep_reference(st[j].g, nullptr, nullptr, st[j].refv, (int*)(st[j].w + st[j].L.sat),
+                                       (int*)(st[j].w + st[j].L.sat_tmp), stream);
+    }
+    // (ii) pixel-map search of the jobs that iterate, batched over jobs
+    std::vector<PmJobDesc> pm;
+    for (int j = 0; j < n_jobs && !rc; ++j) {
+        const pxst_job& J = jobs[j];
+        if (J.iter >= J.opts.n_iter) continue;
+        PmJobDesc d;
+        d.g = st[j].g;
+        d.sc = J.scan;
+        d.refv = st[j].refv;
+        d.sat = (const int*)(st[j].w + st[j].L.sat);
+        d.dx = J.dx;
+        d.u_in = J.u;
+        d.u_out = J.u;
+        d.win = J.opts.pm;
+        d.ws = st[j].w;
+        d.L = &st[j].L;
+        pm.push_back(d);
+    }
+    if (!rc) rc = launch_pixel_map_batch(pm.data(), (int)pm.size(), ar, stream);
+    // (iii) translations and (iv) total error
+    for (int j = 0; j < n_jobs && !rc; ++j) {
+        const pxst_job& J = jobs[j];
+        if (J.iter >= J.opts.n_iter) continue;
+        if (J.opts.update_dx)
+            rc = launch_translations(st[j].g, J.scan, st[j].refv, J.u, J.dx, J.opts.tr, J.dx, nullptr,
+                                     nullptr, st[j].w, st[j].L, stream);
+        if (!rc)
+            rc = launch_error(st[j].g, J.scan, st[j].refv, (float*)(st[j].w + st[j].L.s2), J.u, J.dx,
+                              nullptr, nullptr,
+                              J.err_hist ? J.err_hist + J.iter : (double*)(st[j].w + st[j].L.err_pix) + st[j].g.N,
+                              st[j].w, st[j].L, stream);
+    }
+    hipEventRecord(g_batch_done, stream);
+    return rc;
 }
 
 }  // extern "C"

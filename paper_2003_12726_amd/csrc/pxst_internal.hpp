@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/pxst.h"
 
@@ -102,6 +103,40 @@ void profile_end(const char* family, hipStream_t s, long long work, const int* d
                  long long scale);
 bool profiling();
 
+// ------------------------------------------------------------------- batched launches
+// Argument tables of a batched launch live in the caller's batch workspace; they are
+// written into a pinned host buffer owned by the library and copied with
+// hipMemcpyAsync on the launch stream just before the launch that reads them.
+struct BatchArena {
+    char* host = nullptr;       // pinned staging memory
+    char* dev = nullptr;        // batch workspace
+    size_t cap = 0, used = 0;
+    hipStream_t stream = nullptr;
+    bool overflow = false;
+};
+struct BatchUpload {
+    const void* args_dev = nullptr;
+    const int* off_dev = nullptr;
+};
+// Copies `bytes` of arguments and the item offsets (njobs + 1 ints) into the arena.
+BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const std::vector<int>& off);
+// Persistent work-groups of a batched launch.
+constexpr int PERSISTENT_GROUPS = 256 * 4;
+
+// One job of a batched pixel-map search.
+struct PmJobDesc {
+    Geom g;
+    pxst_scan sc;
+    const float* refv;
+    const int* sat;
+    const float* dx;
+    const float* u_in;
+    float* u_out;
+    pxst_window win;
+    char* ws;
+    const Layout* L;
+};
+
 // ------------------------------------------------------------------------ kernel entry
 // Each returns PXST_OK or a negative code (and sets the message).
 
@@ -124,6 +159,8 @@ int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, c
 int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
                      const float* dx, const float* u_in, const pxst_window& win, float* u_out,
                      float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s);
+
+int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStream_t s);
 
 // Translation search.
 int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,

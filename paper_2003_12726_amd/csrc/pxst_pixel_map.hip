@@ -13,6 +13,8 @@
 //   EDGE    some lookups are invalid: per-candidate variance and frame counts;
 //   GENERIC the staged region does not fit the LDS budget (widely scattered map):
 //           no staging, lookups straight from the reference.
+#include <algorithm>
+
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
 
@@ -67,8 +69,7 @@ __device__ inline bool rect_valid(const int* sat, int Rs, int Rf, int r0, int r1
 }
 
 // One wave per tile: candidate-centre range, LDS fit and validity of every frame.
-__global__ __launch_bounds__(64) void k_classify(PmArgs a) {
-    const int tile = blockIdx.x;
+__device__ void classify_item(const PmArgs& a, int tile) {
     const int lane = threadIdx.x;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int i = ty * TILE + (lane >> 3), j = tx * TILE + (lane & 7);
@@ -219,10 +220,10 @@ __device__ inline void eval_rows(const float* G, const int (&rowoff)[KR], float 
 constexpr int PFS = 4;
 
 template <int CW, int KR>
-__global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
+__device__ void pm_fast_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
-    if ((int)blockIdx.x >= a.counters[CNT_FAST]) return;
-    const int tile = a.lists[CNT_FAST * a.ntiles + blockIdx.x];
+    if (slot >= a.counters[CNT_FAST]) return;
+    const int tile = a.lists[CNT_FAST * a.ntiles + slot];
     const TileDesc td = a.tiles[tile];
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int RH = td.rh, RW = td.rw, P = lds_pitch(RW);
@@ -374,10 +375,10 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
 // variance of slow frames starts at -0.0, so its sign bit records whether any slow
 // frame was valid (-0.0 + x is +0.0 or positive for every x >= +0.0).
 template <int CW, int KR>
-__global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
+__device__ void pm_edge_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
-    if ((int)blockIdx.x >= a.counters[CNT_EDGE]) return;
-    const int tile = a.lists[CNT_EDGE * a.ntiles + blockIdx.x];
+    if (slot >= a.counters[CNT_EDGE]) return;
+    const int tile = a.lists[CNT_EDGE * a.ntiles + slot];
     const TileDesc td = a.tiles[tile];
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int RH = td.rh, RW = td.rw, P = lds_pitch(RW);
@@ -544,11 +545,10 @@ __device__ inline float eval_candidate(const PmArgs& a, size_t pix, size_t HW, i
     return normalised_error(eS + eP, vS + vP, nv);
 }
 
-__global__ __launch_bounds__(256) void k_pm_generic(PmArgs a) {
+__device__ void pm_generic_item(const PmArgs& a, int slot) {
     __shared__ float redE[4][64];
     __shared__ int redK[4][64];
     __shared__ float sten[64][9];
-    const int slot = blockIdx.x;
     if (slot >= a.counters[CNT_GENERIC]) return;
     const int tile = a.lists[CNT_GENERIC * a.ntiles + slot];
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
@@ -616,20 +616,81 @@ __global__ __launch_bounds__(256) void k_pm_generic(PmArgs a) {
             if (a.arg_out) a.arg_out[pix] = kb;
         }
     }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------ wrappers
+// Single-job launches (one work-group per item) and persistent launches over the items
+// of several jobs (item i of the batch belongs to job j with off[j] <= i < off[j + 1];
+// each job's arguments come from a device table).  A job's items and their results do
+// not depend on the other jobs of the batch.
+__device__ inline int batch_job(const int* __restrict__ off, int njobs, int item) {
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+#define PXST_WRAP(NAME, BOUND, BODY)                                                          \
+    __global__ __launch_bounds__(BOUND) void NAME(const PmArgs a) { BODY(a, (int)blockIdx.x); } \
+    __global__ __launch_bounds__(BOUND) void NAME##_batch(const PmArgs* __restrict__ jobs,       \
+                                                          const int* __restrict__ off, int njobs) { \
+        const int total = off[njobs];                                                         \
+        for (int item = blockIdx.x; item < total; item += gridDim.x) {                        \
+            const int j = batch_job(off, njobs, item);                                        \
+            const PmArgs a = jobs[j];                                                         \
+            BODY(a, item - off[j]);                                                           \
+        }                                                                                     \
+    }
+
+PXST_WRAP(k_classify, 64, classify_item)
+PXST_WRAP(k_pm_generic, 256, pm_generic_item)
+
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
+    pm_fast_item<CW, KR>(a, (int)blockIdx.x);
+}
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_fast_batch(const PmArgs* __restrict__ jobs,
+                                                       const int* __restrict__ off, int njobs) {
+    const int total = off[njobs];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int j = batch_job(off, njobs, item);
+        const PmArgs a = jobs[j];
+        pm_fast_item<CW, KR>(a, item - off[j]);
+    }
+}
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
+    pm_edge_item<CW, KR>(a, (int)blockIdx.x);
+}
+template <int CW, int KR>
+__global__ __launch_bounds__(512) void k_pm_edge_batch(const PmArgs* __restrict__ jobs,
+                                                       const int* __restrict__ off, int njobs) {
+    const int total = off[njobs];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int j = batch_job(off, njobs, item);
+        const PmArgs a = jobs[j];
+        pm_edge_item<CW, KR>(a, item - off[j]);
+    }
 }
 
 // ------------------------------------------------------------------------ dispatch
 typedef void (*PmKernel)(PmArgs);
+typedef void (*PmBatchKernel)(const PmArgs*, const int*, int);
 
 struct LdsShape {
     PmKernel fn;
+    PmBatchKernel batch;
     int cw, kr;
 };
 
 template <int CW, int KR>
-constexpr LdsShape fast_shape() { return LdsShape{k_pm_fast<CW, KR>, CW, KR}; }
+constexpr LdsShape fast_shape() { return LdsShape{k_pm_fast<CW, KR>, k_pm_fast_batch<CW, KR>, CW, KR}; }
 template <int CW, int KR>
-constexpr LdsShape edge_shape() { return LdsShape{k_pm_edge<CW, KR>, CW, KR}; }
+constexpr LdsShape edge_shape() { return LdsShape{k_pm_edge<CW, KR>, k_pm_edge_batch<CW, KR>, CW, KR}; }
 
 // FAST: full window rows per thread (CW = 2 r_fs + 1), rows per thread chosen so that
 // two accumulators per candidate stay within about 100 registers.
@@ -698,11 +759,10 @@ size_t lds_bytes(const Launch& l) {
     return stage > red ? stage : red;
 }
 
-}  // namespace
 
-int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
-                     const float* dx, const float* u_in, const pxst_window& win, float* u_out,
-                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
+                    const float* dx, const float* u_in, const pxst_window& win, float* u_out,
+                    float* err_min, int32_t* argmin, char* ws, const Layout& L) {
     PmArgs a{};
     a.frames = sc.frames;
     a.white = sc.white;
@@ -732,15 +792,51 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     a.tiles_x = (g.W + TILE - 1) / TILE;
     const int tiles_y = (g.H + TILE - 1) / TILE;
     a.ntiles = a.tiles_x * tiles_y;
-
     const LdsShape fs = pick_fast(a.NY), es = pick_edge(a.NY);
     const Launch lf = plan_launch(a.NX, a.NY, fs.cw, fs.kr);
     const Launch le = plan_launch(a.NX, a.NY, es.cw, es.kr);
-    // staging capacity: elements per frame over all threads of the smaller launch
-    const int thr_f = lf.waves * 64, thr_e = le.waves * 64;
-    a.stage_cap = 8 * thr_e;
-    a.fast_cap = PFS * thr_f;
+    a.stage_cap = 8 * le.waves * 64;
+    a.fast_cap = PFS * lf.waves * 64;
+    return a;
+}
 
+// Launch shapes of the fast and edge kernels for a window (same for every job with
+// that window).
+struct PmPlan {
+    LdsShape fs, es;
+    Launch lf, le;
+    PmArgs fast_args(const PmArgs& a) const {
+        PmArgs b = a;
+        b.nchunks = lf.nchunks;
+        b.nblocks = lf.nblocks;
+        b.sub = lf.sub;
+        return b;
+    }
+    PmArgs edge_args(const PmArgs& a) const {
+        PmArgs b = a;
+        b.nchunks = le.nchunks;
+        b.nblocks = le.nblocks;
+        b.sub = le.sub;
+        return b;
+    }
+};
+
+PmPlan pm_plan(int NX, int NY) {
+    PmPlan p;
+    p.fs = pick_fast(NY);
+    p.es = pick_edge(NY);
+    p.lf = plan_launch(NX, NY, p.fs.cw, p.fs.kr);
+    p.le = plan_launch(NX, NY, p.es.cw, p.es.kr);
+    return p;
+}
+
+}  // namespace
+
+int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
+                     const float* dx, const float* u_in, const pxst_window& win, float* u_out,
+                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+    const PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L);
+    const PmPlan pl = pm_plan(a.NX, a.NY);
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a.counters);
     hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);
     int rc = check_hip(hipGetLastError(), "pixel-map classification");
@@ -748,27 +844,19 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
     {
-        PmArgs b = a;
-        b.nchunks = lf.nchunks;
-        b.nblocks = lf.nblocks;
-        b.sub = lf.sub;
-        const size_t sh = lds_bytes(lf);
-        hipFuncSetAttribute((const void*)fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        const size_t sh = lds_bytes(pl.lf);
+        hipFuncSetAttribute((const void*)pl.fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_fast", s);
-        hipLaunchKernelGGL(fs.fn, dim3(a.ntiles), dim3(lf.waves * 64), sh, s, b);
+        hipLaunchKernelGGL(pl.fs.fn, dim3(a.ntiles), dim3(pl.lf.waves * 64), sh, s, pl.fast_args(a));
         profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles)");
         if (rc) return rc;
     }
     {
-        PmArgs b = a;
-        b.nchunks = le.nchunks;
-        b.nblocks = le.nblocks;
-        b.sub = le.sub;
-        const size_t sh = lds_bytes(le);
-        hipFuncSetAttribute((const void*)es.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        const size_t sh = lds_bytes(pl.le);
+        hipFuncSetAttribute((const void*)pl.es.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_edge", s);
-        hipLaunchKernelGGL(es.fn, dim3(a.ntiles), dim3(le.waves * 64), sh, s, b);
+        hipLaunchKernelGGL(pl.es.fn, dim3(a.ntiles), dim3(pl.le.waves * 64), sh, s, pl.edge_args(a));
         profile_end("pm_edge", s, 0, a.counters + CNT_GOOD_EDGE, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (edge tiles)");
         if (rc) return rc;
@@ -777,6 +865,93 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     hipLaunchKernelGGL(k_pm_generic, dim3(a.ntiles), dim3(256), 0, s, a);
     profile_end("pm_generic", s, 0, a.counters + CNT_GOOD_GENERIC, evals_per_good_px);
     return check_hip(hipGetLastError(), "pixel-map search (scattered tiles)");
+}
+
+// Batched pixel-map search of several jobs.  Per job: counters reset; then one
+// persistent classification over every tile of every job; then, per group of jobs
+// sharing a window, one persistent launch of each kernel class.  `table` is device
+// memory with room for 3 * n PmArgs and the item offsets.
+int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStream_t s) {
+    if (n <= 0) return PXST_OK;
+    const int persistent_groups = PERSISTENT_GROUPS;
+    // argument table: [fast args n][edge args n][plain args n]; offsets per launch
+    std::vector<PmArgs> base(n);
+    for (int j = 0; j < n; ++j) {
+        const PmJobDesc& d = jobs[j];
+        base[j] = make_pm_args(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
+                               nullptr, d.ws, *d.L);
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, base[j].counters);
+    }
+    // classification of all jobs in one launch
+    {
+        std::vector<int> off(n + 1, 0);
+        for (int j = 0; j < n; ++j) off[j + 1] = off[j] + base[j].ntiles;
+        const BatchUpload up = stage_table(ar, base.data(), n * sizeof(PmArgs), off);
+        if (!ar.overflow)
+            hipLaunchKernelGGL(k_classify_batch, dim3(std::min(off[n], 256 * 16)), dim3(64), 0, s,
+                           (const PmArgs*)up.args_dev, up.off_dev, n);
+    }
+    if (ar.overflow) {
+        set_error("batch workspace too small");
+        return PXST_EWORKSPACE;
+    }
+    int rc = check_hip(hipGetLastError(), "batched pixel-map classification");
+    if (rc) return rc;
+    // groups of jobs with the same window
+    std::vector<int> done(n, 0);
+    for (int j0 = 0; j0 < n; ++j0) {
+        if (done[j0]) continue;
+        std::vector<int> grp;
+        for (int j = j0; j < n; ++j)
+            if (!done[j] && base[j].NX == base[j0].NX && base[j].NY == base[j0].NY) {
+                grp.push_back(j);
+                done[j] = 1;
+            }
+        const PmPlan pl = pm_plan(base[j0].NX, base[j0].NY);
+        const int m = (int)grp.size();
+        std::vector<PmArgs> fa(m), ea(m), ga(m);
+        std::vector<int> off(m + 1, 0);
+        for (int q = 0; q < m; ++q) {
+            fa[q] = pl.fast_args(base[grp[q]]);
+            ea[q] = pl.edge_args(base[grp[q]]);
+            ga[q] = base[grp[q]];
+            off[q + 1] = off[q] + base[grp[q]].ntiles;
+        }
+        const int grid = std::min(off[m], persistent_groups);
+        {
+            const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);
+            if (ar.overflow) break;
+            const size_t sh = lds_bytes(pl.lf);
+            hipFuncSetAttribute((const void*)pl.fs.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sh);
+            profile_begin("pm_fast", s);
+            hipLaunchKernelGGL(pl.fs.batch, dim3(grid), dim3(pl.lf.waves * 64), sh, s,
+                               (const PmArgs*)up.args_dev, up.off_dev, m);
+            profile_end("pm_fast", s, 0, nullptr, 0);
+        }
+        {
+            const BatchUpload up = stage_table(ar, ea.data(), m * sizeof(PmArgs), off);
+            if (ar.overflow) break;
+            const size_t sh = lds_bytes(pl.le);
+            hipFuncSetAttribute((const void*)pl.es.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sh);
+            hipLaunchKernelGGL(pl.es.batch, dim3(grid), dim3(pl.le.waves * 64), sh, s,
+                               (const PmArgs*)up.args_dev, up.off_dev, m);
+        }
+        {
+            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
+            if (ar.overflow) break;
+            hipLaunchKernelGGL(k_pm_generic_batch, dim3(grid), dim3(256), 0, s,
+                               (const PmArgs*)up.args_dev, up.off_dev, m);
+        }
+        if (ar.overflow) {
+            set_error("batch workspace too small");
+            return PXST_EWORKSPACE;
+        }
+        rc = check_hip(hipGetLastError(), "batched pixel-map search");
+        if (rc) return rc;
+    }
+    return PXST_OK;
 }
 
 }  // namespace pxst
