@@ -103,6 +103,55 @@ def cpu_baseline(scan, n_workers: int, px_per_worker: int):
     }
 
 
+# ---------------------------------------------------------------- served stream
+def _gen_job(args):
+    k, spec, arrival = args
+    from synth import make_scan
+    s = make_scan(spec)
+    return (k, arrival, s.frames, s.white, s.mask, s.u0, s.dx0, tuple(s.ref_shape), tuple(s.origin),
+            s.iters, tuple(s.window))
+
+
+def served_requests(n_jobs: int, workers: int):
+    """The served stream's jobs (Poisson arrivals, mean gap 0.5 s), generated in parallel."""
+    from synth import served_job_specs
+    specs, gaps = served_job_specs(n_jobs)
+    arrivals = [float(x) for x in __import__("numpy").cumsum(gaps)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        rows = pool.map(_gen_job, [(k, specs[k], arrivals[k]) for k in range(n_jobs)], chunksize=1)
+    return rows
+
+
+def run_served(rows, time_scale: float):
+    from paper_2003_12726_amd import serve
+    reqs = [serve.Request(job_id=k, arrival=arr, frames=f, white=w, mask=m, u0=u, dx0=d, ref_shape=rs,
+                          origin=o, n_iter=it, window=win, refine=True)
+            for (k, arr, f, w, m, u, d, rs, o, it, win) in rows]
+    evals = sum(r.pm_evals() for r in reqs)
+    out = {}
+    for mode in ("one_by_one", "batched"):
+        if mode == "batched":
+            srv = serve.Server(budget_bytes=200 << 30, max_slots=64, keep_results=False)
+            res = srv.run(reqs, time_scale=time_scale)
+        else:
+            res = serve.run_one_by_one(reqs, time_scale=time_scale, keep_results=False)
+        first = min(r.arrival for r in res.values())
+        last = max(r.finished for r in res.values())
+        st = serve.latency_stats(res)
+        st["pm_evals_per_s"] = evals / (last - first)
+        st["makespan_s"] = last - first
+        if mode == "batched":
+            st["ticks"] = srv.ticks
+            st["max_resident"] = srv.max_resident
+        out[mode] = st
+    out["workload"] = (f"{len(reqs)} jobs, Poisson arrivals (mean 2 jobs/s) replayed {time_scale:g}x "
+                       f"faster, detectors from 128x128 to 512x512, 16-400 frames, windows +-4..15 px, "
+                       f"5 iterations, HBM budget 200 GB")
+    out["pm_evals_total"] = evals
+    return out
+
+
 # ------------------------------------------------------------------------ GPU leg
 class Job:
     """A scan resident on the GPU with its state, workspace and initial map."""
@@ -171,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-divergent", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--served-jobs", type=int, default=64)
+    ap.add_argument("--served-speedup", type=float, default=50.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the reconstruction of one scan runs on one device "
@@ -189,6 +240,9 @@ def main():
     if not args.no_cpu_baseline:
         nw = args.cpu_workers or min(16, os.cpu_count() or 1)
         cpu = cpu_baseline(scan, nw, 192)
+    served_rows = None
+    if args.served_jobs > 0:
+        served_rows = served_requests(args.served_jobs, args.cpu_workers or min(16, os.cpu_count() or 1))
     pxst.load_library()
     dev = torch.device("cuda:0")
     job = Job(scan, dev)
@@ -276,6 +330,13 @@ def main():
         }
         del dj
         torch.cuda.empty_cache()
+
+    if served_rows is not None:
+        torch.cuda.empty_cache()
+        out["served"] = run_served(served_rows, args.served_speedup)
+        latency = out["latency_ms"]
+        latency["served_p50_s"] = out["served"]["batched"]["p50_s"]
+        latency["served_p99_s"] = out["served"]["batched"]["p99_s"]
 
     if cpu is not None:
         out["cpu_baseline"] = cpu
