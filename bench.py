@@ -56,6 +56,63 @@ def load_traffic(workload: str):
     return ent
 
 
+def _counter_rows(d: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter):
+    """Counter value per dispatch (summed over the dimensions rocprofv3 reports)."""
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        key = r["Dispatch_Id"]
+        ent = per.setdefault(key, [r["Kernel_Name"], int(r["Grid_Size"]), 0.0])
+        ent[2] += float(r["Counter_Value"])
+    return list(per.values())
+
+
+def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
+    """HBM bytes per k_pm_fast launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for a device-to-device copy of known
+    size in the same run (copy_mib MiB read and written)."""
+    if copy_mib <= 0:
+        raise SystemExit("--copy-calibration-mib must give the calibration copy's size")
+    nb = copy_mib << 20
+    res = {}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        disp = _per_dispatch(_counter_rows(d), counter)
+        pm = [v for k, g, v in disp if "k_pm_fast" in k]
+        cp = [v for k, g, v in disp if "copyBuffer" in k or "copy" in k.lower()]
+        if not pm or not cp:
+            raise SystemExit(f"{counter}: k_pm_fast dispatches {len(pm)}, copy dispatches {len(cp)}")
+        copy_kib = max(cp)
+        factor = (nb / 1024.0) / copy_kib
+        kib = sum(pm) / len(pm)
+        res[name] = {"kib_per_dispatch_raw": kib, "dispatches": len(pm),
+                     "copy_kib_raw": copy_kib, "factor": factor, "bytes": kib * 1024.0 * factor}
+    p = os.path.join(ROOT, "profiles", "pm_fast_traffic.json")
+    d = {}
+    if os.path.exists(p):
+        with open(p) as fh:
+            d = json.load(fh)
+    d["realistic"] = {"source_hash": pm_source_hash(), "copy_mib": copy_mib,
+                      "fetch": res["fetch"], "write": res["write"],
+                      "bytes_per_launch": res["fetch"]["bytes"] + res["write"]["bytes"]}
+    with open(p, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d["realistic"], indent=1))
+
+
 # --------------------------------------------------------------------- oracle leg
 _ORC = {}
 
@@ -222,7 +279,15 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--served-jobs", type=int, default=64)
     ap.add_argument("--served-speedup", type=float, default=50.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="end with one device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration-mib run into profiles/pm_fast_traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, copy_mib=args.copy_calibration_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the reconstruction of one scan runs on one device "
               f"(--gpus {args.gpus} is not supported; multi-GPU sharding is not built)", file=sys.stderr)
@@ -340,6 +405,14 @@ def main():
 
     if cpu is not None:
         out["cpu_baseline"] = cpu
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     print(json.dumps(out), flush=True)
 
