@@ -219,6 +219,39 @@ __device__ inline void eval_rows(const float* G, const int (&rowoff)[KR], float 
 //   interpolate and store the next frame's elements, barrier.
 constexpr int PFS = 4;
 
+// Per-frame shift table in LDS, after both staging buffers and the dump slots: for
+// frame n, (e, t) of both axes (axis_shift of dx_n).  Built once per tile so that the
+// frame loop reads it from LDS instead of waiting on a global load every frame.
+constexpr int SHIFT_TAB_OFF = 2 * PM_STAGE_FLOATS + 512;   // floats
+
+__device__ inline int4* shift_table(float* smem) { return (int4*)(smem + SHIFT_TAB_OFF); }
+
+__device__ inline void build_shift_table(const PmArgs& a, float* smem) {
+    int4* tab = shift_table(smem);
+    for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
+        const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+        const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+        tab[n] = make_int4(s0.e, s1.e, __float_as_int(s0.t), __float_as_int(s1.t));
+    }
+    __syncthreads();
+}
+
+struct FrameShift {
+    int goff;       // e0 * Rf + e1 (work-group uniform)
+    int e0, e1;
+    float t0, t1;
+};
+
+__device__ inline FrameShift frame_shift(int4 v, int Rf) {
+    FrameShift f;
+    f.e0 = __builtin_amdgcn_readfirstlane(v.x);
+    f.e1 = __builtin_amdgcn_readfirstlane(v.y);
+    f.t0 = __int_as_float(__builtin_amdgcn_readfirstlane(v.z));
+    f.t1 = __int_as_float(__builtin_amdgcn_readfirstlane(v.w));
+    f.goff = f.e0 * Rf + f.e1;
+    return f;
+}
+
 template <int CW, int KR>
 __device__ void pm_fast_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
@@ -257,6 +290,8 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
         st_lds[s] = e < nel ? r * P + q : 2 * bufsz + tid;
         st_glb[s] = (T0 + r) * Rf + (T1 + q);
     }
+    build_shift_table(a, smem);
+    const int4* __restrict__ tab = shift_table(smem);
 
     for (int pass = 0; pass < a.sub; ++pass) {
         const int pidx = pass * ppp + pip;
@@ -287,33 +322,36 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
 
         // stage frame 0 into buffer 0
         {
-            const AxisShift s0 = axis_shift(a.dx[0], a.o0), s1 = axis_shift(a.dx[1], a.o1);
-            const int goff = s0.e * Rf + s1.e;
+            const FrameShift f = frame_shift(tab[0], Rf);
 #pragma unroll
             for (int s = 0; s < PFS; ++s) {
                 if (s < nst) {
-                    const float* p = refv + (st_glb[s] - goff);
-                    smem[st_lds[s]] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], s0.t, s1.t);
+                    const float* p = refv + (st_glb[s] - f.goff);
+                    smem[st_lds[s]] = bilinear4(p[0], p[1], p[Rf], p[Rf + 1], f.t0, f.t1);
                 }
             }
             __syncthreads();
         }
+        int4 shn = tab[min(1, N - 1)];   // shift of the frame staged next
 
         const uint16_t* fp = a.frames + pix;
         float I = (float)fp[0];
-        for (int n = 0; n < N; ++n) {
+        // blocks of FOLD frames: plain sums inside a block, compensated fold after it
+        // (keeping the fold out of the frame loop keeps the accumulators in place)
+        for (int n0 = 0; n0 < N; n0 += FOLD) {
+        const int nend = min(n0 + FOLD, N);
+        for (int n = n0; n < nend; ++n) {
             const int n1 = min(n + 1, N - 1);
             const float* G = smem + (n & 1) * bufsz + base;
             float* Gn = smem + ((n + 1) & 1) * bufsz;
             const float Inext = (float)fp[(size_t)n1 * HW];
-            const AxisShift s0n = axis_shift(a.dx[2 * n1], a.o0);
-            const AxisShift s1n = axis_shift(a.dx[2 * n1 + 1], a.o1);
-            const int goff = s0n.e * Rf + s1n.e;
+            const FrameShift fn = frame_shift(shn, Rf);
+            shn = tab[min(n + 2, N - 1)];
             float pv[PFS][4];
 #pragma unroll
             for (int s = 0; s < PFS; ++s) {
                 if (s < nst) {
-                    const float* p = refv + (st_glb[s] - goff);
+                    const float* p = refv + (st_glb[s] - fn.goff);
                     pv[s][0] = p[0];
                     pv[s][1] = p[1];
                     pv[s][2] = p[Rf];
@@ -330,17 +368,15 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
 #pragma unroll
             for (int s = 0; s < PFS; ++s)
                 if (s < nst)
-                    Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], s0n.t, s1n.t);
+                    Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], fn.t0, fn.t1);
             I = Inext;
             __syncthreads();
-
-            if (((n + 1) % FOLD) == 0) {
+        }
 #pragma unroll
-                for (int r = 0; r < KR; ++r)
+        for (int r = 0; r < KR; ++r)
 #pragma unroll
-                    for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
-                two_sum_fold(vS, vP);
-            }
+            for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
+        two_sum_fold(vS, vP);
         }
 
         // per-thread first minimum over its candidates (index order); the normalised
@@ -400,6 +436,8 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
     int rowoff[KR];
 #pragma unroll
     for (int r = 0; r < KR; ++r) rowoff[r] = min(kx0 + r, NX - 1) * P;
+    build_shift_table(a, smem);
+    const int4* __restrict__ tab = shift_table(smem);
 
     for (int pass = 0; pass < a.sub; ++pass) {
         const int pidx = pass * ppp + pip;
@@ -433,11 +471,11 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
         // stage frame 0 into buffer 0
         int slow_cur;
         {
-            const AxisShift s0 = axis_shift(a.dx[0], a.o0), s1 = axis_shift(a.dx[1], a.o1);
+            const FrameShift f = frame_shift(tab[0], Rf);
             int mine = 0;
             for (int e = tid; e < nel; e += nthr) {
                 const int r = e / RW, q = e - r * RW;
-                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - s0.e, T1 + q - s1.e, s0.t, s1.t);
+                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - f.e0, T1 + q - f.e1, f.t0, f.t1);
                 smem[r * P + q] = g;
                 mine |= valid(g) ? 0 : 1;
             }
@@ -446,7 +484,9 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
 
         const uint16_t* fp = a.frames + pix;
         float I = (float)fp[0];
-        for (int n = 0; n < N; ++n) {
+        for (int n0 = 0; n0 < N; n0 += FOLD) {
+        const int nend = min(n0 + FOLD, N);
+        for (int n = n0; n < nend; ++n) {
             const int n1 = min(n + 1, N - 1);
             const float* G = smem + (n & 1) * bufsz + base;
             float* Gn = smem + ((n + 1) & 1) * bufsz;
@@ -473,26 +513,23 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
             __builtin_amdgcn_sched_barrier(0);
 
             // stage frame n + 1 (the last frame is staged again harmlessly)
-            const AxisShift s0n = axis_shift(a.dx[2 * n1], a.o0);
-            const AxisShift s1n = axis_shift(a.dx[2 * n1 + 1], a.o1);
+            const FrameShift fn = frame_shift(tab[n1], Rf);
             int mine = 0;
             for (int e = tid; e < nel; e += nthr) {
                 const int r = e / RW, q = e - r * RW;
-                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - s0n.e, T1 + q - s1n.e, s0n.t,
-                                                s1n.t);
+                const float g = masked_bilinear(refv, a.Rs, Rf, T0 + r - fn.e0, T1 + q - fn.e1, fn.t0,
+                                                fn.t1);
                 Gn[r * P + q] = g;
                 mine |= valid(g) ? 0 : 1;
             }
             I = Inext;
             slow_cur = __syncthreads_or(mine);
-
-            if (((n + 1) % FOLD) == 0) {
+        }
 #pragma unroll
-                for (int r = 0; r < KR; ++r)
+        for (int r = 0; r < KR; ++r)
 #pragma unroll
-                    for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
-                two_sum_fold(vS, vP);
-            }
+            for (int m = 0; m < CW; ++m) two_sum_fold(eS[r][m], eP[r][m]);
+        two_sum_fold(vS, vP);
         }
 
         float bestE = INFINITY;
@@ -752,8 +789,8 @@ Launch plan_launch(int nx, int ny, int cw, int kr) {
     return l;
 }
 
-size_t lds_bytes(const Launch& l) {
-    const size_t stage = (2 * (size_t)PM_STAGE_FLOATS + 512) * sizeof(float);
+size_t lds_bytes(const Launch& l, int n_frames) {
+    const size_t stage = (size_t)SHIFT_TAB_OFF * sizeof(float) + (size_t)n_frames * sizeof(int4);
     const int ppp = 64 / l.sub;
     const size_t red = (size_t)l.nblocks * ppp * 8 + (size_t)ppp * 8 + (size_t)ppp * 9 * 4;
     return stage > red ? stage : red;
@@ -844,7 +881,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
     {
-        const size_t sh = lds_bytes(pl.lf);
+        const size_t sh = lds_bytes(pl.lf, g.N);
         hipFuncSetAttribute((const void*)pl.fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_fast", s);
         hipLaunchKernelGGL(pl.fs.fn, dim3(a.ntiles), dim3(pl.lf.waves * 64), sh, s, pl.fast_args(a));
@@ -853,7 +890,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
         if (rc) return rc;
     }
     {
-        const size_t sh = lds_bytes(pl.le);
+        const size_t sh = lds_bytes(pl.le, g.N);
         hipFuncSetAttribute((const void*)pl.es.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_edge", s);
         hipLaunchKernelGGL(pl.es.fn, dim3(a.ntiles), dim3(pl.le.waves * 64), sh, s, pl.edge_args(a));
@@ -918,10 +955,12 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
             off[q + 1] = off[q] + base[grp[q]].ntiles;
         }
         const int grid = std::min(off[m], persistent_groups);
+        int max_n = 1;
+        for (int q = 0; q < m; ++q) max_n = std::max(max_n, base[grp[q]].N);
         {
             const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
-            const size_t sh = lds_bytes(pl.lf);
+            const size_t sh = lds_bytes(pl.lf, max_n);
             hipFuncSetAttribute((const void*)pl.fs.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sh);
             profile_begin("pm_fast", s);
@@ -932,7 +971,7 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
         {
             const BatchUpload up = stage_table(ar, ea.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
-            const size_t sh = lds_bytes(pl.le);
+            const size_t sh = lds_bytes(pl.le, max_n);
             hipFuncSetAttribute((const void*)pl.es.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sh);
             hipLaunchKernelGGL(pl.es.batch, dim3(grid), dim3(pl.le.waves * 64), sh, s,
