@@ -170,6 +170,11 @@ Layout make_layout(const Geom& g, int tr_ct) {
     L.tiles = take(ntiles * sizeof(TileDesc));
     L.lists = take(3 * ntiles * sizeof(int));
     L.counters = take(CNT_N * sizeof(int));
+    L.kblocks = (g.N + MM_KB - 1) / MM_KB;
+    L.ipk = take(ntiles * (size_t)L.kblocks * MM_PACK_BYTES);
+    L.pstat = take(ntiles * 64 * 4 * sizeof(double));
+    L.rowmax = take((size_t)g.Rs * sizeof(float));
+    L.fscale = take(sizeof(int));
     const size_t nblk_tr = (HW + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK;
     L.tr_part = take((size_t)g.N * nblk_tr * (tr_ct > 0 ? tr_ct : 1) * 3 * sizeof(float));
     const size_t per_err = (size_t)ERR_THREADS * ERR_PIX_PER_THREAD_CFG;
@@ -319,8 +324,10 @@ int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double*
     char* w = (char*)ws;
     float* refv = (float*)(w + L.refv);
     int* sat = (int*)(w + L.sat);
-    if ((rc = launch_prep_reference(g, ref, wsum, refv, sat, (int*)(w + L.sat_tmp), stream)))
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, sat, (int*)(w + L.sat_tmp),
+                                        (float*)(w + L.rowmax), (int*)(w + L.fscale), stream)))
         return rc;
+    if ((rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
     return launch_pixel_map(g, *scan, refv, sat, dx, u_in, window, u_out, err_min, argmin, w, L,
                             stream);
 }
@@ -342,7 +349,7 @@ int pxst_update_translations(const pxst_scan* scan, const float* ref, const doub
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     char* w = (char*)ws;
     float* refv = (float*)(w + L.refv);
-    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, stream))) return rc;
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
     return launch_translations(g, *scan, refv, u, dx_in, window, dx_out, err_min, argmin, w, L,
                                stream);
 }
@@ -364,7 +371,7 @@ int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, cons
     char* w = (char*)ws;
     float* refv = (float*)(w + L.refv);
     float* s2 = (float*)(w + L.s2);
-    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, stream))) return rc;
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
     if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
     if ((rc = launch_error(g, *scan, refv, s2, u, dx, pixel_err, frame_err, total, w, L, stream)))
         return rc;
@@ -400,9 +407,11 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     int* sat_tmp = (int*)(w + L.sat_tmp);
     float* s2 = (float*)(w + L.s2);
     if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
+    if (opts->n_iter > 0 && (rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
     for (int k = 0; k < opts->n_iter; ++k) {
         if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream))) return rc;
-        if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, stream))) return rc;
+        if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, (float*)(w + L.rowmax),
+                                             (int*)(w + L.fscale), stream))) return rc;
         if ((rc = launch_pixel_map(g, *scan, refv, sat, dx, u, opts->pm, u, nullptr, nullptr, w, L,
                                    stream)))
             return rc;
@@ -533,12 +542,16 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
     for (int j = 0; j < n_jobs && !rc; ++j) {
         const pxst_job& J = jobs[j];
         if (J.iter == 0) rc = launch_sigma2(st[j].g, J.scan, (float*)(st[j].w + st[j].L.s2), stream);
+        if (!rc && J.iter == 0 && J.opts.n_iter > 0)
+            rc = launch_pm_setup(st[j].g, J.scan, st[j].w, st[j].L, stream);
         if (!rc)
             rc = launch_update_reference(st[j].g, J.scan, J.u, J.dx, J.ref, J.wsum, st[j].refv, st[j].w,
                                          st[j].L, stream);
         if (!rc && J.iter < J.opts.n_iter)
             rc = launch_prep_reference(st[j].g, nullptr, nullptr, st[j].refv, (int*)(st[j].w + st[j].L.sat),
-                                       (int*)(st[j].w + st[j].L.sat_tmp), stream);
+                                       (int*)(st[j].w + st[j].L.sat_tmp),
+                                       (float*)(st[j].w + st[j].L.rowmax),
+                                       (int*)(st[j].w + st[j].L.fscale), stream);
     }
     // (ii) pixel-map search of the jobs that iterate, batched over jobs
     std::vector<PmJobDesc> pm;

@@ -26,6 +26,10 @@ inline Geom geom_of(const pxst_geom& g) {
 constexpr int TILE = 8;
 // Staging budget of one LDS buffer of the pixel-map search (floats); two are used.
 constexpr int PM_STAGE_FLOATS = 7936;
+// Pixel-map search on the matrix cores: frames per K-block of the int8 products.
+constexpr int MM_KB = 64;
+// Packed frames of one tile and K-block: 4 row groups x 2 bytes x 64 lanes x 16 bytes.
+constexpr size_t MM_PACK_BYTES = 4 * 2 * 64 * 16;
 // Translation partial sums: detector pixels per work-group.
 constexpr int TR_PIX_PER_BLOCK = 4096;
 constexpr int TR_THREADS = 256;
@@ -71,6 +75,9 @@ struct Layout {
     size_t sort_tmp_bytes;
     // pixel map
     size_t tiles, lists, counters;
+    size_t ipk, pstat;        // frames packed as int8 matrix operands; per-pixel frame sums
+    size_t rowmax, fscale;    // per-row max |reference| and the fixed-point exponent
+    int kblocks;              // frame K-blocks of the packed frames
     // translations
     size_t tr_part;
     // error
@@ -142,8 +149,15 @@ struct PmJobDesc {
 
 // Reference preparation for lookups: refv = ref where wsum > 0, else NaN; and (when
 // `sat` is non-null) the summed-area table of invalid reference pixels.
+// refv = reference with NaN where the weight sum is 0; when sat is given also the
+// summed-area table of invalid pixels and, from the per-row maxima of |refv|, the
+// exponent F of the fixed-point reference used by the matrix-core search.
 int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv,
-                          int* sat, int* sat_tmp, hipStream_t s);
+                          int* sat, int* sat_tmp, float* rowmax, int* fscale, hipStream_t s);
+
+// Job setup of the matrix-core pixel-map search (depends on the frames only): frames
+// packed as biased int8 operands per tile and K-block, and per-pixel frame sums.
+int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& L, hipStream_t s);
 
 // Reference update (splat as a deterministic gather over the inverted map).
 int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,

@@ -46,6 +46,11 @@ struct PmArgs {
     int nchunks, nblocks, sub;
     int stage_cap;      // max RH * RW handled with staging (edge kernel)
     int fast_cap;       // max RH * RW of the fast kernel (staged elements per frame)
+    // matrix-core search of interior tiles
+    const uint4* ipk;   // packed frames [tile][kblock][4][2][64] x 16 bytes
+    const double* pstat;  // per tile pixel: sum I^2, 32896 sum I, sum (I - W)^2, good
+    const int* fscale;  // fixed-point exponent of the reference
+    int kblocks;
 };
 
 __global__ void k_zero_counters(int* c) {
@@ -656,6 +661,316 @@ __device__ void pm_generic_item(const PmArgs& a, int slot) {
     __syncthreads();
 }
 
+// ------------------------------------------------------ matrix-core search (interior)
+//
+// For an interior tile every lookup is valid, and with g_n(q) the reference interpolated
+// for frame n at the tile-region position q of a candidate, the error of that candidate
+// at pixel p expands as
+//     sum_n (I_n - W g_n)^2 = sum_n I_n^2 - 2 W sum_n I_n g_n(q) + W^2 sum_n g_n(q)^2.
+// The middle sum is a contraction over frames, S[p][q] = sum_n I[p][n] G[n][q], of the
+// 64 x N count matrix of the tile with the N x Q matrix of interpolated reference values:
+// it runs on the int8 matrix cores with exact int32 accumulation.  Counts are split into
+// two bytes, g into a 24-bit fixed-point number G = rint(g 2^F) (F per reference, so
+// that |G| < 2^22) offset by 2^23 and split into three bytes; every byte is stored
+// biased by -128 so that it is a signed int8, and the bias is removed with row and
+// column sums.  The three sums are exact (or FP64) and combined in FP64, so the
+// cancellation between them costs no accuracy.  The errors of all candidates of the
+// tile's 64 pixels go to LDS; the first minimum and the paraboloid refinement follow.
+constexpr int MM_WAVES = 8;
+constexpr int MM_THREADS = MM_WAVES * 64;
+
+typedef int mm_v4i __attribute__((ext_vector_type(4)));
+
+struct MmPix {
+    double A;      // sum I^2
+    double Ib;     // 32896 sum I: the count-sum terms of the bias and of the 2^23 offset
+    double var;    // sum (I - W)^2
+    double rvar;   // 1 / var
+    float W;
+    int dc0, dc1;  // window centre relative to the tile's smallest centre
+    int good;
+};
+
+// Frames of a tile as the A operand (rows = the tile's 64 pixels in four groups of 16,
+// K = frames): lane l of group m holds pixel m*16 + l%16, frames 16*(l/16) .. +15 of the
+// K-block, byte 0 (then byte 1) of each count, biased by -128.
+__global__ __launch_bounds__(256) void k_pm_pack(const uint16_t* __restrict__ frames,
+                                                 const uint8_t* __restrict__ mask, int N, int H, int W,
+                                                 int tiles_x, int KB, uint4* __restrict__ ipk) {
+    const int tile = blockIdx.x / KB, kb = blockIdx.x - tile * KB;
+    const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = m * 16 + (lane & 15);
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+    const bool good = i < H && j < W && mask[(size_t)i * W + j] != 0;
+    const size_t HW = (size_t)H * W;
+    const size_t pix = good ? (size_t)i * W + j : 0;
+    unsigned lo[4], hi[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        unsigned l = 0, h = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int n = kb * MM_KB + 16 * (lane >> 4) + 4 * w + b;
+            const unsigned v = (good && n < N) ? (unsigned)frames[(size_t)n * HW + pix] : 0u;
+            l |= (v & 255u) << (8 * b);
+            h |= (v >> 8) << (8 * b);
+        }
+        lo[w] = l ^ 0x80808080u;
+        hi[w] = h ^ 0x80808080u;
+    }
+    const size_t base = (((size_t)tile * KB + kb) * 4 + m) * 2 * 64 + lane;
+    ipk[base] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    ipk[base + 64] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+}
+
+// Per-pixel frame sums of a tile (FP64, exact for the integer sums).
+__global__ __launch_bounds__(64) void k_pm_pixstats(const uint16_t* __restrict__ frames,
+                                                    const float* __restrict__ white,
+                                                    const uint8_t* __restrict__ mask, int N, int H,
+                                                    int W, int tiles_x, double* __restrict__ pstat) {
+    const int tile = blockIdx.x, p = threadIdx.x;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+    const bool good = i < H && j < W && mask[(size_t)i * W + j] != 0;
+    const size_t HW = (size_t)H * W;
+    double A = 0.0, S = 0.0, V = 0.0;
+    if (good) {
+        const size_t pix = (size_t)i * W + j;
+        const double Wp = (double)white[pix];
+        for (int n = 0; n < N; ++n) {
+            const double I = (double)frames[(size_t)n * HW + pix];
+            A = fma(I, I, A);
+            S += I;
+            const double v = I - Wp;
+            V = fma(v, v, V);
+        }
+    }
+    double* o = pstat + ((size_t)tile * 64 + p) * 4;
+    o[0] = A;
+    o[1] = 32896.0 * S;
+    o[2] = V;
+    o[3] = good ? 1.0 : 0.0;
+}
+
+__device__ inline mm_v4i mm_as_v4i(uint4 v) {
+    mm_v4i r;
+    r.x = (int)v.x;
+    r.y = (int)v.y;
+    r.z = (int)v.z;
+    r.w = (int)v.w;
+    return r;
+}
+
+// LDS of the matrix-core search: E [64][NC] floats | frame weights float4 [N] | frame
+// offsets int [N] | pixel parameters MmPix [64].
+__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames) {
+    const size_t e = ((size_t)64 * nc + 3) / 4 * 4 * sizeof(float);
+    const size_t w = (size_t)n_frames * 16;
+    const size_t o = ((size_t)n_frames * 4 + 7) / 8 * 8;
+    return e + w + o + 64 * sizeof(MmPix);
+}
+
+__device__ void pm_mma_item(const PmArgs& a, int slot) {
+    extern __shared__ float smem[];
+    if (slot >= a.counters[CNT_FAST]) return;
+    const int tile = a.lists[CNT_FAST * a.ntiles + slot];
+    const TileDesc td = a.tiles[tile];
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int RW = td.rw, Q = td.rh * td.rw, NT = (Q + 15) >> 4;
+    const int T0 = td.cmin0 - a.rx, T1 = td.cmin1 - a.ry;
+    const int NX = a.NX, NY = a.NY, NC = NX * NY, N = a.N, Rf = a.Rf, KB = a.kblocks;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t HW = (size_t)a.H * a.W;
+
+    float* ebuf = smem;
+    float4* fw = (float4*)(smem + ((size_t)64 * NC + 3) / 4 * 4);
+    int* fgo = (int*)(fw + N);
+    MmPix* pp = (MmPix*)((char*)fgo + ((size_t)N * 4 + 7) / 8 * 8);
+
+    for (int n = tid; n < N; n += MM_THREADS) {
+        const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+        const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+        fgo[n] = s0.e * Rf + s1.e;
+        const float t0 = s0.t, t1 = s1.t;
+        fw[n] = make_float4((1.f - t0) * (1.f - t1), (1.f - t0) * t1, t0 * (1.f - t1), t0 * t1);
+    }
+    if (tid < 64) {
+        const int p = tid;
+        const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+        const bool inb = i < a.H && j < a.W;
+        const size_t pix = inb ? (size_t)i * a.W + j : 0;
+        MmPix q;
+        q.good = inb && a.mask[pix] != 0;
+        q.dc0 = q.dc1 = -(1 << 28);
+        q.W = 0.f;
+        q.A = q.Ib = q.var = q.rvar = 0.0;
+        if (q.good) {
+            q.dc0 = window_centre(a.u_in[pix]) - td.cmin0;
+            q.dc1 = window_centre(a.u_in[HW + pix]) - td.cmin1;
+            q.W = a.white[pix];
+            const double* st = a.pstat + ((size_t)tile * 64 + p) * 4;
+            q.A = st[0];
+            q.Ib = st[1];
+            q.var = st[2];
+            q.rvar = q.var > 0.0 ? 1.0 / q.var : 0.0;
+        }
+        pp[p] = q;
+    }
+    __syncthreads();
+
+    const int F = *a.fscale;
+    const float fs = ldexpf(1.f, F);
+    const double inv = ldexp(1.0, -F), inv2 = inv * inv;
+    const double kconst = 16384.0 * 257.0 * 65793.0 * (double)(KB * MM_KB);
+    const int c = lane & 15, g = lane >> 4;
+    const uint4* __restrict__ ipk = a.ipk + (size_t)tile * KB * (4 * 2 * 64) + lane;
+
+    for (int nt = wave; nt < NT; nt += MM_WAVES) {
+        const int q = nt * 16 + c;
+        const bool qv = q < Q;
+        const int r = qv ? q / RW : 0, cc = qv ? q - r * RW : 0;
+        const float* __restrict__ rp = a.refv + ((size_t)(T0 + r) * Rf + (T1 + cc));
+        mm_v4i acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[m][s] = mm_v4i{0, 0, 0, 0};
+        double GU = 0.0, CS = 0.0;
+        for (int kb = 0; kb < KB; ++kb) {
+            // B operand: 16 frames of this lane's position, three biased bytes each
+            unsigned B0[4], B1[4], B2[4];
+            unsigned gsum = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                unsigned u[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int n = kb * MM_KB + 16 * g + 4 * w + b;
+                    unsigned gu = 0;
+                    if (qv && n < N) {
+                        const float* pr = rp - fgo[n];
+                        const float4 wt = fw[n];
+                        const float v =
+                            fmaf(wt.w, pr[Rf + 1], fmaf(wt.z, pr[Rf], fmaf(wt.y, pr[1], wt.x * pr[0])));
+                        const int gt = (int)rintf(v * fs);
+                        CS = fma((double)gt, (double)gt, CS);
+                        gu = (unsigned)(gt + (1 << 23));
+                        gsum += gu;
+                    }
+                    u[b] = gu;
+                }
+                const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
+                const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
+                const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
+                const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
+                B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
+                B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
+                B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
+            }
+            GU += (double)gsum;
+            const mm_v4i b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
+            const mm_v4i b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
+            const mm_v4i b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
+            const uint4* ak = ipk + (size_t)kb * (4 * 2 * 64);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const mm_v4i a0 = mm_as_v4i(ak[(m * 2) * 64]);
+                const mm_v4i a1 = mm_as_v4i(ak[(m * 2 + 1) * 64]);
+                acc[m][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[m][0], 0, 0, 0);
+                acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[m][1], 0, 0, 0);
+                acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[m][1], 0, 0, 0);
+                acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b2, acc[m][2], 0, 0, 0);
+                acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[m][2], 0, 0, 0);
+                acc[m][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b2, acc[m][3], 0, 0, 0);
+            }
+        }
+        // column sums of the position over the four lane groups (same sum in all four)
+        GU += __shfl_xor(GU, 16, 64);
+        GU += __shfl_xor(GU, 32, 64);
+        CS += __shfl_xor(CS, 16, 64);
+        CS += __shfl_xor(CS, 32, 64);
+        const double gterm = 128.0 * 257.0 * GU - kconst;
+        const double Cq = CS * inv2;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = m * 16 + 4 * g + i;
+                const MmPix& P = pp[p];
+                const int kx = r - P.dc0, ky = cc - P.dc1;
+                if (!qv || (unsigned)kx >= (unsigned)NX || (unsigned)ky >= (unsigned)NY) continue;
+                const double D = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                                 65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
+                const double B = (D + gterm + P.Ib) * inv;   // sum_n I_n g_n
+                const double Wd = (double)P.W;
+                double err = fma(Wd * Wd, Cq, fma(-2.0 * Wd, B, P.A));
+                err = err > 0.0 ? err : 0.0;
+                float E;
+                if (P.var > 0.0)
+                    E = (float)(err * P.rvar);
+                else
+                    E = err == 0.0 ? 0.f : INFINITY;
+                ebuf[(size_t)p * NC + kx * NY + ky] = E;
+            }
+        }
+    }
+    __syncthreads();
+
+    // first minimum per pixel (8 lanes per pixel), then refinement and output
+    {
+        const int p = tid >> 3, sub = tid & 7;
+        const MmPix P = pp[p];
+        float be = INFINITY;
+        int bk = INT_MAX;
+        if (P.good) {
+            const float* e = ebuf + (size_t)p * NC;
+            for (int k = sub; k < NC; k += 8) {
+                const float v = e[k];
+                if (better(v, k, be, bk)) {
+                    be = v;
+                    bk = k;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            const float e2 = __shfl_xor(be, o, 64);
+            const int k2 = __shfl_xor(bk, o, 64);
+            if (better(e2, k2, be, bk)) {
+                be = e2;
+                bk = k2;
+            }
+        }
+        const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+        if (sub == 0 && i < a.H && j < a.W) {
+            const size_t pix = (size_t)i * a.W + j;
+            if (!P.good || !isfinite(be)) {
+                write_unchanged(a, pix, HW);
+            } else {
+                const int bx = bk / NY, by = bk - bx * NY;
+                float ox = 0.f, oy = 0.f;
+                if (a.refine) {
+                    float st[9];
+                    const float* e = ebuf + (size_t)p * NC;
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) {
+                        const int kx = bx + t / 3 - 1, ky = by + t % 3 - 1;
+                        st[t] = (kx >= 0 && kx < NX && ky >= 0 && ky < NY) ? e[kx * NY + ky] : INFINITY;
+                    }
+                    refine_at(st, bx, by, NX, NY, ox, oy);
+                }
+                const int c0 = P.dc0 + td.cmin0, c1 = P.dc1 + td.cmin1;
+                a.u_out[pix] = (float)(c0 + bx - a.rx) + ox;
+                a.u_out[HW + pix] = (float)(c1 + by - a.ry) + oy;
+                if (a.err_out) a.err_out[pix] = be;
+                if (a.arg_out) a.arg_out[pix] = bk;
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------------ wrappers
 // Single-job launches (one work-group per item) and persistent launches over the items
 // of several jobs (item i of the batch belongs to job j with off[j] <= i < off[j + 1];
@@ -684,6 +999,7 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
 
 PXST_WRAP(k_classify, 64, classify_item)
 PXST_WRAP(k_pm_generic, 256, pm_generic_item)
+PXST_WRAP(k_pm_mma, MM_THREADS, pm_mma_item)
 
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
@@ -834,8 +1150,16 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     const Launch le = plan_launch(a.NX, a.NY, es.cw, es.kr);
     a.stage_cap = 8 * le.waves * 64;
     a.fast_cap = PFS * lf.waves * 64;
+    a.ipk = (const uint4*)(ws + L.ipk);
+    a.pstat = (const double*)(ws + L.pstat);
+    a.fscale = (const int*)(ws + L.fscale);
+    a.kblocks = L.kblocks;
     return a;
 }
+
+// Interior tiles go to the matrix-core search when its LDS fits.
+constexpr size_t MM_LDS_MAX = 160 * 1024;
+bool mm_fits(int nx, int ny, int n_frames) { return mm_lds_bytes(nx * ny, n_frames) <= MM_LDS_MAX; }
 
 // Launch shapes of the fast and edge kernels for a window (same for every job with
 // that window).
@@ -880,7 +1204,15 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     if (rc) return rc;
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
-    {
+    if (mm_fits(a.NX, a.NY, g.N)) {
+        const size_t sh = mm_lds_bytes(a.NX * a.NY, g.N);
+        hipFuncSetAttribute((const void*)k_pm_mma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        profile_begin("pm_fast", s);
+        hipLaunchKernelGGL(k_pm_mma, dim3(a.ntiles), dim3(MM_THREADS), sh, s, a);
+        profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
+        rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles, matrix cores)");
+        if (rc) return rc;
+    } else {
         const size_t sh = lds_bytes(pl.lf, g.N);
         hipFuncSetAttribute((const void*)pl.fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_fast", s);
@@ -902,6 +1234,16 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     hipLaunchKernelGGL(k_pm_generic, dim3(a.ntiles), dim3(256), 0, s, a);
     profile_end("pm_generic", s, 0, a.counters + CNT_GOOD_GENERIC, evals_per_good_px);
     return check_hip(hipGetLastError(), "pixel-map search (scattered tiles)");
+}
+
+int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& L, hipStream_t s) {
+    const int tiles_x = (g.W + TILE - 1) / TILE;
+    const int ntiles = tiles_x * ((g.H + TILE - 1) / TILE);
+    hipLaunchKernelGGL(k_pm_pack, dim3((unsigned)(ntiles * L.kblocks)), dim3(256), 0, s, sc.frames,
+                       sc.mask, g.N, g.H, g.W, tiles_x, L.kblocks, (uint4*)(ws + L.ipk));
+    hipLaunchKernelGGL(k_pm_pixstats, dim3((unsigned)ntiles), dim3(64), 0, s, sc.frames, sc.white,
+                       sc.mask, g.N, g.H, g.W, tiles_x, (double*)(ws + L.pstat));
+    return check_hip(hipGetLastError(), "pixel-map setup");
 }
 
 // Batched pixel-map search of several jobs.  Per job: counters reset; then one
@@ -957,7 +1299,17 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
         const int grid = std::min(off[m], persistent_groups);
         int max_n = 1;
         for (int q = 0; q < m; ++q) max_n = std::max(max_n, base[grp[q]].N);
-        {
+        if (mm_fits(base[j0].NX, base[j0].NY, max_n)) {
+            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
+            if (ar.overflow) break;
+            const size_t sh = mm_lds_bytes(base[j0].NX * base[j0].NY, max_n);
+            hipFuncSetAttribute((const void*)k_pm_mma_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sh);
+            profile_begin("pm_fast", s);
+            hipLaunchKernelGGL(k_pm_mma_batch, dim3(grid), dim3(MM_THREADS), sh, s,
+                               (const PmArgs*)up.args_dev, up.off_dev, m);
+            profile_end("pm_fast", s, 0, nullptr, 0);
+        } else {
             const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
             const size_t sh = lds_bytes(pl.lf, max_n);

@@ -331,17 +331,33 @@ __global__ void k_prep_refv(const float* __restrict__ ref, const double* __restr
 }
 
 // Inclusive prefix sums of the invalid flags along each reference row, written
-// transposed: tmp[c][r].
+// transposed: tmp[c][r]; rowmax[r] = max |refv| over the valid pixels of row r.
 __global__ __launch_bounds__(256) void k_sat_rows(const float* __restrict__ refv, int Rs, int Rf,
-                                                  int* __restrict__ tmp) {
+                                                  int* __restrict__ tmp, float* __restrict__ rowmax) {
     __shared__ int part[256];
+    __shared__ float pmax[256 / 64];
     const int r = blockIdx.x;
     const int per = (Rf + 255) / 256;
     const int c0 = threadIdx.x * per;
     int s = 0;
-    for (int c = c0; c < min(c0 + per, Rf); ++c) s += valid(refv[(size_t)r * Rf + c]) ? 0 : 1;
+    float mx = 0.f;
+    for (int c = c0; c < min(c0 + per, Rf); ++c) {
+        const float v = refv[(size_t)r * Rf + c];
+        s += valid(v) ? 0 : 1;
+        if (valid(v)) mx = fmaxf(mx, fabsf(v));
+    }
+    if (rowmax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if ((threadIdx.x & 63) == 0) pmax[threadIdx.x >> 6] = mx;
+    }
     part[threadIdx.x] = s;
     __syncthreads();
+    if (rowmax && threadIdx.x == 0) {
+        float m = pmax[0];
+        for (int w = 1; w < 256 / 64; ++w) m = fmaxf(m, pmax[w]);
+        rowmax[r] = m;
+    }
     for (int off = 1; off < 256; off <<= 1) {
         const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
@@ -357,9 +373,27 @@ __global__ __launch_bounds__(256) void k_sat_rows(const float* __restrict__ refv
 
 // Column prefix sums of tmp[c][:] into sat[(r+1)][(c+1)] (row 0 and column 0 are 0).
 __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, int Rs, int Rf,
-                                                  int* __restrict__ sat) {
+                                                  int* __restrict__ sat, const float* __restrict__ rowmax,
+                                                  int* __restrict__ fscale) {
     __shared__ int part[256];
     const int c = blockIdx.x;
+    if (c == 0 && fscale) {
+        // fixed-point exponent F: |refv| * 2^F < 2^22 for every valid pixel, so that a
+        // bilinear value (a convex combination of pixels) rounds to |G| <= 2^22
+        __shared__ float pm[256];
+        float m = 0.f;
+        for (int r = threadIdx.x; r < Rs; r += 256) m = fmaxf(m, rowmax[r]);
+        pm[threadIdx.x] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float mm = 0.f;
+            for (int t = 0; t < 256; ++t) mm = fmaxf(mm, pm[t]);
+            int e = 0;
+            if (mm > 0.f && isfinite(mm)) frexpf(mm, &e);   // mm < 2^e
+            *fscale = mm > 0.f && isfinite(mm) ? min(100, max(-100, 22 - e)) : 0;
+        }
+        __syncthreads();
+    }
     const int per = (Rs + 255) / 256;
     const int r0 = threadIdx.x * per;
     int s = 0;
@@ -395,14 +429,16 @@ size_t sort_temp_bound(size_t n) {
 }
 
 int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv, int* sat,
-                          int* sat_tmp, hipStream_t s) {
+                          int* sat_tmp, float* rowmax, int* fscale, hipStream_t s) {
     const size_t RR = g.RR();
     if (ref != nullptr)
         hipLaunchKernelGGL(k_prep_refv, dim3(grid_blocks(RR, 256)), dim3(256), 0, s, ref, wsum,
                            (int)RR, refv);
     if (sat != nullptr) {
-        hipLaunchKernelGGL(k_sat_rows, dim3(g.Rs), dim3(256), 0, s, refv, g.Rs, g.Rf, sat_tmp);
-        hipLaunchKernelGGL(k_sat_cols, dim3(g.Rf), dim3(256), 0, s, sat_tmp, g.Rs, g.Rf, sat);
+        hipLaunchKernelGGL(k_sat_rows, dim3(g.Rs), dim3(256), 0, s, refv, g.Rs, g.Rf, sat_tmp,
+                           fscale ? rowmax : nullptr);
+        hipLaunchKernelGGL(k_sat_cols, dim3(g.Rf), dim3(256), 0, s, sat_tmp, g.Rs, g.Rf, sat, rowmax,
+                           fscale);
     }
     return check_hip(hipGetLastError(), "prepare reference");
 }
