@@ -31,6 +31,7 @@ METRIC = "pixel-map candidate evals/s (pixels×shifts×frames); p50/p99 solve la
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_INT8_MFMA_TOPS = 5000.0   # dense int8 matrix-core peak
 FLOP_PER_EVAL = 4   # r = I - W g (1 FMA) and E += r^2 (1 FMA)
 
 
@@ -111,6 +112,34 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
     with open(p, "w") as fh:
         json.dump(d, fh, indent=1)
     print(json.dumps(d["realistic"], indent=1))
+
+
+def roofline(mm, avg_ms, launches, evals_per_launch, fp32_equiv_tflops, traffic):
+    """Roofline of the dominant kernel, the interior-tile pixel-map search.  On the matrix
+    cores its work is the int8 contraction it issues (2 ops per multiply-add); the
+    classic form (4 float32 flop per candidate evaluation on the vector ALUs) is given
+    beside it for comparison."""
+    common = {
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "avg_launch_ms": avg_ms,
+        "launches": launches,
+        "evals_per_launch": evals_per_launch,
+    }
+    equiv = {"fp32_vector_equivalent_tflops": fp32_equiv_tflops,
+             "fp32_vector_equivalent_frac_nonpacked": (fp32_equiv_tflops / PEAK_FP32_NONPACKED_TFLOPS)
+             if fp32_equiv_tflops else None}
+    mm_ms, mm_n, mm_ops = mm
+    if mm_n:
+        ops = mm_ops / mm_n
+        achieved = ops / (mm_ms / mm_n * 1e-3) / 1e12
+        return {"kernel": "pixel-map search, interior tiles (k_pm_mma: int8 matrix cores)",
+                "bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
+                "frac": achieved / PEAK_INT8_MFMA_TOPS, "int8_ops_per_launch": ops,
+                **common, **equiv}
+    return {"kernel": "pixel-map search, interior tiles (k_pm_fast: vector ALU)", "bound": "alu",
+            "achieved": fp32_equiv_tflops, "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+            "frac": equiv["fp32_vector_equivalent_frac_nonpacked"], "flop_per_eval": FLOP_PER_EVAL,
+            **common}
 
 
 # --------------------------------------------------------------------- oracle leg
@@ -313,17 +342,20 @@ def main():
     job = Job(scan, dev)
 
     pxst.profile_enable(True)
-    for fam in ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial", "err_pixels"):
+    fams = ("pm_fast", "pm_fast_int8_ops", "pm_edge", "pm_generic", "ref_gather", "tr_partial",
+            "err_pixels")
+    for fam in fams:
         pxst.profile_read(fam)
     # warm-up outside the profiled window
     for _ in range(args.warmup):
         job.step()
     torch.cuda.synchronize()
-    for fam in ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial", "err_pixels"):
+    for fam in fams:
         pxst.profile_read(fam)
     wall, lat = time_steps(job, args.steps, 0)
-    kern = {fam: pxst.profile_read(fam) for fam in
-            ("pm_fast", "pm_edge", "pm_generic", "ref_gather", "err_pixels")}
+    kern = {fam: pxst.profile_read(fam) for fam in fams}
+    mm = kern.pop("pm_fast_int8_ops")
+    kern.pop("tr_partial")
     pxst.profile_enable(False)
 
     ms_per_step = 1000.0 * wall / args.steps
@@ -360,21 +392,7 @@ def main():
         },
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": lat[-1],
                        "kind": "one full solve per job, jobs run one by one"},
-        "roofline": {
-            "kernel": "pixel-map search, interior tiles (k_pm_fast)",
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP32_NONPACKED_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": (achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS) if achieved_tflops else None,
-            "frac_of_packed_fp32_peak": (achieved_tflops / PEAK_FP32_PACKED_TFLOPS)
-            if achieved_tflops else None,
-            "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "avg_launch_ms": avg_ms,
-            "launches": f_n,
-            "evals_per_launch": evals_per_launch,
-            "flop_per_eval": FLOP_PER_EVAL,
-        },
+        "roofline": roofline(mm, avg_ms, f_n, evals_per_launch, achieved_tflops, traffic),
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
         "pixel_map_only_evals_per_s": pm_total_evals / (pm_total_ms * 1e-3) if pm_total_ms else None,
     }

@@ -223,8 +223,11 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
  * Families: "pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial",
- * "err_pixels".  pxst_profile_read returns the total milliseconds and the number
- * of timed launches, and resets the family. */
+ * "err_pixels", and "pm_fast_int8_ops" (the interior-tile search on the matrix
+ * cores, counting int8 operations).  pxst_profile_read returns the total
+ * milliseconds, the number of timed launches and the work units of the family
+ * (candidate evaluations, or int8 operations for "pm_fast_int8_ops"), and resets
+ * the family. */
 int pxst_profile_enable(int32_t on);
 int pxst_profile_read(const char* family, double* total_ms, int64_t* launches,
                       int64_t* work_units);

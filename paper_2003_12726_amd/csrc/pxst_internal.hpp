@@ -93,8 +93,10 @@ struct TileDesc {
 };
 
 // Counters written by the tile classification.
+// CNT_MM_POS: region positions (padded to 16) of the interior tiles, the column count of
+// the matrix-core search's products.
 enum { CNT_FAST = 0, CNT_EDGE = 1, CNT_GENERIC = 2, CNT_NONE = 3, CNT_GOOD_FAST = 4,
-       CNT_GOOD_EDGE = 5, CNT_GOOD_GENERIC = 6, CNT_N = 8 };
+       CNT_GOOD_EDGE = 5, CNT_GOOD_GENERIC = 6, CNT_MM_POS = 7, CNT_N = 8 };
 
 // Round up to a multiple of a such that the row pitch is 8 (mod 32) floats: an 8-wide
 // row of lanes then spans distinct LDS banks in each half-wave.

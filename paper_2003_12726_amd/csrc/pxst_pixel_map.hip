@@ -51,6 +51,7 @@ struct PmArgs {
     const double* pstat;  // per tile pixel: sum I^2, 32896 sum I, sum (I - W)^2, good
     const int* fscale;  // fixed-point exponent of the reference
     int kblocks;
+    int mm_lds_a;       // the tile's packed frames are staged in LDS
 };
 
 __global__ void k_zero_counters(int* c) {
@@ -119,6 +120,7 @@ __device__ void classify_item(const PmArgs& a, int tile) {
         const int slot = atomicAdd(&a.counters[cls], 1);
         a.lists[cls * a.ntiles + slot] = tile;
         atomicAdd(&a.counters[CNT_GOOD_FAST + cls], ngood);
+        if (cls == CNT_FAST) atomicAdd(&a.counters[CNT_MM_POS], (int)((rh * rw + 15) / 16 * 16));
     }
 }
 
@@ -681,13 +683,14 @@ constexpr int MM_THREADS = MM_WAVES * 64;
 
 typedef int mm_v4i __attribute__((ext_vector_type(4)));
 
+// Per-pixel coefficients of the normalised error: with S the combined int8 products of
+// the pixel and a position, g_q and C_q the position's column terms,
+//     E = al + be (S + g_q) + ga C_q;
+// when var = 0 the same coefficients give the error itself.
 struct MmPix {
-    double A;      // sum I^2
-    double Ib;     // 32896 sum I: the count-sum terms of the bias and of the 2^23 offset
-    double var;    // sum (I - W)^2
-    double rvar;   // 1 / var
-    float W;
+    double al, be, ga;
     int dc0, dc1;  // window centre relative to the tile's smallest centre
+    int zvar;      // var == 0
     int good;
 };
 
@@ -762,15 +765,20 @@ __device__ inline mm_v4i mm_as_v4i(uint4 v) {
     return r;
 }
 
-// LDS of the matrix-core search: E [64][NC] floats | frame weights float4 [N] | frame
-// offsets int [N] | pixel parameters MmPix [64].
-__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames) {
+// LDS of the matrix-core search: E [64][NC] floats | frame weights float4 [KB * 64] |
+// frame offsets int [KB * 64] | pixel parameters MmPix [64].  Frames past N (padding of
+// the last K-block) get zero weights and frame 0's offset.
+__host__ __device__ inline int mm_frames_padded(int n_frames) {
+    return (n_frames + MM_KB - 1) / MM_KB * MM_KB;
+}
+__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a) {
+    const size_t np = (size_t)mm_frames_padded(n_frames);
     const size_t e = ((size_t)64 * nc + 3) / 4 * 4 * sizeof(float);
-    const size_t w = (size_t)n_frames * 16;
-    const size_t o = ((size_t)n_frames * 4 + 7) / 8 * 8;
-    return e + w + o + 64 * sizeof(MmPix);
+    const size_t apk = stage_a ? np / MM_KB * MM_PACK_BYTES : 0;
+    return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + apk;
 }
 
+template <bool LDSA>
 __device__ void pm_mma_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
     if (slot >= a.counters[CNT_FAST]) return;
@@ -783,18 +791,28 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t HW = (size_t)a.H * a.W;
 
+    const int NP = KB * MM_KB;
     float* ebuf = smem;
     float4* fw = (float4*)(smem + ((size_t)64 * NC + 3) / 4 * 4);
-    int* fgo = (int*)(fw + N);
-    MmPix* pp = (MmPix*)((char*)fgo + ((size_t)N * 4 + 7) / 8 * 8);
+    unsigned* fgo4 = (unsigned*)(fw + NP);   // 4 * (e0 Rf + e1), modulo 2^32
+    MmPix* pp = (MmPix*)(fgo4 + NP);
+    uint4* apk = (uint4*)(pp + 64);          // the tile's packed frames, when staged
 
-    for (int n = tid; n < N; n += MM_THREADS) {
-        const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
-        const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
-        fgo[n] = s0.e * Rf + s1.e;
+    // frame table: bilinear weights scaled by 2^F (exact: a power of two) and the
+    // reference offset of the frame's shift
+    const float fs = ldexpf(1.f, *a.fscale);
+    for (int n = tid; n < NP; n += MM_THREADS) {
+        const int nn = n < N ? n : 0;
+        const AxisShift s0 = axis_shift(a.dx[2 * nn], a.o0);
+        const AxisShift s1 = axis_shift(a.dx[2 * nn + 1], a.o1);
+        fgo4[n] = 4u * (unsigned)(s0.e * Rf + s1.e);
         const float t0 = s0.t, t1 = s1.t;
-        fw[n] = make_float4((1.f - t0) * (1.f - t1), (1.f - t0) * t1, t0 * (1.f - t1), t0 * t1);
+        fw[n] = n < N ? make_float4((1.f - t0) * (1.f - t1) * fs, (1.f - t0) * t1 * fs,
+                                    t0 * (1.f - t1) * fs, t0 * t1 * fs)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    const int F = *a.fscale;
+    const double inv = ldexp(1.0, -F), inv2 = inv * inv;
     if (tid < 64) {
         const int p = tid;
         const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
@@ -803,34 +821,45 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         MmPix q;
         q.good = inb && a.mask[pix] != 0;
         q.dc0 = q.dc1 = -(1 << 28);
-        q.W = 0.f;
-        q.A = q.Ib = q.var = q.rvar = 0.0;
+        q.al = q.be = q.ga = 0.0;
+        q.zvar = 0;
         if (q.good) {
             q.dc0 = window_centre(a.u_in[pix]) - td.cmin0;
             q.dc1 = window_centre(a.u_in[HW + pix]) - td.cmin1;
-            q.W = a.white[pix];
+            const double Wd = (double)a.white[pix];
             const double* st = a.pstat + ((size_t)tile * 64 + p) * 4;
-            q.A = st[0];
-            q.Ib = st[1];
-            q.var = st[2];
-            q.rvar = q.var > 0.0 ? 1.0 / q.var : 0.0;
+            // err = A - 2 W inv (S + g_q + Ib) + W^2 inv^2 C_q
+            const double A = st[0], Ib = st[1], var = st[2];
+            const double s = var > 0.0 ? 1.0 / var : 1.0;
+            q.zvar = var > 0.0 ? 0 : 1;
+            q.be = -2.0 * Wd * inv * s;
+            q.ga = Wd * Wd * inv2 * s;
+            q.al = fma(-2.0 * Wd * inv, Ib, A) * s;
         }
         pp[p] = q;
     }
+    if (LDSA) {
+        const uint4* src = a.ipk + (size_t)tile * KB * (4 * 2 * 64);
+        for (int e = tid; e < KB * (4 * 2 * 64); e += MM_THREADS) apk[e] = src[e];
+    }
     __syncthreads();
 
-    const int F = *a.fscale;
-    const float fs = ldexpf(1.f, F);
-    const double inv = ldexp(1.0, -F), inv2 = inv * inv;
     const double kconst = 16384.0 * 257.0 * 65793.0 * (double)(KB * MM_KB);
     const int c = lane & 15, g = lane >> 4;
-    const uint4* __restrict__ ipk = a.ipk + (size_t)tile * KB * (4 * 2 * 64) + lane;
+    const uint4* __restrict__ ipk =
+        (LDSA ? (const uint4*)apk : a.ipk + (size_t)tile * KB * (4 * 2 * 64)) + lane;
 
     for (int nt = wave; nt < NT; nt += MM_WAVES) {
         const int q = nt * 16 + c;
         const bool qv = q < Q;
-        const int r = qv ? q / RW : 0, cc = qv ? q - r * RW : 0;
-        const float* __restrict__ rp = a.refv + ((size_t)(T0 + r) * Rf + (T1 + cc));
+        // lanes past the region compute the region's last position and discard it
+        const int qc = qv ? q : Q - 1;
+        const int r = qc / RW, cc = qc - r * RW;
+        // byte offset into the reference before the frame shift (every looked-up pixel
+        // lies in the validated rectangle, so offsets are in [0, 4 Rs Rf))
+        const unsigned roff4 = 4u * (unsigned)((T0 + r) * Rf + (T1 + cc));
+        const unsigned rf4 = 4u * (unsigned)Rf;
+        const char* __restrict__ refb = (const char*)a.refv;
         mm_v4i acc[4][4];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -839,25 +868,30 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         double GU = 0.0, CS = 0.0;
         for (int kb = 0; kb < KB; ++kb) {
             // B operand: 16 frames of this lane's position, three biased bytes each
+            // branch-free so that the 32 loads of the 16 frames are in flight together
             unsigned B0[4], B1[4], B2[4];
             unsigned gsum = 0;
+            float2 top[16], bot[16];
+            const int nb = kb * MM_KB + 16 * g;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const unsigned e4 = roff4 - fgo4[nb + t];
+                top[t] = *(const float2*)(refb + e4);
+                bot[t] = *(const float2*)(refb + (e4 + rf4));
+            }
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
                 unsigned u[4];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int n = kb * MM_KB + 16 * g + 4 * w + b;
-                    unsigned gu = 0;
-                    if (qv && n < N) {
-                        const float* pr = rp - fgo[n];
-                        const float4 wt = fw[n];
-                        const float v =
-                            fmaf(wt.w, pr[Rf + 1], fmaf(wt.z, pr[Rf], fmaf(wt.y, pr[1], wt.x * pr[0])));
-                        const int gt = (int)rintf(v * fs);
-                        CS = fma((double)gt, (double)gt, CS);
-                        gu = (unsigned)(gt + (1 << 23));
-                        gsum += gu;
-                    }
+                    const int t = 4 * w + b;
+                    const float4 wt = fw[nb + t];
+                    const float v = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                    // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
+                    const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
+                    const int gt = (int)gu - (1 << 23);
+                    CS = fma((double)gt, (double)gt, CS);
+                    gsum += gu;
                     u[b] = gu;
                 }
                 const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
@@ -890,28 +924,21 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         GU += __shfl_xor(GU, 32, 64);
         CS += __shfl_xor(CS, 16, 64);
         CS += __shfl_xor(CS, 32, 64);
-        const double gterm = 128.0 * 257.0 * GU - kconst;
-        const double Cq = CS * inv2;
+        const double gq = 128.0 * 257.0 * GU - kconst;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int p = m * 16 + 4 * g + i;
-                const MmPix& P = pp[p];
-                const int kx = r - P.dc0, ky = cc - P.dc1;
-                if (!qv || (unsigned)kx >= (unsigned)NX || (unsigned)ky >= (unsigned)NY) continue;
-                const double D = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                const MmPix P = pp[p];
+                const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
                                  65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                const double B = (D + gterm + P.Ib) * inv;   // sum_n I_n g_n
-                const double Wd = (double)P.W;
-                double err = fma(Wd * Wd, Cq, fma(-2.0 * Wd, B, P.A));
-                err = err > 0.0 ? err : 0.0;
-                float E;
-                if (P.var > 0.0)
-                    E = (float)(err * P.rvar);
-                else
-                    E = err == 0.0 ? 0.f : INFINITY;
-                ebuf[(size_t)p * NC + kx * NY + ky] = E;
+                double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                v = v > 0.0 ? v : 0.0;
+                const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
+                const int kx = r - P.dc0, ky = cc - P.dc1;
+                if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
+                    ebuf[(size_t)p * NC + kx * NY + ky] = E;
             }
         }
     }
@@ -999,7 +1026,10 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
 
 PXST_WRAP(k_classify, 64, classify_item)
 PXST_WRAP(k_pm_generic, 256, pm_generic_item)
-PXST_WRAP(k_pm_mma, MM_THREADS, pm_mma_item)
+__device__ void pm_mma_item_lds(const PmArgs& a, int slot) { pm_mma_item<true>(a, slot); }
+__device__ void pm_mma_item_glb(const PmArgs& a, int slot) { pm_mma_item<false>(a, slot); }
+PXST_WRAP(k_pm_mma_lds, MM_THREADS, pm_mma_item_lds)
+PXST_WRAP(k_pm_mma_glb, MM_THREADS, pm_mma_item_glb)
 
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
@@ -1159,7 +1189,13 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
 
 // Interior tiles go to the matrix-core search when its LDS fits.
 constexpr size_t MM_LDS_MAX = 160 * 1024;
-bool mm_fits(int nx, int ny, int n_frames) { return mm_lds_bytes(nx * ny, n_frames) <= MM_LDS_MAX; }
+bool mm_fits(int nx, int ny, int n_frames) {
+    return mm_lds_bytes(nx * ny, n_frames, false) <= MM_LDS_MAX;
+}
+// The tile's packed frames are staged in LDS when they fit beside the rest.
+bool mm_stage_a(int nx, int ny, int n_frames) {
+    return mm_lds_bytes(nx * ny, n_frames, true) <= MM_LDS_MAX;
+}
 
 // Launch shapes of the fast and edge kernels for a window (same for every job with
 // that window).
@@ -1205,10 +1241,18 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
     if (mm_fits(a.NX, a.NY, g.N)) {
-        const size_t sh = mm_lds_bytes(a.NX * a.NY, g.N);
-        hipFuncSetAttribute((const void*)k_pm_mma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        PmArgs b = a;
+        b.mm_lds_a = mm_stage_a(a.NX, a.NY, g.N) ? 1 : 0;
+        const size_t sh = mm_lds_bytes(a.NX * a.NY, g.N, b.mm_lds_a != 0);
+        const PmKernel kern = b.mm_lds_a ? k_pm_mma_lds : k_pm_mma_glb;
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_fast", s);
-        hipLaunchKernelGGL(k_pm_mma, dim3(a.ntiles), dim3(MM_THREADS), sh, s, a);
+        profile_begin("pm_fast_int8_ops", s);
+        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(MM_THREADS), sh, s, b);
+        // int8 operations issued on the matrix cores: 2 per multiply-add, 64 pixels x
+        // positions x padded frames x 6 byte pairs
+        profile_end("pm_fast_int8_ops", s, 0, a.counters + CNT_MM_POS,
+                    2LL * 64 * 6 * (long long)mm_frames_padded(g.N));
         profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles, matrix cores)");
         if (rc) return rc;
@@ -1300,14 +1344,17 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
         int max_n = 1;
         for (int q = 0; q < m; ++q) max_n = std::max(max_n, base[grp[q]].N);
         if (mm_fits(base[j0].NX, base[j0].NY, max_n)) {
-            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
+            const int stage_a = mm_stage_a(base[j0].NX, base[j0].NY, max_n) ? 1 : 0;
+            std::vector<PmArgs> ma(ga);
+            for (auto& x : ma) x.mm_lds_a = stage_a;
+            const BatchUpload up = stage_table(ar, ma.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
-            const size_t sh = mm_lds_bytes(base[j0].NX * base[j0].NY, max_n);
-            hipFuncSetAttribute((const void*)k_pm_mma_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sh);
+            const size_t sh = mm_lds_bytes(base[j0].NX * base[j0].NY, max_n, stage_a != 0);
+            const PmBatchKernel kern = stage_a ? k_pm_mma_lds_batch : k_pm_mma_glb_batch;
+            hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
             profile_begin("pm_fast", s);
-            hipLaunchKernelGGL(k_pm_mma_batch, dim3(grid), dim3(MM_THREADS), sh, s,
-                               (const PmArgs*)up.args_dev, up.off_dev, m);
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, (const PmArgs*)up.args_dev,
+                               up.off_dev, m);
             profile_end("pm_fast", s, 0, nullptr, 0);
         } else {
             const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);

@@ -378,8 +378,9 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
     __shared__ int part[256];
     const int c = blockIdx.x;
     if (c == 0 && fscale) {
-        // fixed-point exponent F: |refv| * 2^F < 2^22 for every valid pixel, so that a
-        // bilinear value (a convex combination of pixels) rounds to |G| <= 2^22
+        // fixed-point exponent F: |refv| * 2^F < 2^21 for every valid pixel, so that a
+        // bilinear value (a convex combination of pixels, weights rounded) stays well
+        // inside |G| < 2^22
         __shared__ float pm[256];
         float m = 0.f;
         for (int r = threadIdx.x; r < Rs; r += 256) m = fmaxf(m, rowmax[r]);
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
             for (int t = 0; t < 256; ++t) mm = fmaxf(mm, pm[t]);
             int e = 0;
             if (mm > 0.f && isfinite(mm)) frexpf(mm, &e);   // mm < 2^e
-            *fscale = mm > 0.f && isfinite(mm) ? min(100, max(-100, 22 - e)) : 0;
+            *fscale = mm > 0.f && isfinite(mm) ? min(100, max(-100, 21 - e)) : 0;
         }
         __syncthreads();
     }
