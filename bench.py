@@ -342,8 +342,8 @@ def main():
     job = Job(scan, dev)
 
     pxst.profile_enable(True)
-    fams = ("pm_fast", "pm_fast_int8_ops", "pm_edge", "pm_generic", "ref_gather", "tr_partial",
-            "err_pixels")
+    fams = ("pm_fast", "pm_fast_int8_ops", "pm_edge", "pm_edge_mma", "pm_generic", "ref_gather",
+            "tr_partial", "err_pixels")
     for fam in fams:
         pxst.profile_read(fam)
     # warm-up outside the profiled window
@@ -366,8 +366,8 @@ def main():
     avg_ms = f_ms / max(f_n, 1)
     evals_per_launch = f_work / max(f_n, 1)
     achieved_tflops = FLOP_PER_EVAL * evals_per_launch / (avg_ms * 1e-3) / 1e12 if f_n else None
-    pm_total_ms = sum(kern[k][0] for k in ("pm_fast", "pm_edge", "pm_generic"))
-    pm_total_evals = sum(kern[k][2] for k in ("pm_fast", "pm_edge", "pm_generic"))
+    pm_total_ms = sum(kern[k][0] for k in ("pm_fast", "pm_edge", "pm_edge_mma", "pm_generic"))
+    pm_total_evals = sum(kern[k][2] for k in ("pm_fast", "pm_edge", "pm_edge_mma", "pm_generic"))
     traffic = load_traffic("realistic")
 
     out = {

@@ -168,7 +168,7 @@ Layout make_layout(const Geom& g, int tr_ct) {
     L.sort_tmp = take(L.sort_tmp_bytes);
     const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);
     L.tiles = take(ntiles * sizeof(TileDesc));
-    L.lists = take(3 * ntiles * sizeof(int));
+    L.lists = take(4 * ntiles * sizeof(int));
     L.counters = take(CNT_N * sizeof(int));
     L.kblocks = (g.N + MM_KB - 1) / MM_KB;
     L.ipk = take(ntiles * (size_t)L.kblocks * MM_PACK_BYTES);

@@ -95,8 +95,14 @@ struct TileDesc {
 // Counters written by the tile classification.
 // CNT_MM_POS: region positions (padded to 16) of the interior tiles, the column count of
 // the matrix-core search's products.
+// CNT_EDGE_MM: tiles with a few frames of invalid lookups, searched on the matrix cores
+// (list 3).
 enum { CNT_FAST = 0, CNT_EDGE = 1, CNT_GENERIC = 2, CNT_NONE = 3, CNT_GOOD_FAST = 4,
-       CNT_GOOD_EDGE = 5, CNT_GOOD_GENERIC = 6, CNT_MM_POS = 7, CNT_N = 8 };
+       CNT_GOOD_EDGE = 5, CNT_GOOD_GENERIC = 6, CNT_MM_POS = 7, CNT_EDGE_MM = 8,
+       CNT_GOOD_EDGE_MM = 9, CNT_MM_POS_EDGE = 10, CNT_N = 12 };
+constexpr int LIST_EDGE_MM = 3;
+// Frames with invalid lookups that a matrix-core edge tile may have.
+constexpr int MM_SLOW_MAX = 64;
 
 // Round up to a multiple of a such that the row pitch is 8 (mod 32) floats: an 8-wide
 // row of lanes then spans distinct LDS banks in each half-wave.

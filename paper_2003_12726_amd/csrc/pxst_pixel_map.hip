@@ -52,6 +52,7 @@ struct PmArgs {
     const int* fscale;  // fixed-point exponent of the reference
     int kblocks;
     int mm_lds_a;       // the tile's packed frames are staged in LDS
+    int mm_on;          // interior and edge tiles go to the matrix-core search
 };
 
 __global__ void k_zero_counters(int* c) {
@@ -105,22 +106,28 @@ __device__ void classify_item(const PmArgs& a, int tile) {
     } else {
         // FAST needs, for every frame, all corners of the staged region valid
         const int T0 = mn0 - a.rx, T1 = mn1 - a.ry;
-        bool ok = true;
+        int nbad = 0;   // frames whose staged region holds an invalid lookup
         for (int n = lane; n < a.N; n += 64) {
             const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
             const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
             const int r0 = T0 - s0.e, c0r = T1 - s1.e;
-            ok = ok && rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + (int)rh, c0r, c0r + (int)rw);
+            nbad += rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + (int)rh, c0r, c0r + (int)rw) ? 0 : 1;
         }
-        const int bad = wave_sum<int>(ok ? 0 : 1);
-        cls = (bad == 0 && rh * rw <= a.fast_cap) ? CNT_FAST : CNT_EDGE;
+        const int bad = wave_sum<int>(nbad);
+        if (a.mm_on)
+            cls = bad == 0 ? CNT_FAST : (bad <= MM_SLOW_MAX && bad < a.N ? CNT_EDGE_MM : CNT_EDGE);
+        else
+            cls = (bad == 0 && rh * rw <= a.fast_cap) ? CNT_FAST : CNT_EDGE;
         if (lane == 0) a.tiles[tile] = TileDesc{mn0, mn1, (int)rh, (int)rw};
     }
     if (lane == 0) {
+        const int list = cls == CNT_EDGE_MM ? LIST_EDGE_MM : cls;
         const int slot = atomicAdd(&a.counters[cls], 1);
-        a.lists[cls * a.ntiles + slot] = tile;
-        atomicAdd(&a.counters[CNT_GOOD_FAST + cls], ngood);
+        a.lists[list * a.ntiles + slot] = tile;
+        atomicAdd(&a.counters[cls == CNT_EDGE_MM ? CNT_GOOD_EDGE_MM : CNT_GOOD_FAST + cls], ngood);
         if (cls == CNT_FAST) atomicAdd(&a.counters[CNT_MM_POS], (int)((rh * rw + 15) / 16 * 16));
+        if (cls == CNT_EDGE_MM)
+            atomicAdd(&a.counters[CNT_MM_POS_EDGE], (int)((rh * rw + 15) / 16 * 16));
     }
 }
 
@@ -683,15 +690,19 @@ constexpr int MM_THREADS = MM_WAVES * 64;
 
 typedef int mm_v4i __attribute__((ext_vector_type(4)));
 
-// Per-pixel coefficients of the normalised error: with S the combined int8 products of
-// the pixel and a position, g_q and C_q the position's column terms,
-//     E = al + be (S + g_q) + ga C_q;
-// when var = 0 the same coefficients give the error itself.
+// Per-pixel coefficients of the error.  With S the combined int8 products of the pixel
+// and a position, g_q and C_q the position's column terms, interior tiles use
+//     E = al + be (S + g_q) + ga C_q            (the normalised error;
+// when var = 0 the same coefficients give the error itself), edge tiles
+//     err_fast = al + be (S + g_q) + ga C_q     (over the frames without invalid
+// lookups, whose variance is vf) and add the remaining frames term by term.
 struct MmPix {
-    double al, be, ga;
+    double al, be, ga, vf;
+    float W;
     int dc0, dc1;  // window centre relative to the tile's smallest centre
     int zvar;      // var == 0
     int good;
+    int pad;
 };
 
 // Frames of a tile as the A operand (rows = the tile's 64 pixels in four groups of 16,
@@ -771,18 +782,35 @@ __device__ inline mm_v4i mm_as_v4i(uint4 v) {
 __host__ __device__ inline int mm_frames_padded(int n_frames) {
     return (n_frames + MM_KB - 1) / MM_KB * MM_KB;
 }
-__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a) {
+// Extra LDS of edge tiles: slow-frame flags [NP] | slow list [MAX] | slow shifts int4
+// [MAX] | counts I [MAX][64] | nslow, first fast frame.
+__host__ __device__ inline size_t mm_edge_bytes(int np) {
+    return (size_t)np * 4 + MM_SLOW_MAX * 4 + MM_SLOW_MAX * 16 + MM_SLOW_MAX * 64 * 4 + 16;
+}
+__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a, bool edge) {
     const size_t np = (size_t)mm_frames_padded(n_frames);
     const size_t e = ((size_t)64 * nc + 3) / 4 * 4 * sizeof(float);
     const size_t apk = stage_a ? np / MM_KB * MM_PACK_BYTES : 0;
-    return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + apk;
+    return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + (edge ? mm_edge_bytes((int)np) : 0) + apk;
 }
 
-template <bool LDSA>
+// Interior tiles (bit 0) and edge tiles (bit 1) go to the matrix-core search when its
+// LDS fits; the tile's packed frames are staged in LDS when they fit beside the rest.
+constexpr size_t MM_LDS_MAX = 160 * 1024;
+int mm_flags(int nx, int ny, int n_frames) {
+    return (mm_lds_bytes(nx * ny, n_frames, false, false) <= MM_LDS_MAX ? 1 : 0) |
+           (mm_lds_bytes(nx * ny, n_frames, false, true) <= MM_LDS_MAX ? 2 : 0);
+}
+bool mm_stage_a(int nx, int ny, int n_frames, bool edge) {
+    return mm_lds_bytes(nx * ny, n_frames, true, edge) <= MM_LDS_MAX;
+}
+
+template <bool LDSA, bool EDGE>
 __device__ void pm_mma_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
-    if (slot >= a.counters[CNT_FAST]) return;
-    const int tile = a.lists[CNT_FAST * a.ntiles + slot];
+    const int cnt = EDGE ? CNT_EDGE_MM : CNT_FAST;
+    if (slot >= a.counters[cnt]) return;
+    const int tile = a.lists[(EDGE ? LIST_EDGE_MM : CNT_FAST) * a.ntiles + slot];
     const TileDesc td = a.tiles[tile];
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int RW = td.rw, Q = td.rh * td.rw, NT = (Q + 15) >> 4;
@@ -796,20 +824,76 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     float4* fw = (float4*)(smem + ((size_t)64 * NC + 3) / 4 * 4);
     unsigned* fgo4 = (unsigned*)(fw + NP);   // 4 * (e0 Rf + e1), modulo 2^32
     MmPix* pp = (MmPix*)(fgo4 + NP);
-    uint4* apk = (uint4*)(pp + 64);          // the tile's packed frames, when staged
+    char* ext = (char*)(pp + 64);
+    int* sflag = (int*)ext;                                    // edge tiles only
+    int* slist = sflag + NP;
+    int4* sinfo = (int4*)(slist + MM_SLOW_MAX);
+    float* sI = (float*)(sinfo + MM_SLOW_MAX);                 // [MAX][64]
+    int* smisc = (int*)(sI + MM_SLOW_MAX * 64);
+    uint4* apk = (uint4*)(EDGE ? ext + mm_edge_bytes(NP) : ext);   // packed frames, if staged
+
+    // edge tiles: the frames whose staged region holds an invalid lookup (the test of
+    // the classification), in frame order, and the first frame without one
+    int nslow = 0, nref = 0;
+    if (EDGE) {
+        for (int n = tid; n < N; n += MM_THREADS) {
+            const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+            const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+            const int r0 = T0 - s0.e, c0r = T1 - s1.e;
+            sflag[n] = rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + td.rh, c0r, c0r + td.rw) ? 0 : 1;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            int count = 0, first = -1;
+            for (int b0 = 0; b0 < N; b0 += 64) {
+                const int n = b0 + lane;
+                const int f = n < N ? sflag[n] : 0;
+                const unsigned long long m = __ballot(f);
+                const unsigned long long fm = __ballot(n < N && !f);
+                const int before = __popcll(m & ((1ull << lane) - 1ull));
+                if (f && count + before < MM_SLOW_MAX) slist[count + before] = n;
+                if (first < 0 && fm) first = b0 + __ffsll((long long)fm) - 1;
+                count += __popcll(m);
+            }
+            if (lane == 0) {
+                smisc[0] = min(count, MM_SLOW_MAX);
+                smisc[1] = first < 0 ? 0 : first;
+            }
+        }
+        __syncthreads();
+        nslow = smisc[0];
+        nref = smisc[1];
+    }
 
     // frame table: bilinear weights scaled by 2^F (exact: a power of two) and the
-    // reference offset of the frame's shift
+    // reference offset of the frame's shift; padding frames and (edge tiles) frames
+    // with invalid lookups get zero weights and the offset of a frame without any
     const float fs = ldexpf(1.f, *a.fscale);
     for (int n = tid; n < NP; n += MM_THREADS) {
-        const int nn = n < N ? n : 0;
+        const bool zero = n >= N || (EDGE && sflag[n]);
+        const int nn = zero ? nref : n;
         const AxisShift s0 = axis_shift(a.dx[2 * nn], a.o0);
         const AxisShift s1 = axis_shift(a.dx[2 * nn + 1], a.o1);
         fgo4[n] = 4u * (unsigned)(s0.e * Rf + s1.e);
         const float t0 = s0.t, t1 = s1.t;
-        fw[n] = n < N ? make_float4((1.f - t0) * (1.f - t1) * fs, (1.f - t0) * t1 * fs,
-                                    t0 * (1.f - t1) * fs, t0 * t1 * fs)
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        fw[n] = zero ? make_float4(0.f, 0.f, 0.f, 0.f)
+                     : make_float4((1.f - t0) * (1.f - t1) * fs, (1.f - t0) * t1 * fs,
+                                   t0 * (1.f - t1) * fs, t0 * t1 * fs);
+    }
+    if (EDGE) {
+        for (int e = tid; e < nslow * 64; e += MM_THREADS) {
+            const int k = e >> 6, p = e & 63;
+            const int n = slist[k];
+            if (p == 0) {
+                const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+                const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+                sinfo[k] = make_int4(s0.e, s1.e, __float_as_int(s0.t), __float_as_int(s1.t));
+            }
+            const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+            const bool good = i < a.H && j < a.W && a.mask[(size_t)i * a.W + j] != 0;
+            const size_t pix = good ? (size_t)i * a.W + j : 0;
+            sI[e] = good ? (float)a.frames[(size_t)n * HW + pix] : 0.f;
+        }
     }
     const int F = *a.fscale;
     const double inv = ldexp(1.0, -F), inv2 = inv * inv;
@@ -821,16 +905,29 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         MmPix q;
         q.good = inb && a.mask[pix] != 0;
         q.dc0 = q.dc1 = -(1 << 28);
-        q.al = q.be = q.ga = 0.0;
+        q.al = q.be = q.ga = q.vf = 0.0;
+        q.W = 0.f;
         q.zvar = 0;
+        q.pad = 0;
         if (q.good) {
             q.dc0 = window_centre(a.u_in[pix]) - td.cmin0;
             q.dc1 = window_centre(a.u_in[HW + pix]) - td.cmin1;
             const double Wd = (double)a.white[pix];
+            q.W = a.white[pix];
             const double* st = a.pstat + ((size_t)tile * 64 + p) * 4;
             // err = A - 2 W inv (S + g_q + Ib) + W^2 inv^2 C_q
-            const double A = st[0], Ib = st[1], var = st[2];
-            const double s = var > 0.0 ? 1.0 / var : 1.0;
+            double A = st[0], var = st[2];
+            const double Ib = st[1];
+            if (EDGE) {
+                // sums over the frames without invalid lookups
+                for (int k = 0; k < nslow; ++k) {
+                    const double I = (double)a.frames[(size_t)slist[k] * HW + pix];
+                    A -= I * I;
+                    var -= (I - Wd) * (I - Wd);
+                }
+                q.vf = var;
+            }
+            const double s = (EDGE || var <= 0.0) ? 1.0 : 1.0 / var;
             q.zvar = var > 0.0 ? 0 : 1;
             q.be = -2.0 * Wd * inv * s;
             q.ga = Wd * Wd * inv2 * s;
@@ -867,7 +964,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             for (int s = 0; s < 4; ++s) acc[m][s] = mm_v4i{0, 0, 0, 0};
         double GU = 0.0, CS = 0.0;
         for (int kb = 0; kb < KB; ++kb) {
-            // B operand: 16 frames of this lane's position, three biased bytes each
+            // B operand: 16 frames of this lane's position, three biased bytes each;
             // branch-free so that the 32 loads of the 16 frames are in flight together
             unsigned B0[4], B1[4], B2[4];
             unsigned gsum = 0;
@@ -925,20 +1022,77 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         CS += __shfl_xor(CS, 16, 64);
         CS += __shfl_xor(CS, 32, 64);
         const double gq = 128.0 * 257.0 * GU - kconst;
+        if (!EDGE) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < 4; ++m) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = m * 16 + 4 * g + i;
-                const MmPix P = pp[p];
-                const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
-                                 65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
-                v = v > 0.0 ? v : 0.0;
-                const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
-                const int kx = r - P.dc0, ky = cc - P.dc1;
-                if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
-                    ebuf[(size_t)p * NC + kx * NY + ky] = E;
+                for (int i = 0; i < 4; ++i) {
+                    const int p = m * 16 + 4 * g + i;
+                    const MmPix P = pp[p];
+                    const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                                     65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
+                    double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                    v = v > 0.0 ? v : 0.0;
+                    const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
+                    const int kx = r - P.dc0, ky = cc - P.dc1;
+                    if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
+                        ebuf[(size_t)p * NC + kx * NY + ky] = E;
+                }
+            }
+        } else {
+            // frames without invalid lookups from the products (the cancellation happens
+            // in FP64; the resulting error is kept in FP32 like the terms added to it);
+            // the others term by term
+            float ef[16], es[16], vs[16], Wl[16];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = m * 4 + i, p = m * 16 + 4 * g + i;
+                    const MmPix& P = pp[p];
+                    const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                                     65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
+                    ef[e] = (float)fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                    es[e] = 0.f;
+                    vs[e] = 0.f;
+                    Wl[e] = P.W;
+                }
+            }
+            int ns = 0;
+            for (int k = 0; k < nslow; ++k) {
+                const int4 si = sinfo[k];
+                const float gk = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - si.x, T1 + cc - si.y,
+                                                 __int_as_float(si.z), __int_as_float(si.w));
+                if (valid(gk)) {
+                    ++ns;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int e = m * 4 + i, p = m * 16 + 4 * g + i;
+                            const float I = sI[k * 64 + p];
+                            const float rr = fmaf(-Wl[e], gk, I);
+                            es[e] = fmaf(rr, rr, es[e]);
+                            const float v = I - Wl[e];
+                            vs[e] = fmaf(v, v, vs[e]);
+                        }
+                    }
+                }
+            }
+            const int nv = (N - nslow) + ns;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int e = m * 4 + i, p = m * 16 + 4 * g + i;
+                    const int kx = r - pp[p].dc0, ky = cc - pp[p].dc1;
+                    if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY) {
+                        float err = ef[e] + es[e];
+                        err = err > 0.f ? err : 0.f;
+                        const float var = (float)pp[p].vf + vs[e];
+                        ebuf[(size_t)p * NC + kx * NY + ky] = normalised_error(err, var, nv);
+                    }
+                }
             }
         }
     }
@@ -1026,10 +1180,14 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
 
 PXST_WRAP(k_classify, 64, classify_item)
 PXST_WRAP(k_pm_generic, 256, pm_generic_item)
-__device__ void pm_mma_item_lds(const PmArgs& a, int slot) { pm_mma_item<true>(a, slot); }
-__device__ void pm_mma_item_glb(const PmArgs& a, int slot) { pm_mma_item<false>(a, slot); }
-PXST_WRAP(k_pm_mma_lds, MM_THREADS, pm_mma_item_lds)
-PXST_WRAP(k_pm_mma_glb, MM_THREADS, pm_mma_item_glb)
+__device__ void pm_mma_fast_lds(const PmArgs& a, int slot) { pm_mma_item<true, false>(a, slot); }
+__device__ void pm_mma_fast_glb(const PmArgs& a, int slot) { pm_mma_item<false, false>(a, slot); }
+__device__ void pm_mma_edge_lds(const PmArgs& a, int slot) { pm_mma_item<true, true>(a, slot); }
+__device__ void pm_mma_edge_glb(const PmArgs& a, int slot) { pm_mma_item<false, true>(a, slot); }
+PXST_WRAP(k_pm_mma_lds, MM_THREADS, pm_mma_fast_lds)
+PXST_WRAP(k_pm_mma_glb, MM_THREADS, pm_mma_fast_glb)
+PXST_WRAP(k_pm_mma_edge_lds, MM_THREADS, pm_mma_edge_lds)
+PXST_WRAP(k_pm_mma_edge_glb, MM_THREADS, pm_mma_edge_glb)
 
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
@@ -1184,17 +1342,31 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     a.pstat = (const double*)(ws + L.pstat);
     a.fscale = (const int*)(ws + L.fscale);
     a.kblocks = L.kblocks;
+    a.mm_on = mm_flags(a.NX, a.NY, g.N);
     return a;
 }
 
-// Interior tiles go to the matrix-core search when its LDS fits.
-constexpr size_t MM_LDS_MAX = 160 * 1024;
-bool mm_fits(int nx, int ny, int n_frames) {
-    return mm_lds_bytes(nx * ny, n_frames, false) <= MM_LDS_MAX;
-}
-// The tile's packed frames are staged in LDS when they fit beside the rest.
-bool mm_stage_a(int nx, int ny, int n_frames) {
-    return mm_lds_bytes(nx * ny, n_frames, true) <= MM_LDS_MAX;
+// One launch of the matrix-core search (interior or edge tiles) for one job (jobs ==
+// nullptr) or a batch of jobs sharing the window (nx, ny) with at most max_n frames.
+int launch_mma(const PmArgs& a, const PmArgs* jobs, const int* off, int njobs, int grid, int max_n,
+               bool edge, hipStream_t s) {
+    const bool stage = mm_stage_a(a.NX, a.NY, max_n, edge);
+    const size_t sh = mm_lds_bytes(a.NX * a.NY, max_n, stage, edge);
+    if (jobs == nullptr) {
+        PmArgs b = a;
+        b.mm_lds_a = stage ? 1 : 0;
+        const PmKernel kern = edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
+                                   : (stage ? k_pm_mma_lds : k_pm_mma_glb);
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, b);
+    } else {
+        const PmBatchKernel kern = edge ? (stage ? k_pm_mma_edge_lds_batch : k_pm_mma_edge_glb_batch)
+                                        : (stage ? k_pm_mma_lds_batch : k_pm_mma_glb_batch);
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, jobs, off, njobs);
+    }
+    return check_hip(hipGetLastError(), edge ? "pixel-map search (edge tiles, matrix cores)"
+                                             : "pixel-map search (interior tiles, matrix cores)");
 }
 
 // Launch shapes of the fast and edge kernels for a window (same for every job with
@@ -1240,21 +1412,15 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     if (rc) return rc;
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
-    if (mm_fits(a.NX, a.NY, g.N)) {
-        PmArgs b = a;
-        b.mm_lds_a = mm_stage_a(a.NX, a.NY, g.N) ? 1 : 0;
-        const size_t sh = mm_lds_bytes(a.NX * a.NY, g.N, b.mm_lds_a != 0);
-        const PmKernel kern = b.mm_lds_a ? k_pm_mma_lds : k_pm_mma_glb;
-        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (a.mm_on & 1) {
         profile_begin("pm_fast", s);
         profile_begin("pm_fast_int8_ops", s);
-        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(MM_THREADS), sh, s, b);
+        rc = launch_mma(a, nullptr, nullptr, 0, a.ntiles, g.N, false, s);
         // int8 operations issued on the matrix cores: 2 per multiply-add, 64 pixels x
         // positions x padded frames x 6 byte pairs
         profile_end("pm_fast_int8_ops", s, 0, a.counters + CNT_MM_POS,
                     2LL * 64 * 6 * (long long)mm_frames_padded(g.N));
         profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
-        rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles, matrix cores)");
         if (rc) return rc;
     } else {
         const size_t sh = lds_bytes(pl.lf, g.N);
@@ -1263,6 +1429,12 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
         hipLaunchKernelGGL(pl.fs.fn, dim3(a.ntiles), dim3(pl.lf.waves * 64), sh, s, pl.fast_args(a));
         profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles)");
+        if (rc) return rc;
+    }
+    if (a.mm_on & 2) {
+        profile_begin("pm_edge_mma", s);
+        rc = launch_mma(a, nullptr, nullptr, 0, a.ntiles, g.N, true, s);
+        profile_end("pm_edge_mma", s, 0, a.counters + CNT_GOOD_EDGE_MM, evals_per_good_px);
         if (rc) return rc;
     }
     {
@@ -1320,13 +1492,16 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
     }
     int rc = check_hip(hipGetLastError(), "batched pixel-map classification");
     if (rc) return rc;
-    // groups of jobs with the same window
+    // groups of jobs with the same window and the same kernel choice (each job's choice
+    // depends on its own sizes only, so a job is classified and searched the same way
+    // alone and in a batch)
     std::vector<int> done(n, 0);
     for (int j0 = 0; j0 < n; ++j0) {
         if (done[j0]) continue;
         std::vector<int> grp;
         for (int j = j0; j < n; ++j)
-            if (!done[j] && base[j].NX == base[j0].NX && base[j].NY == base[j0].NY) {
+            if (!done[j] && base[j].NX == base[j0].NX && base[j].NY == base[j0].NY &&
+                base[j].mm_on == base[j0].mm_on) {
                 grp.push_back(j);
                 done[j] = 1;
             }
@@ -1343,19 +1518,13 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
         const int grid = std::min(off[m], persistent_groups);
         int max_n = 1;
         for (int q = 0; q < m; ++q) max_n = std::max(max_n, base[grp[q]].N);
-        if (mm_fits(base[j0].NX, base[j0].NY, max_n)) {
-            const int stage_a = mm_stage_a(base[j0].NX, base[j0].NY, max_n) ? 1 : 0;
-            std::vector<PmArgs> ma(ga);
-            for (auto& x : ma) x.mm_lds_a = stage_a;
-            const BatchUpload up = stage_table(ar, ma.data(), m * sizeof(PmArgs), off);
+        if (base[j0].mm_on & 1) {
+            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
-            const size_t sh = mm_lds_bytes(base[j0].NX * base[j0].NY, max_n, stage_a != 0);
-            const PmBatchKernel kern = stage_a ? k_pm_mma_lds_batch : k_pm_mma_glb_batch;
-            hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
             profile_begin("pm_fast", s);
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, (const PmArgs*)up.args_dev,
-                               up.off_dev, m);
+            rc = launch_mma(base[j0], (const PmArgs*)up.args_dev, up.off_dev, m, grid, max_n, false, s);
             profile_end("pm_fast", s, 0, nullptr, 0);
+            if (rc) return rc;
         } else {
             const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
@@ -1366,6 +1535,14 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
             hipLaunchKernelGGL(pl.fs.batch, dim3(grid), dim3(pl.lf.waves * 64), sh, s,
                                (const PmArgs*)up.args_dev, up.off_dev, m);
             profile_end("pm_fast", s, 0, nullptr, 0);
+        }
+        if (base[j0].mm_on & 2) {
+            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
+            if (ar.overflow) break;
+            profile_begin("pm_edge_mma", s);
+            rc = launch_mma(base[j0], (const PmArgs*)up.args_dev, up.off_dev, m, grid, max_n, true, s);
+            profile_end("pm_edge_mma", s, 0, nullptr, 0);
+            if (rc) return rc;
         }
         {
             const BatchUpload up = stage_table(ar, ea.data(), m * sizeof(PmArgs), off);
