@@ -47,13 +47,14 @@ struct GridInfo {
     int bmin0, bmin1, bmax0, bmax1;   // bounding box of floor(u) - origin over good pixels
     int g0, g1;                       // cell-grid origin
     int n_good;
-    int pad;
+    float wmax;                       // max |W| over good pixels (fixed-point scale of the splat)
     long long sum0, sum1;             // sums of the cell coordinates (for a centred origin)
 };
 
 // Per-block partial of the bounding-box reduction.
 struct GridPart {
-    int bmin0, bmin1, bmax0, bmax1, n_good, pad0;
+    int bmin0, bmin1, bmax0, bmax1, n_good;
+    float wmax;
     long long sum0, sum1;
 };
 constexpr int GRID_THREADS = 256;

@@ -1,15 +1,22 @@
-// Reference update (Sec. 2.2.1 with the bilinear splat of Sec. 4) as a gather.
+// Reference update (Sec. 2.2.1 with the bilinear splat of Sec. 4) and the
+// reference-plane error (Sec. 2.2.4).
 //
-// The splat adds every good pixel of every frame at u - dx_n - origin.  Instead of
-// scattering with atomics, the pixels are binned by floor(u) - origin into a cell
-// grid (a stable radix sort of cell keys gives each cell its pixels in index order),
-// and every reference pixel p then gathers, frame by frame, from the 3x3 cells around
-// p + floor(dx_n): only those can put a bilinear corner on p.  The frames are copied
-// into sorted-entry order first, so an entry's frame value is read at the entry's own
-// index.  The frames are split into chunks (grid z) to keep enough gathers in flight;
-// per-frame partials are added with compensated float32 summation and float64 weight
-// sums, and the chunks are combined in chunk order, so every sum has a fixed order and
-// the result is bitwise reproducible.
+// Both start from an inverted map: the good pixels are binned by floor(u) - origin
+// into a cell grid (a stable radix sort of cell keys gives each cell its pixels in
+// index order, so a row of cells is a contiguous run of sorted entries), and the
+// frames are copied into sorted-entry order so that an entry's frame value is read at
+// the entry's own index.
+//
+// Reference update: a work-group owns a tile of reference pixels and, frame by frame,
+// walks the rows of cells whose points can put a bilinear corner on the tile, adding
+// the corners' value and weight into LDS bins with terms rounded to a power-of-two
+// quantum, so that the FP64 sums are exact and independent of the order of the atomic
+// additions (see k_ref_splat).
+//
+// Reference-plane error: every reference pixel p gathers, frame by frame, from the 3x3
+// cells around p + floor(dx_n) (only those can put a corner on p), with compensated
+// float32 sums over frames and float64 weight sums; frame chunks (grid z) are combined
+// in chunk order, so every sum has a fixed order.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "pxst_device.hpp"
@@ -31,7 +38,8 @@ __device__ inline int cell_coord(float u, int o) {
 }
 
 __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restrict__ u,
-                                                            const uint8_t* __restrict__ mask, int HW,
+                                                            const uint8_t* __restrict__ mask,
+                                                            const float* __restrict__ white, int HW,
                                                             int o0, int o1, GridPart* __restrict__ part) {
     __shared__ GridPart wp[GRID_THREADS / 64];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,7 +57,10 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restr
     g.sum0 = wave_sum<long long>(good ? (long long)b0 : 0);
     g.sum1 = wave_sum<long long>(good ? (long long)b1 : 0);
     g.n_good = wave_sum<int>(good ? 1 : 0);
-    g.pad0 = 0;
+    float wm = good ? fabsf(white[k]) : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o, 64));
+    g.wmax = wm;
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) wp[w] = g;
     __syncthreads();
@@ -63,6 +74,7 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restr
             t.sum0 += wp[q].sum0;
             t.sum1 += wp[q].sum1;
             t.n_good += wp[q].n_good;
+            t.wmax = fmaxf(t.wmax, wp[q].wmax);
         }
         part[blockIdx.x] = t;
     }
@@ -80,9 +92,10 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __
     t.bmax0 = t.bmax1 = INT_MIN;
     t.sum0 = t.sum1 = 0;
     t.n_good = 0;
-    t.pad0 = 0;
+    t.wmax = 0.f;
     for (int q = threadIdx.x; q < nparts; q += GRID_THREADS) {
         const GridPart p = part[q];
+        t.wmax = fmaxf(t.wmax, p.wmax);
         t.bmin0 = min(t.bmin0, p.bmin0);
         t.bmax0 = max(t.bmax0, p.bmax0);
         t.bmin1 = min(t.bmin1, p.bmin1);
@@ -102,7 +115,9 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __
         t.sum0 += wp[q].sum0;
         t.sum1 += wp[q].sum1;
         t.n_good += wp[q].n_good;
+        t.wmax = fmaxf(t.wmax, wp[q].wmax);
     }
+    gi->wmax = t.wmax;
     gi->bmin0 = t.bmin0;
     gi->bmin1 = t.bmin1;
     gi->bmax0 = t.bmax0;
@@ -419,6 +434,160 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
     if (threadIdx.x == 0) sat[c + 1] = 0;
 }
 
+// ------------------------------------------------------------ reference update (splat)
+//
+// The reference update proper: every work-group owns a tile of RS_TR x RS_TC reference
+// pixels and, frame by frame, walks the cells of the inverted map whose points can put
+// a bilinear corner on the tile (rows of cells are contiguous runs of sorted entries,
+// one lane per entry), adding each corner's value M W I w and weight M W^2 w into LDS
+// bins.  The terms are rounded to multiples of a power-of-two quantum chosen from
+// max |W| so that every term is an integer below 2^30 in quantum units; sums of up to
+// 2^23 such terms are exact in FP64, so the LDS atomic additions give the same result
+// in any order (bitwise reproducible), and the rounding is about 1e-9 of the largest
+// term.  Frame chunks (grid z) write exact partial sums that a second pass adds.
+constexpr int RS_TR = 16, RS_TC = 62, RS_THREADS = 256;
+
+struct SplatArgs {
+    const uint16_t* fsort;
+    const float* dx;
+    const unsigned* cstart;
+    const float4* pdata;
+    const int2* bsort;
+    const GridInfo* gi;
+    int N, HW, Rs, Rf, GH, GW, nchunks;
+    double2* part;     // [nchunks][Rs * Rf] quantised (numerator, weight) sums
+    float* ref;
+    double* wsum;
+    float* refv;
+};
+
+// Corners of a point at (b - s) + t, t in (-1, 1), along one axis: plo with weight wlo
+// and plo + 1 with weight whi.
+__device__ inline void splat_axis(int b, int s, float t, int& plo, float& wlo, float& whi) {
+    if (t >= 0.f) {
+        plo = b - s;
+        wlo = 1.f - t;
+        whi = t;
+    } else {
+        plo = b - s - 1;
+        wlo = -t;
+        whi = 1.f + t;
+    }
+}
+
+// Quantum exponents: |W I| 2^fn <= 2^30 and W^2 2^fd <= 2^30 for every term.
+__device__ inline void splat_scales(float wmax, int& fn, int& fd) {
+    int e1 = 0, e2 = 0;
+    if (wmax > 0.f && isfinite(wmax)) {
+        frexp((double)wmax * 65535.0, &e1);
+        frexp((double)wmax * (double)wmax, &e2);
+    }
+    fn = 30 - e1;
+    fd = 30 - e2;
+}
+
+__device__ inline void splat_entry(const SplatArgs& a, unsigned e, int n, int s0, int s1, float fd0,
+                                   float fd1, int P0, int P1, double sn, double sd, double* bn,
+                                   double* bd) {
+    const float4 pd = a.pdata[e];
+    const int2 b = a.bsort[e];
+    const double I = (double)a.fsort[(size_t)n * a.HW + e];
+    int p0, p1;
+    float wl0, wh0, wl1, wh1;
+    splat_axis(b.x, s0, pd.x - fd0, p0, wl0, wh0);
+    splat_axis(b.y, s1, pd.y - fd1, p1, wl1, wh1);
+    const double Wd = (double)pd.z;
+    const double vn = Wd * I * sn, vd = Wd * Wd * sd;
+    const int i0 = p0 - P0, j0 = p1 - P1;
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj) {
+            const int i = i0 + di, j = j0 + dj;
+            const float w = (di ? wh0 : wl0) * (dj ? wh1 : wl1);
+            if ((unsigned)i < (unsigned)RS_TR && (unsigned)j < (unsigned)RS_TC && w != 0.f) {
+                atomicAdd(&bn[i * RS_TC + j], rint((double)w * vn));
+                atomicAdd(&bd[i * RS_TC + j], rint((double)w * vd));
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
+    __shared__ double bn[RS_TR * RS_TC], bd[RS_TR * RS_TC];
+    const int P1 = blockIdx.x * RS_TC, P0 = blockIdx.y * RS_TR;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < RS_TR * RS_TC; i += RS_THREADS) {
+        bn[i] = 0.0;
+        bd[i] = 0.0;
+    }
+    const GridInfo gi = *a.gi;
+    int fn, fd;
+    splat_scales(gi.wmax, fn, fd);
+    const double sn = ldexp(1.0, fn), sd = ldexp(1.0, fd);
+    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
+    const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
+    const int F = (a.N + a.nchunks - 1) / a.nchunks;
+    const int n_begin = blockIdx.z * F, n_end = min(a.N, n_begin + F);
+    __syncthreads();
+    for (int n = n_begin; n < n_end; ++n) {
+        const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+        const float fs0 = floorf(d0), fs1 = floorf(d1);
+        const float fd0 = d0 - fs0, fd1 = d1 - fs1;
+        const int s0 = (int)fs0, s1 = (int)fs1;
+        // cells whose points can reach the tile: rows P0 - 1 + s0 .. P0 + RS_TR + s0
+        const int r_lo = max(P0 - 1 + s0 - gi.g0, 0), r_hi = min(P0 + RS_TR + s0 - gi.g0, a.GH - 1);
+        const int c_lo = max(P1 - 1 + s1 - gi.g1, 0), c_hi = min(P1 + RS_TC + s1 - gi.g1, a.GW - 1);
+        if (c_lo <= c_hi) {
+            for (int r = r_lo + wave; r <= r_hi; r += RS_THREADS / 64) {
+                const unsigned eb = a.cstart[(unsigned)r * a.GW + c_lo];
+                const unsigned ee = a.cstart[(unsigned)r * a.GW + c_hi + 1];
+                for (unsigned e = eb + lane; e < ee; e += 64)
+                    splat_entry(a, e, n, s0, s1, fd0, fd1, P0, P1, sn, sd, bn, bd);
+            }
+        }
+        // good pixels outside the cell grid (none for a sensible map)
+        for (unsigned e = ov_begin + tid; e < ov_end; e += RS_THREADS)
+            splat_entry(a, e, n, s0, s1, fd0, fd1, P0, P1, sn, sd, bn, bd);
+    }
+    __syncthreads();
+    const size_t RR = (size_t)a.Rs * a.Rf;
+    for (int i = tid; i < RS_TR * RS_TC; i += RS_THREADS) {
+        const int p0 = P0 + i / RS_TC, p1 = P1 + i % RS_TC;
+        if (p0 >= a.Rs || p1 >= a.Rf) continue;
+        const size_t p = (size_t)p0 * a.Rf + p1;
+        if (a.nchunks > 1) {
+            a.part[(size_t)blockIdx.z * RR + p] = make_double2(bn[i], bd[i]);
+        } else {
+            const double num = bn[i] * ldexp(1.0, -fn), den = bd[i] * ldexp(1.0, -fd);
+            const float val = den > 0.0 ? (float)(num / den) : 0.f;
+            a.ref[p] = val;
+            a.wsum[p] = den;
+            if (a.refv) a.refv[p] = den > 0.0 ? val : qnan();
+        }
+    }
+}
+
+// Adds the exact chunk partials and writes the reference.
+__global__ void k_ref_splat_combine(SplatArgs a) {
+    const size_t RR = (size_t)a.Rs * a.Rf;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= RR) return;
+    double sn = 0.0, sdd = 0.0;
+    for (int c = 0; c < a.nchunks; ++c) {
+        const double2 q = a.part[(size_t)c * RR + p];
+        sn += q.x;
+        sdd += q.y;
+    }
+    int fn, fd;
+    splat_scales(a.gi->wmax, fn, fd);
+    const double num = sn * ldexp(1.0, -fn), den = sdd * ldexp(1.0, -fd);
+    const float val = den > 0.0 ? (float)(num / den) : 0.f;
+    a.ref[p] = val;
+    a.wsum[p] = den;
+    if (a.refv) a.refv[p] = den > 0.0 ? val : qnan();
+}
+
 inline unsigned grid_blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -458,8 +627,8 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     unsigned* cstart = (unsigned*)(ws + L.cstart);
     const unsigned nparts = grid_blocks(HW, GRID_THREADS);
     GridPart* gpart = (GridPart*)(ws + L.gpart);
-    hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, HW, g.o0,
-                       g.o1, gpart);
+    hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, sc.white, HW,
+                       g.o0, g.o1, gpart);
     hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(GRID_THREADS), 0, s, gpart, (int)nparts, gi, GH,
                        GW);
     hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
@@ -527,14 +696,31 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
                             hipStream_t s) {
     int rc = build_inverse_map(g, sc, u, ws, L, s);
     if (rc) return rc;
-    GatherArgs a = gather_args(g, sc, u, dx, ws, L);
-    a.out = ref;
+    SplatArgs a{};
+    a.fsort = (const uint16_t*)(ws + L.fsort);
+    a.dx = dx;
+    a.cstart = (const unsigned*)(ws + L.cstart);
+    a.pdata = (const float4*)(ws + L.pdata);
+    a.bsort = (const int2*)(ws + L.bsort);
+    a.gi = (const GridInfo*)(ws + L.ginfo);
+    a.N = g.N;
+    a.HW = (int)g.HW();
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.GH = grid_h(g);
+    a.GW = grid_w(g);
+    a.nchunks = L.ref_chunks;
+    a.part = (double2*)(ws + L.rpart);
+    a.ref = ref;
     a.wsum = wsum;
-    a.refv_out = refv;
+    a.refv = refv;
+    const dim3 grid((g.Rf + RS_TC - 1) / RS_TC, (g.Rs + RS_TR - 1) / RS_TR, a.nchunks);
     profile_begin("ref_gather", s);
-    launch_gather(a, 0, g, s);
+    hipLaunchKernelGGL(k_ref_splat, grid, dim3(RS_THREADS), 0, s, a);
+    if (a.nchunks > 1)
+        hipLaunchKernelGGL(k_ref_splat_combine, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, a);
     profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
-    return check_hip(hipGetLastError(), "reference gather");
+    return check_hip(hipGetLastError(), "reference update");
 }
 
 int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
