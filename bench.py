@@ -83,7 +83,8 @@ def _per_dispatch(rows, counter):
 
 
 def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
-    """HBM bytes per k_pm_fast launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch),
+    """HBM bytes per launch of the interior-tile pixel-map search from FETCH_SIZE /
+    WRITE_SIZE (KiB per dispatch),
     each scaled by what the same counter reads for a device-to-device copy of known
     size in the same run (copy_mib MiB read and written)."""
     if copy_mib <= 0:
@@ -92,10 +93,10 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         disp = _per_dispatch(_counter_rows(d), counter)
-        pm = [v for k, g, v in disp if "k_pm_fast" in k]
+        pm = [v for k, g, v in disp if ("k_pm_mma_" in k and "edge" not in k) or "k_pm_fast" in k]
         cp = [v for k, g, v in disp if "copyBuffer" in k or "copy" in k.lower()]
         if not pm or not cp:
-            raise SystemExit(f"{counter}: k_pm_fast dispatches {len(pm)}, copy dispatches {len(cp)}")
+            raise SystemExit(f"{counter}: pixel-map dispatches {len(pm)}, copy dispatches {len(cp)}")
         copy_kib = max(cp)
         factor = (nb / 1024.0) / copy_kib
         kib = sum(pm) / len(pm)

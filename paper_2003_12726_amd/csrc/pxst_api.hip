@@ -169,6 +169,7 @@ Layout make_layout(const Geom& g, int tr_ct) {
     const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);
     L.tiles = take(ntiles * sizeof(TileDesc));
     L.lists = take(4 * ntiles * sizeof(int));
+    L.tinfo = take(ntiles * 4 * sizeof(int));
     L.counters = take(CNT_N * sizeof(int));
     L.kblocks = (g.N + MM_KB - 1) / MM_KB;
     L.ipk = take(ntiles * (size_t)L.kblocks * MM_PACK_BYTES);

@@ -4,8 +4,8 @@
 // once: every thread owns one pixel, forms eps = M (I - W g)^2 / sigma2 with the
 // masked bilinear lookup at u - dx_n - origin, accumulates the pixel error with
 // compensated float32 sums and adds the frame error in float64 per wave; the final
-// pass adds the per-block frame partials in block order and the frames in frame
-// order, so the totals are reproducible.
+// passes add the per-block frame partials and then the frames, each in a fixed order,
+// so the totals are reproducible.
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
 
@@ -109,19 +109,25 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
     }
 }
 
-__global__ void k_err_final(ErrArgs a) {
-    for (int n = threadIdx.x; n < a.N; n += blockDim.x) {
-        double acc = 0.0;
-        for (int b = 0; b < a.nblk; ++b) acc += a.part[(size_t)n * a.nblk + b];
+// One wave per frame: lanes add the block partials in lane-strided order, a fixed
+// butterfly combines the lanes.
+__global__ __launch_bounds__(64) void k_err_frames(ErrArgs a) {
+    const int n = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < a.nblk; b += 64) acc += a.part[(size_t)n * a.nblk + b];
+    acc = wave_sum<double>(acc);
+    if (threadIdx.x == 0) {
         a.frame_err[n] = acc;
         if (a.frame_out) a.frame_out[n] = acc;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int n = 0; n < a.N; ++n) t += a.frame_err[n];
-        *a.total = t;
-    }
+}
+
+// Total: the frame errors added by one wave in the same fixed order.
+__global__ __launch_bounds__(64) void k_err_total(ErrArgs a) {
+    double acc = 0.0;
+    for (int n = threadIdx.x; n < a.N; n += 64) acc += a.frame_err[n];
+    acc = wave_sum<double>(acc);
+    if (threadIdx.x == 0) *a.total = acc;
 }
 
 }  // namespace
@@ -166,7 +172,8 @@ int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const fl
     profile_begin("err_pixels", s);
     hipLaunchKernelGGL(k_err_pixels, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
     profile_end("err_pixels", s, (long long)g.HW() * g.N, nullptr, 0);
-    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_err_frames, dim3(g.N), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_err_total, dim3(1), dim3(64), 0, s, a);
     return check_hip(hipGetLastError(), "error evaluation");
 }
 

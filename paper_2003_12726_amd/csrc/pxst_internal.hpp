@@ -75,7 +75,7 @@ struct Layout {
     int ref_chunks;   // frame chunks of the reference gather
     size_t sort_tmp_bytes;
     // pixel map
-    size_t tiles, lists, counters;
+    size_t tiles, lists, counters, tinfo;
     size_t ipk, pstat;        // frames packed as int8 matrix operands; per-pixel frame sums
     size_t rowmax, fscale;    // per-row max |reference| and the fixed-point exponent
     int kblocks;              // frame K-blocks of the packed frames

@@ -37,8 +37,9 @@ struct PmArgs {
     float* err_out;
     int* arg_out;
     TileDesc* tiles;
-    int* lists;        // [3][ntiles]
+    int* lists;        // [4][ntiles]
     int* counters;
+    int4* tinfo;       // per tile: class, good pixels, padded region positions
     int N, H, W, Rs, Rf, o0, o1;
     int rx, ry, NX, NY, refine;
     int tiles_x, ntiles;
@@ -55,9 +56,6 @@ struct PmArgs {
     int mm_on;          // interior and edge tiles go to the matrix-core search
 };
 
-__global__ void k_zero_counters(int* c) {
-    if (threadIdx.x < CNT_N) c[threadIdx.x] = 0;
-}
 
 __device__ inline void write_unchanged(const PmArgs& a, size_t pix, size_t HW) {
     a.u_out[pix] = a.u_in[pix];
@@ -92,7 +90,7 @@ __device__ void classify_item(const PmArgs& a, int tile) {
     const int ngood = wave_sum<int>(good ? 1 : 0);
     if (ngood == 0) {
         if (inb) write_unchanged(a, pix, HW);
-        if (lane == 0) atomicAdd(&a.counters[CNT_NONE], 1);
+        if (lane == 0) a.tinfo[tile] = make_int4(CNT_NONE, 0, 0, 0);
         return;
     }
     const int mn0 = wave_min_i(good ? c0 : INT_MAX), mx0 = wave_max_i(good ? c0 : INT_MIN);
@@ -121,14 +119,87 @@ __device__ void classify_item(const PmArgs& a, int tile) {
         if (lane == 0) a.tiles[tile] = TileDesc{mn0, mn1, (int)rh, (int)rw};
     }
     if (lane == 0) {
-        const int list = cls == CNT_EDGE_MM ? LIST_EDGE_MM : cls;
-        const int slot = atomicAdd(&a.counters[cls], 1);
-        a.lists[list * a.ntiles + slot] = tile;
-        atomicAdd(&a.counters[cls == CNT_EDGE_MM ? CNT_GOOD_EDGE_MM : CNT_GOOD_FAST + cls], ngood);
-        if (cls == CNT_FAST) atomicAdd(&a.counters[CNT_MM_POS], (int)((rh * rw + 15) / 16 * 16));
-        if (cls == CNT_EDGE_MM)
-            atomicAdd(&a.counters[CNT_MM_POS_EDGE], (int)((rh * rw + 15) / 16 * 16));
+        const int pos = cls == CNT_GENERIC ? 0 : (int)((rh * rw + 15) / 16 * 16);
+        a.tinfo[tile] = make_int4(cls, ngood, pos, 0);
     }
+}
+
+// Work lists of the classes in tile order and the counters, by one work-group of 1024
+// threads per job (ordered compaction with wave ballots; no atomics).
+constexpr int COMPACT_THREADS = 1024;
+
+__device__ void compact_item(const PmArgs& a) {
+    __shared__ int wcnt[COMPACT_THREADS / 64][4];
+    __shared__ int base[4];
+    __shared__ int red[COMPACT_THREADS / 64][8];
+    const int cls_of[4] = {CNT_FAST, CNT_EDGE, CNT_GENERIC, CNT_EDGE_MM};
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    if (tid < 4) base[tid] = 0;
+    // per thread: good pixels of each list's tiles, positions of FAST / EDGE_MM, NONE
+    int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __syncthreads();
+    for (int t0 = 0; t0 < a.ntiles; t0 += COMPACT_THREADS) {
+        const int tile = t0 + tid;
+        int4 ti = make_int4(-1, 0, 0, 0);
+        if (tile < a.ntiles) ti = a.tinfo[tile];
+        int mine[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const unsigned long long m = __ballot(ti.x == cls_of[c]);
+            mine[c] = __popcll(m & lt);
+            if (lane == 0) wcnt[wave][c] = __popcll(m);
+        }
+        __syncthreads();
+        if (tid < 4) {
+            int run = base[tid];
+            for (int w = 0; w < COMPACT_THREADS / 64; ++w) {
+                const int v = wcnt[w][tid];
+                wcnt[w][tid] = run;
+                run += v;
+            }
+            base[tid] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (ti.x == cls_of[c]) {
+                a.lists[c * a.ntiles + wcnt[wave][c] + mine[c]] = tile;
+                acc[c] += ti.y;
+            }
+        }
+        if (ti.x == CNT_FAST) acc[4] += ti.z;
+        if (ti.x == CNT_EDGE_MM) acc[5] += ti.z;
+        if (ti.x == CNT_NONE) acc[6] += 1;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const int v = wave_sum<int>(acc[q]);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int tot[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < COMPACT_THREADS / 64; ++w)
+            for (int q = 0; q < 7; ++q) tot[q] += red[w][q];
+        a.counters[CNT_FAST] = base[0];
+        a.counters[CNT_EDGE] = base[1];
+        a.counters[CNT_GENERIC] = base[2];
+        a.counters[CNT_EDGE_MM] = base[3];
+        a.counters[CNT_GOOD_FAST] = tot[0];
+        a.counters[CNT_GOOD_EDGE] = tot[1];
+        a.counters[CNT_GOOD_GENERIC] = tot[2];
+        a.counters[CNT_GOOD_EDGE_MM] = tot[3];
+        a.counters[CNT_MM_POS] = tot[4];
+        a.counters[CNT_MM_POS_EDGE] = tot[5];
+        a.counters[CNT_NONE] = tot[6];
+    }
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_compact(const PmArgs a) { compact_item(a); }
+__global__ __launch_bounds__(COMPACT_THREADS) void k_compact_batch(const PmArgs* __restrict__ jobs) {
+    compact_item(jobs[blockIdx.x]);
 }
 
 // Cross-thread first minimum, 3x3 stencil and refinement of one pass's pixels; E
@@ -1318,6 +1389,7 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     a.tiles = (TileDesc*)(ws + L.tiles);
     a.lists = (int*)(ws + L.lists);
     a.counters = (int*)(ws + L.counters);
+    a.tinfo = (int4*)(ws + L.tinfo);
     a.N = g.N;
     a.H = g.H;
     a.W = g.W;
@@ -1406,8 +1478,8 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
                      float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
     const PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L);
     const PmPlan pl = pm_plan(a.NX, a.NY);
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a.counters);
     hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(COMPACT_THREADS), 0, s, a);
     int rc = check_hip(hipGetLastError(), "pixel-map classification");
     if (rc) return rc;
 
@@ -1475,16 +1547,18 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
         const PmJobDesc& d = jobs[j];
         base[j] = make_pm_args(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
                                nullptr, d.ws, *d.L);
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, base[j].counters);
     }
     // classification of all jobs in one launch
     {
         std::vector<int> off(n + 1, 0);
         for (int j = 0; j < n; ++j) off[j + 1] = off[j] + base[j].ntiles;
         const BatchUpload up = stage_table(ar, base.data(), n * sizeof(PmArgs), off);
-        if (!ar.overflow)
+        if (!ar.overflow) {
             hipLaunchKernelGGL(k_classify_batch, dim3(std::min(off[n], 256 * 16)), dim3(64), 0, s,
-                           (const PmArgs*)up.args_dev, up.off_dev, n);
+                               (const PmArgs*)up.args_dev, up.off_dev, n);
+            hipLaunchKernelGGL(k_compact_batch, dim3(n), dim3(COMPACT_THREADS), 0, s,
+                               (const PmArgs*)up.args_dev);
+        }
     }
     if (ar.overflow) {
         set_error("batch workspace too small");
