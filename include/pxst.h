@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PXST_ABI_VERSION 1
+#define PXST_ABI_VERSION 2
 
 #define PXST_OK 0
 #define PXST_EINVAL (-1)       /* null pointer, bad size or misaligned pointer        */
@@ -86,14 +86,29 @@ typedef struct {
     pxst_geom geom;
 } pxst_scan;
 
+/* Arithmetic of the reference update (Sec. 2.2.1), for the precision study:
+ *   PXST_REF_EXACT  every term rounded to a power-of-two quantum (about 1e-9 of the
+ *                   largest term) and summed exactly in float64; the reference is
+ *                   stored as float32.  The default.
+ *   PXST_REF_FP32   float32 numerator with compensated sums over frames, float64
+ *                   weight sums; stored as float32.
+ *   PXST_REF_BF16   as PXST_REF_EXACT, then every reference value rounded to the
+ *                   nearest bfloat16 (ties to even); all later lookups see bfloat16
+ *                   values (kept in float32 arrays). */
+#define PXST_REF_EXACT 0
+#define PXST_REF_FP32 1
+#define PXST_REF_BF16 2
+
 /* Main-loop options (Sec. 2.2): n_iter iterations of (i) reference update,
  * (ii) pixel-map update with window `pm`, (iii) translation update with window
- * `tr` when update_dx != 0, (iv) total error. */
+ * `tr` when update_dx != 0, (iv) total error; ref_mode selects the arithmetic of
+ * every reference update of the loop (PXST_REF_*). */
 typedef struct {
     int32_t n_iter;
     pxst_window pm;
     int32_t update_dx;
     pxst_window tr;
+    int32_t ref_mode;
 } pxst_solve_opts;
 
 /* Workspace bytes that every entry point below needs for this geometry and these
@@ -109,13 +124,17 @@ size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts);
  * u[:, i, j] - dx[n] - origin.  ref = 0 where wsum == 0.
  *   u    [2][H][W] float32 (in)      dx   [N][2] float32 (in)
  *   ref  [Rs][Rf]  float32 (out)     wsum [Rs][Rf] float64 (out)
- * The numerator is accumulated in float32 with compensated summation over frames,
- * the weight sums in float64.  Deterministic: the sums are gathered per reference
- * pixel in a fixed order, without atomics on floating-point values.
+ * Arithmetic PXST_REF_EXACT: numerator and weight terms rounded to power-of-two
+ * quanta and summed exactly in float64, so the result is the same bits whatever the
+ * order of the additions (deterministic).  pxst_update_reference_ex selects the
+ * arithmetic (PXST_REF_*; EINVAL for another value).
  */
 int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx,
                           float* ref, double* wsum, void* ws, size_t ws_bytes,
                           hipStream_t stream);
+int pxst_update_reference_ex(const pxst_scan* scan, const float* u, const float* dx,
+                             int32_t ref_mode, float* ref, double* wsum, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
 
 /*
  * Pixel-map update -- Sec. 2.2.2 (brute-force search, normalised error, argmin,
@@ -134,7 +153,10 @@ int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx
  *   linear candidate index (k_ss + r_ss) * (2 r_fs + 1) + (k_fs + r_fs), or -1
  *   (and err_min = +inf, u unchanged) for bad pixels and pixels with no finite
  *   candidate.
- * Bulk arithmetic is float32; the sums over frames are compensated.
+ * Lookups are interpolated in float32.  For windows whose per-tile error table fits
+ * the LDS (up to 21 x 21 candidates at 121 frames), the frame sums run as an exact
+ * int8 contraction of the counts with a fixed-point reference (rounding 2^-22 of the
+ * largest reference value) combined in float64; otherwise float32 compensated sums.
  */
 int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum,
                           const float* dx, const float* u_in, pxst_window window,

@@ -46,7 +46,7 @@ class CScan(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("pm", Window), ("update_dx", ctypes.c_int32),
-                ("tr", Window)]
+                ("tr", Window), ("ref_mode", ctypes.c_int32)]
 
 
 class CJob(ctypes.Structure):
@@ -55,7 +55,8 @@ class CJob(ctypes.Structure):
                 ("iter", ctypes.c_int32), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
-SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_pixel_map",
+SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_reference_ex",
+           "pxst_update_pixel_map",
            "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
            "pxst_batch_iterate", "pxst_profile_enable", "pxst_profile_read", "pxst_last_error",
            "pxst_abi_version")
@@ -76,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_workspace_bytes.argtypes = [P(Geom), P(SolveOpts)]
     lib.pxst_workspace_bytes.restype = sz
     lib.pxst_update_reference.argtypes = [P(CScan), vp, vp, vp, vp, vp, sz, vp]
+    lib.pxst_update_reference_ex.argtypes = [P(CScan), vp, vp, i32, vp, vp, vp, sz, vp]
     lib.pxst_update_pixel_map.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_update_translations.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_error.argtypes = [P(CScan), vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -88,7 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                       P(ctypes.c_int64)]
     lib.pxst_last_error.restype = ctypes.c_char_p
     lib.pxst_abi_version.restype = i32
-    for name in ("pxst_update_reference", "pxst_update_pixel_map", "pxst_update_translations",
+    for name in ("pxst_update_reference", "pxst_update_reference_ex", "pxst_update_pixel_map",
+                 "pxst_update_translations",
                  "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_profile_enable",
                  "pxst_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
@@ -130,10 +133,13 @@ def make_window(r_ss: int, r_fs: int, refine: bool = True) -> Window:
     return Window(int(r_ss), int(r_fs), int(bool(refine)))
 
 
+REF_MODES = {"exact": 0, "fp32": 1, "bf16": 2}   # PXST_REF_EXACT, _FP32, _BF16
+
+
 def make_opts(n_iter: int, pm: Sequence[int], refine: bool = True, update_dx: bool = False,
-              tr: Sequence[int] = (2, 2), tr_refine: bool = True) -> SolveOpts:
+              tr: Sequence[int] = (2, 2), tr_refine: bool = True, ref_mode: str = "exact") -> SolveOpts:
     return SolveOpts(int(n_iter), make_window(pm[0], pm[1], refine), int(bool(update_dx)),
-                     make_window(tr[0], tr[1], tr_refine))
+                     make_window(tr[0], tr[1], tr_refine), REF_MODES[ref_mode])
 
 
 @dataclasses.dataclass
@@ -171,12 +177,17 @@ def _ws(ws):
     return (_ptr(ws), int(ws.numel()) if ws is not None and not isinstance(ws, int) else 0)
 
 
-def update_reference(scan: Scan, u, dx, ref, wsum, ws, stream=None):
-    """Reference update (Sec. 2.2.1): writes ref [Rs, Rf] float32 and wsum float64."""
+def update_reference(scan: Scan, u, dx, ref, wsum, ws, stream=None, mode: str = "exact"):
+    """Reference update (Sec. 2.2.1): writes ref [Rs, Rf] float32 and wsum float64; mode
+    selects the arithmetic ("exact", "fp32", "bf16")."""
     lib = load_library()
     p, n = _ws(ws)
-    _check(lib.pxst_update_reference(ctypes.byref(scan.c()), _ptr(u), _ptr(dx), _ptr(ref), _ptr(wsum),
-                                     p, n, _stream(stream)))
+    if mode == "exact":
+        _check(lib.pxst_update_reference(ctypes.byref(scan.c()), _ptr(u), _ptr(dx), _ptr(ref),
+                                         _ptr(wsum), p, n, _stream(stream)))
+    else:
+        _check(lib.pxst_update_reference_ex(ctypes.byref(scan.c()), _ptr(u), _ptr(dx), REF_MODES[mode],
+                                            _ptr(ref), _ptr(wsum), p, n, _stream(stream)))
 
 
 def update_pixel_map(scan: Scan, ref, wsum, dx, u_in, window: Window, u_out, err_min=None,

@@ -294,17 +294,32 @@ size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts) 
     return make_layout(geom_of(*geom), tr_ct_of(opts)).total;
 }
 
-int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx, float* ref,
-                          double* wsum, void* ws, size_t ws_bytes, hipStream_t stream) {
+static int check_ref_mode(int mode) {
+    if (mode != PXST_REF_EXACT && mode != PXST_REF_FP32 && mode != PXST_REF_BF16) {
+        set_error("unknown reference-update mode %d", mode);
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
+int pxst_update_reference_ex(const pxst_scan* scan, const float* u, const float* dx, int32_t ref_mode,
+                             float* ref, double* wsum, void* ws, size_t ws_bytes, hipStream_t stream) {
     int rc;
     if ((rc = check_scan(scan))) return rc;
     if ((rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
         (rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")))
         return rc;
+    if ((rc = check_ref_mode(ref_mode))) return rc;
     const Geom g = geom_of(scan->geom);
     const Layout L = make_layout(g, TR_CT_MAX);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
-    return launch_update_reference(g, *scan, u, dx, ref, wsum, nullptr, (char*)ws, L, stream);
+    return launch_update_reference(g, *scan, u, dx, ref, wsum, nullptr, (char*)ws, L, stream,
+                                   ref_mode);
+}
+
+int pxst_update_reference(const pxst_scan* scan, const float* u, const float* dx, float* ref,
+                          double* wsum, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return pxst_update_reference_ex(scan, u, dx, PXST_REF_EXACT, ref, wsum, ws, ws_bytes, stream);
 }
 
 int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum,
@@ -395,6 +410,7 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     if ((rc = check_window(opts->pm, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
     if (opts->update_dx && (rc = check_window(opts->tr, PXST_MAX_TR_RADIUS, "translation")))
         return rc;
+    if ((rc = check_ref_mode(opts->ref_mode))) return rc;
     if ((rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
         (rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
         (rc = check_ptr(err_hist, 8, "err_hist", false)))
@@ -410,7 +426,9 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
     if (opts->n_iter > 0 && (rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
     for (int k = 0; k < opts->n_iter; ++k) {
-        if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream))) return rc;
+        if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream,
+                                          opts->ref_mode)))
+            return rc;
         if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, (float*)(w + L.rowmax),
                                              (int*)(w + L.fscale), stream))) return rc;
         if ((rc = launch_pixel_map(g, *scan, refv, sat, dx, u, opts->pm, u, nullptr, nullptr, w, L,
@@ -424,7 +442,7 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
         if ((rc = launch_error(g, *scan, refv, s2, u, dx, nullptr, nullptr, tot, w, L, stream)))
             return rc;
     }
-    return launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream);
+    return launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream, opts->ref_mode);
 }
 
 int pxst_profile_enable(int32_t on) {
@@ -488,6 +506,7 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         if ((rc = check_window(J.opts.pm, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
         if (J.opts.update_dx && (rc = check_window(J.opts.tr, PXST_MAX_TR_RADIUS, "translation")))
             return rc;
+        if ((rc = check_ref_mode(J.opts.ref_mode))) return rc;
         if ((rc = check_ptr(J.u, 4, "u")) || (rc = check_ptr(J.dx, 4, "dx")) ||
             (rc = check_ptr(J.ref, 4, "ref")) || (rc = check_ptr(J.wsum, 8, "wsum")) ||
             (rc = check_ptr(J.err_hist, 8, "err_hist", false)))
@@ -547,7 +566,7 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
             rc = launch_pm_setup(st[j].g, J.scan, st[j].w, st[j].L, stream);
         if (!rc)
             rc = launch_update_reference(st[j].g, J.scan, J.u, J.dx, J.ref, J.wsum, st[j].refv, st[j].w,
-                                         st[j].L, stream);
+                                         st[j].L, stream, J.opts.ref_mode);
         if (!rc && J.iter < J.opts.n_iter)
             rc = launch_prep_reference(st[j].g, nullptr, nullptr, st[j].refv, (int*)(st[j].w + st[j].L.sat),
                                        (int*)(st[j].w + st[j].L.sat_tmp),

@@ -171,7 +171,7 @@ int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& 
 // Reference update (splat as a deterministic gather over the inverted map).
 int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
                             float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s);
+                            hipStream_t s, int ref_mode = PXST_REF_EXACT);
 
 // Reference-plane error: ref_err = sum w M eps / sum w M (needs sigma2 in ws s2).
 int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,

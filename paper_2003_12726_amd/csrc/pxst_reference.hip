@@ -440,11 +440,14 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 // pixels and, frame by frame, walks the cells of the inverted map whose points can put
 // a bilinear corner on the tile (rows of cells are contiguous runs of sorted entries,
 // one lane per entry), adding each corner's value M W I w and weight M W^2 w into LDS
-// bins.  The terms are rounded to multiples of a power-of-two quantum chosen from
-// max |W| so that every term is an integer below 2^30 in quantum units; sums of up to
-// 2^23 such terms are exact in FP64, so the LDS atomic additions give the same result
-// in any order (bitwise reproducible), and the rounding is about 1e-9 of the largest
-// term.  Frame chunks (grid z) write exact partial sums that a second pass adds.
+// bins.  The terms are rounded to integer multiples of a power-of-two quantum and
+// summed as 64-bit integers.  The quantum comes from max |W| and from the number of
+// terms a reference pixel can receive at most (frames x good pixels), so that no sum
+// can leave the 63-bit range: terms get 43 bits when that bound allows (36 bits for a
+// 512 x 512 detector with 400 frames; the rounding is 2^-bits of the largest possible
+// term).  The sums are exact, so the LDS atomic additions give the same result in any
+// order (bitwise reproducible).  Frame chunks (grid z) write exact partial sums that a
+// second pass adds; the quotient is formed in FP64.
 constexpr int RS_TR = 16, RS_TC = 62, RS_THREADS = 256;
 
 struct SplatArgs {
@@ -455,7 +458,7 @@ struct SplatArgs {
     const int2* bsort;
     const GridInfo* gi;
     int N, HW, Rs, Rf, GH, GW, nchunks;
-    double2* part;     // [nchunks][Rs * Rf] quantised (numerator, weight) sums
+    longlong2* part;   // [nchunks][Rs * Rf] quantised (numerator, weight) sums
     float* ref;
     double* wsum;
     float* refv;
@@ -475,20 +478,28 @@ __device__ inline void splat_axis(int b, int s, float t, int& plo, float& wlo, f
     }
 }
 
-// Quantum exponents: |W I| 2^fn <= 2^30 and W^2 2^fd <= 2^30 for every term.
-__device__ inline void splat_scales(float wmax, int& fn, int& fd) {
-    int e1 = 0, e2 = 0;
+// Quantum exponents: |W I| 2^fn < 2^T and W^2 2^fd < 2^T for every term (counts are at
+// most 65535), T = min(43, 62 - bits(N n_good)): a sum of at most N n_good terms stays
+// below 2^62.
+__device__ inline void splat_scales(float wmax, int n_frames, int n_good, int& fn, int& fd) {
+    int e1 = 0, e2 = 0, et = 0;
     if (wmax > 0.f && isfinite(wmax)) {
         frexp((double)wmax * 65535.0, &e1);
         frexp((double)wmax * (double)wmax, &e2);
     }
-    fn = 30 - e1;
-    fd = 30 - e2;
+    frexp((double)n_frames * (double)(n_good > 0 ? n_good : 1), &et);
+    const int T = min(43, 62 - et);
+    fn = T - e1;
+    fd = T - e2;
+}
+
+__device__ inline unsigned long long quantise(double t) {
+    return (unsigned long long)(long long)rint(t);
 }
 
 __device__ inline void splat_entry(const SplatArgs& a, unsigned e, int n, int s0, int s1, float fd0,
-                                   float fd1, int P0, int P1, double sn, double sd, double* bn,
-                                   double* bd) {
+                                   float fd1, int P0, int P1, double sn, double sd,
+                                   unsigned long long* bn, unsigned long long* bd) {
     const float4 pd = a.pdata[e];
     const int2 b = a.bsort[e];
     const double I = (double)a.fsort[(size_t)n * a.HW + e];
@@ -506,24 +517,24 @@ __device__ inline void splat_entry(const SplatArgs& a, unsigned e, int n, int s0
             const int i = i0 + di, j = j0 + dj;
             const float w = (di ? wh0 : wl0) * (dj ? wh1 : wl1);
             if ((unsigned)i < (unsigned)RS_TR && (unsigned)j < (unsigned)RS_TC && w != 0.f) {
-                atomicAdd(&bn[i * RS_TC + j], rint((double)w * vn));
-                atomicAdd(&bd[i * RS_TC + j], rint((double)w * vd));
+                atomicAdd(&bn[i * RS_TC + j], quantise((double)w * vn));
+                atomicAdd(&bd[i * RS_TC + j], quantise((double)w * vd));
             }
         }
     }
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
-    __shared__ double bn[RS_TR * RS_TC], bd[RS_TR * RS_TC];
+    __shared__ unsigned long long bn[RS_TR * RS_TC], bd[RS_TR * RS_TC];
     const int P1 = blockIdx.x * RS_TC, P0 = blockIdx.y * RS_TR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < RS_TR * RS_TC; i += RS_THREADS) {
-        bn[i] = 0.0;
-        bd[i] = 0.0;
+        bn[i] = 0ull;
+        bd[i] = 0ull;
     }
     const GridInfo gi = *a.gi;
     int fn, fd;
-    splat_scales(gi.wmax, fn, fd);
+    splat_scales(gi.wmax, a.N, gi.n_good, fn, fd);
     const double sn = ldexp(1.0, fn), sd = ldexp(1.0, fd);
     const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
     const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
@@ -557,9 +568,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
         if (p0 >= a.Rs || p1 >= a.Rf) continue;
         const size_t p = (size_t)p0 * a.Rf + p1;
         if (a.nchunks > 1) {
-            a.part[(size_t)blockIdx.z * RR + p] = make_double2(bn[i], bd[i]);
+            a.part[(size_t)blockIdx.z * RR + p] = make_longlong2((long long)bn[i], (long long)bd[i]);
         } else {
-            const double num = bn[i] * ldexp(1.0, -fn), den = bd[i] * ldexp(1.0, -fd);
+            const double num = (double)(long long)bn[i] * ldexp(1.0, -fn);
+            const double den = (double)(long long)bd[i] * ldexp(1.0, -fd);
             const float val = den > 0.0 ? (float)(num / den) : 0.f;
             a.ref[p] = val;
             a.wsum[p] = den;
@@ -568,20 +580,36 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
     }
 }
 
+// Reference values rounded to the nearest bfloat16 (ties to even), NaN kept.
+__device__ inline float round_bf16(float x) {
+    if (!(x == x) || isinf(x)) return x;
+    unsigned b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return __uint_as_float(b & 0xFFFF0000u);
+}
+
+__global__ void k_round_bf16(float* __restrict__ ref, float* __restrict__ refv, size_t n) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    ref[p] = round_bf16(ref[p]);
+    if (refv) refv[p] = round_bf16(refv[p]);
+}
+
 // Adds the exact chunk partials and writes the reference.
 __global__ void k_ref_splat_combine(SplatArgs a) {
     const size_t RR = (size_t)a.Rs * a.Rf;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= RR) return;
-    double sn = 0.0, sdd = 0.0;
+    unsigned long long sn = 0ull, sdd = 0ull;
     for (int c = 0; c < a.nchunks; ++c) {
-        const double2 q = a.part[(size_t)c * RR + p];
-        sn += q.x;
-        sdd += q.y;
+        const longlong2 q = a.part[(size_t)c * RR + p];
+        sn += (unsigned long long)q.x;
+        sdd += (unsigned long long)q.y;
     }
     int fn, fd;
-    splat_scales(a.gi->wmax, fn, fd);
-    const double num = sn * ldexp(1.0, -fn), den = sdd * ldexp(1.0, -fd);
+    splat_scales(a.gi->wmax, a.N, a.gi->n_good, fn, fd);
+    const double num = (double)(long long)sn * ldexp(1.0, -fn);
+    const double den = (double)(long long)sdd * ldexp(1.0, -fd);
     const float val = den > 0.0 ? (float)(num / den) : 0.f;
     a.ref[p] = val;
     a.wsum[p] = den;
@@ -693,9 +721,19 @@ static void launch_gather(const GatherArgs& a, int mode, const Geom& g, hipStrea
 
 int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
                             float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s) {
+                            hipStream_t s, int ref_mode) {
     int rc = build_inverse_map(g, sc, u, ws, L, s);
     if (rc) return rc;
+    if (ref_mode == PXST_REF_FP32) {
+        GatherArgs b = gather_args(g, sc, u, dx, ws, L);
+        b.out = ref;
+        b.wsum = wsum;
+        b.refv_out = refv;
+        profile_begin("ref_gather", s);
+        launch_gather(b, 0, g, s);
+        profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
+        return check_hip(hipGetLastError(), "reference update (float32 gather)");
+    }
     SplatArgs a{};
     a.fsort = (const uint16_t*)(ws + L.fsort);
     a.dx = dx;
@@ -710,7 +748,7 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     a.GH = grid_h(g);
     a.GW = grid_w(g);
     a.nchunks = L.ref_chunks;
-    a.part = (double2*)(ws + L.rpart);
+    a.part = (longlong2*)(ws + L.rpart);
     a.ref = ref;
     a.wsum = wsum;
     a.refv = refv;
@@ -719,6 +757,9 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     hipLaunchKernelGGL(k_ref_splat, grid, dim3(RS_THREADS), 0, s, a);
     if (a.nchunks > 1)
         hipLaunchKernelGGL(k_ref_splat_combine, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, a);
+    if (ref_mode == PXST_REF_BF16)
+        hipLaunchKernelGGL(k_round_bf16, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, ref, refv,
+                           g.RR());
     profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
     return check_hip(hipGetLastError(), "reference update");
 }

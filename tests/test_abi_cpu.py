@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pxst.SYMBOLS)
-    assert pxst.abi_version() == 1
+    assert pxst.abi_version() == 2
 
 
 def test_workspace_bytes_grows_with_problem(lib):
@@ -70,6 +70,9 @@ def test_error_paths_return_before_gpu_work(lib):
     assert lib.pxst_update_reference(ctypes.byref(sc), P, P, None, P, P, 1 << 30, None) == pxst.PXST_EINVAL
     # misaligned double pointer
     assert lib.pxst_update_reference(ctypes.byref(sc), P, P, P, P + 4, P, 1 << 30, None) == pxst.PXST_EINVAL
+    # unknown reference-update mode
+    assert lib.pxst_update_reference_ex(ctypes.byref(sc), P, P, 7, P, P, P, 1 << 30, None) == pxst.PXST_EINVAL
+    assert "mode" in pxst.last_error()
     # workspace too small
     assert lib.pxst_update_reference(ctypes.byref(sc), P, P, P, P, 0x100000, 16, None) == pxst.PXST_EWORKSPACE
     assert "workspace" in pxst.last_error()
@@ -93,6 +96,12 @@ def test_error_paths_return_before_gpu_work(lib):
     o = pxst.make_opts(-1, (3, 3))
     assert lib.pxst_solve(ctypes.byref(sc), ctypes.byref(o), P, P, P, P, None, P, 1 << 30,
                           None) == pxst.PXST_EINVAL
+    # solve: unknown reference-update mode
+    o = pxst.make_opts(2, (3, 3))
+    o.ref_mode = 5
+    assert lib.pxst_solve(ctypes.byref(sc), ctypes.byref(o), P, P, P, P, None, P, 1 << 30,
+                          None) == pxst.PXST_EINVAL
+    assert "mode" in pxst.last_error()
     # oversized detector
     huge = _scan(geom=pxst.make_geom(4, (8192, 4096), (40, 40), (0, 0)))
     assert lib.pxst_update_reference(ctypes.byref(huge), P, P, P, P, P, 1 << 40, None) == pxst.PXST_EUNSUPPORTED

@@ -35,12 +35,12 @@ def _lib():
 
 # ------------------------------------------------------------------------ helpers
 
-def gpu_reference(s, u, dx):
+def gpu_reference(s, u, dx, mode="exact"):
     sc = dev_scan(s)
     ref = empty(s.ref_shape, torch.float32)
     w = empty(s.ref_shape, torch.float64)
     ws = pxst.alloc_workspace(sc.geom, None)
-    pxst.update_reference(sc, to_dev(u), to_dev(dx), ref, w, ws)
+    pxst.update_reference(sc, to_dev(u), to_dev(dx), ref, w, ws, mode=mode)
     torch.cuda.synchronize()
     return ref.cpu().numpy(), w.cpu().numpy()
 
@@ -130,6 +130,34 @@ def test_reference_parity(case):
     pos = wo > 0
     np.testing.assert_allclose(wg[pos], wo[pos], rtol=1e-6)
     assert np.all(rg[~pos] == 0)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+def test_reference_modes(mode):
+    """The other reference-update arithmetics of the precision study: the float32
+    gather meets the same bar as the default; bfloat16 storage is the exact update
+    rounded to bfloat16 (ties to even), within 2^-8 relative of the oracle (bfloat16
+    keeps 8 significand bits)."""
+    s = random_small_scan(det=(37, 53), n_frames=7, seed=23)
+    say(f"[reference] mode {mode} det={s.det} N={s.n_frames}")
+    rg, wg = gpu_reference(s, s.u0, s.dx0, mode=mode)
+    ro, wo = oracle_state(s)
+    np.testing.assert_array_equal(wg > 0, wo > 0)
+    pos = wo > 0
+    np.testing.assert_allclose(wg[pos], wo[pos], rtol=1e-6)
+    if mode == "fp32":
+        err, _ = ref_rel_error(rg, ro, wo)
+        assert err < REF_TOL_REL, err
+    else:
+        bits = rg.view(np.uint32)
+        assert np.all(bits & 0xFFFF == 0)
+        re_, _ = gpu_reference(s, s.u0, s.dx0, mode="exact")
+        # the rounding of the exact result, ties to even
+        b = re_.view(np.uint32).astype(np.uint64)
+        rounded = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32).view(np.float32)
+        np.testing.assert_array_equal(rg, rounded)
+        rel = np.abs(rg[pos].astype(np.float64) - ro[pos]) / np.abs(ro[pos]).clip(1e-30)
+        assert rel.max() <= 2.0 ** -8 + 1e-5, rel.max()
 
 
 def test_reference_parity_realistic_full():
