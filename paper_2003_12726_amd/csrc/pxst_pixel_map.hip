@@ -53,7 +53,9 @@ struct PmArgs {
     const int* fscale;  // fixed-point exponent of the reference
     int kblocks;
     int mm_lds_a;       // the tile's packed frames are staged in LDS
-    int mm_on;          // interior and edge tiles go to the matrix-core search
+    int mm_on;          // bits: interior tiles / edge tiles on the matrix cores, frames
+                        // staged in LDS for interior / edge tiles
+    int mm_slow_max;    // slow-frame capacity of a matrix-core edge tile
 };
 
 
@@ -112,8 +114,9 @@ __device__ void classify_item(const PmArgs& a, int tile) {
             nbad += rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + (int)rh, c0r, c0r + (int)rw) ? 0 : 1;
         }
         const int bad = wave_sum<int>(nbad);
-        if (a.mm_on)
-            cls = bad == 0 ? CNT_FAST : (bad <= MM_SLOW_MAX && bad < a.N ? CNT_EDGE_MM : CNT_EDGE);
+        if (a.mm_on & 1)
+            cls = bad == 0 ? CNT_FAST
+                           : ((a.mm_on & 2) && bad <= a.mm_slow_max && bad < a.N ? CNT_EDGE_MM : CNT_EDGE);
         else
             cls = (bad == 0 && rh * rw <= a.fast_cap) ? CNT_FAST : CNT_EDGE;
         if (lane == 0) a.tiles[tile] = TileDesc{mn0, mn1, (int)rh, (int)rw};
@@ -853,27 +856,50 @@ __device__ inline mm_v4i mm_as_v4i(uint4 v) {
 __host__ __device__ inline int mm_frames_padded(int n_frames) {
     return (n_frames + MM_KB - 1) / MM_KB * MM_KB;
 }
-// Extra LDS of edge tiles: slow-frame flags [NP] | slow list [MAX] | slow shifts int4
-// [MAX] | counts I [MAX][64] | nslow, first fast frame.
-__host__ __device__ inline size_t mm_edge_bytes(int np) {
-    return (size_t)np * 4 + MM_SLOW_MAX * 4 + MM_SLOW_MAX * 16 + MM_SLOW_MAX * 64 * 4 + 16;
+// Extra LDS of edge tiles: slow-frame flags [NP] | slow list [S] | slow shifts int4
+// [S] | counts I [S][64] | nslow, first fast frame.
+__host__ __device__ inline size_t mm_edge_bytes(int np, int smax) {
+    return (size_t)np * 4 + (size_t)smax * (4 + 16 + 64 * 4) + 16;
 }
-__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a, bool edge) {
+__host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a, bool edge,
+                                               int smax) {
     const size_t np = (size_t)mm_frames_padded(n_frames);
     const size_t e = ((size_t)64 * nc + 3) / 4 * 4 * sizeof(float);
     const size_t apk = stage_a ? np / MM_KB * MM_PACK_BYTES : 0;
-    return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + (edge ? mm_edge_bytes((int)np) : 0) + apk;
+    return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + (edge ? mm_edge_bytes((int)np, smax) : 0) + apk;
 }
 
-// Interior tiles (bit 0) and edge tiles (bit 1) go to the matrix-core search when its
-// LDS fits; the tile's packed frames are staged in LDS when they fit beside the rest.
+// Matrix-core search of one job: whether interior (fast) and edge tiles go to it, whether
+// the packed frames are staged in LDS, and the edge tiles' slow-frame capacity (the
+// largest that fits the LDS, preferring staged frames).  Depends on the job's own
+// window and frame count only.
 constexpr size_t MM_LDS_MAX = 160 * 1024;
-int mm_flags(int nx, int ny, int n_frames) {
-    return (mm_lds_bytes(nx * ny, n_frames, false, false) <= MM_LDS_MAX ? 1 : 0) |
-           (mm_lds_bytes(nx * ny, n_frames, false, true) <= MM_LDS_MAX ? 2 : 0);
-}
-bool mm_stage_a(int nx, int ny, int n_frames, bool edge) {
-    return mm_lds_bytes(nx * ny, n_frames, true, edge) <= MM_LDS_MAX;
+struct MmPlan {
+    bool fast, edge, fast_stage, edge_stage;
+    int slow_max;
+};
+MmPlan mm_plan(int nx, int ny, int n_frames) {
+    MmPlan p{};
+    const int nc = nx * ny;
+    p.fast = mm_lds_bytes(nc, n_frames, false, false, 0) <= MM_LDS_MAX;
+    p.fast_stage = mm_lds_bytes(nc, n_frames, true, false, 0) <= MM_LDS_MAX;
+    auto cap = [&](bool stage) {
+        const size_t base = mm_lds_bytes(nc, n_frames, stage, true, 0);
+        if (base >= MM_LDS_MAX) return 0;
+        const size_t s = (MM_LDS_MAX - base) / (4 + 16 + 64 * 4);
+        return (int)(s > (size_t)MM_SLOW_CAP ? MM_SLOW_CAP : s);
+    };
+    const int s_lds = cap(true), s_glb = cap(false);
+    if (s_lds >= 64 || (s_lds >= MM_SLOW_MIN && s_glb < 64)) {
+        p.edge = true;
+        p.edge_stage = true;
+        p.slow_max = s_lds;
+    } else if (s_glb >= MM_SLOW_MIN) {
+        p.edge = true;
+        p.edge_stage = false;
+        p.slow_max = s_glb;
+    }
+    return p;
 }
 
 template <bool LDSA, bool EDGE>
@@ -898,10 +924,11 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     char* ext = (char*)(pp + 64);
     int* sflag = (int*)ext;                                    // edge tiles only
     int* slist = sflag + NP;
-    int4* sinfo = (int4*)(slist + MM_SLOW_MAX);
-    float* sI = (float*)(sinfo + MM_SLOW_MAX);                 // [MAX][64]
-    int* smisc = (int*)(sI + MM_SLOW_MAX * 64);
-    uint4* apk = (uint4*)(EDGE ? ext + mm_edge_bytes(NP) : ext);   // packed frames, if staged
+    const int SMAX = a.mm_slow_max;
+    int4* sinfo = (int4*)(slist + SMAX);
+    float* sI = (float*)(sinfo + SMAX);                        // [SMAX][64]
+    int* smisc = (int*)(sI + SMAX * 64);
+    uint4* apk = (uint4*)(EDGE ? ext + mm_edge_bytes(NP, SMAX) : ext);   // packed frames, if staged
 
     // edge tiles: the frames whose staged region holds an invalid lookup (the test of
     // the classification), in frame order, and the first frame without one
@@ -922,12 +949,12 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 const unsigned long long m = __ballot(f);
                 const unsigned long long fm = __ballot(n < N && !f);
                 const int before = __popcll(m & ((1ull << lane) - 1ull));
-                if (f && count + before < MM_SLOW_MAX) slist[count + before] = n;
+                if (f && count + before < SMAX) slist[count + before] = n;
                 if (first < 0 && fm) first = b0 + __ffsll((long long)fm) - 1;
                 count += __popcll(m);
             }
             if (lane == 0) {
-                smisc[0] = min(count, MM_SLOW_MAX);
+                smisc[0] = min(count, SMAX);
                 smisc[1] = first < 0 ? 0 : first;
             }
         }
@@ -1414,28 +1441,36 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     a.pstat = (const double*)(ws + L.pstat);
     a.fscale = (const int*)(ws + L.fscale);
     a.kblocks = L.kblocks;
-    a.mm_on = mm_flags(a.NX, a.NY, g.N);
+    const MmPlan mp = mm_plan(a.NX, a.NY, g.N);
+    a.mm_on = (mp.fast ? 1 : 0) | (mp.edge ? 2 : 0) | (mp.fast_stage ? 4 : 0) | (mp.edge_stage ? 8 : 0);
+    a.mm_slow_max = mp.slow_max;
     return a;
 }
 
-// One launch of the matrix-core search (interior or edge tiles) for one job (jobs ==
-// nullptr) or a batch of jobs sharing the window (nx, ny) with at most max_n frames.
-int launch_mma(const PmArgs& a, const PmArgs* jobs, const int* off, int njobs, int grid, int max_n,
+// One launch of the matrix-core search (interior or edge tiles) for one job
+// (dev_jobs == nullptr: host_args[0] is passed by value) or a batch of jobs with the
+// same window and the same kernel choice (their host-side arguments in host_args).
+// The frames are staged in LDS when every job of the launch stages them; the LDS size
+// is the largest any job needs.
+int launch_mma(const PmArgs* host_args, int nargs, const PmArgs* dev_jobs, const int* off, int grid,
                bool edge, hipStream_t s) {
-    const bool stage = mm_stage_a(a.NX, a.NY, max_n, edge);
-    const size_t sh = mm_lds_bytes(a.NX * a.NY, max_n, stage, edge);
-    if (jobs == nullptr) {
-        PmArgs b = a;
-        b.mm_lds_a = stage ? 1 : 0;
+    bool stage = true;
+    for (int j = 0; j < nargs; ++j) stage = stage && (host_args[j].mm_on & (edge ? 8 : 4)) != 0;
+    size_t sh = 0;
+    for (int j = 0; j < nargs; ++j) {
+        const PmArgs& x = host_args[j];
+        sh = std::max(sh, mm_lds_bytes(x.NX * x.NY, x.N, stage, edge, x.mm_slow_max));
+    }
+    if (dev_jobs == nullptr) {
         const PmKernel kern = edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
                                    : (stage ? k_pm_mma_lds : k_pm_mma_glb);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, b);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, host_args[0]);
     } else {
         const PmBatchKernel kern = edge ? (stage ? k_pm_mma_edge_lds_batch : k_pm_mma_edge_glb_batch)
                                         : (stage ? k_pm_mma_lds_batch : k_pm_mma_glb_batch);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, jobs, off, njobs);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, dev_jobs, off, nargs);
     }
     return check_hip(hipGetLastError(), edge ? "pixel-map search (edge tiles, matrix cores)"
                                              : "pixel-map search (interior tiles, matrix cores)");
@@ -1487,7 +1522,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     if (a.mm_on & 1) {
         profile_begin("pm_fast", s);
         profile_begin("pm_fast_int8_ops", s);
-        rc = launch_mma(a, nullptr, nullptr, 0, a.ntiles, g.N, false, s);
+        rc = launch_mma(&a, 1, nullptr, nullptr, a.ntiles, false, s);
         // int8 operations issued on the matrix cores: 2 per multiply-add, 64 pixels x
         // positions x padded frames x 6 byte pairs
         profile_end("pm_fast_int8_ops", s, 0, a.counters + CNT_MM_POS,
@@ -1505,7 +1540,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     }
     if (a.mm_on & 2) {
         profile_begin("pm_edge_mma", s);
-        rc = launch_mma(a, nullptr, nullptr, 0, a.ntiles, g.N, true, s);
+        rc = launch_mma(&a, 1, nullptr, nullptr, a.ntiles, true, s);
         profile_end("pm_edge_mma", s, 0, a.counters + CNT_GOOD_EDGE_MM, evals_per_good_px);
         if (rc) return rc;
     }
@@ -1596,7 +1631,7 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
             const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
             profile_begin("pm_fast", s);
-            rc = launch_mma(base[j0], (const PmArgs*)up.args_dev, up.off_dev, m, grid, max_n, false, s);
+            rc = launch_mma(ga.data(), m, (const PmArgs*)up.args_dev, up.off_dev, grid, false, s);
             profile_end("pm_fast", s, 0, nullptr, 0);
             if (rc) return rc;
         } else {
@@ -1614,7 +1649,7 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
             const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
             if (ar.overflow) break;
             profile_begin("pm_edge_mma", s);
-            rc = launch_mma(base[j0], (const PmArgs*)up.args_dev, up.off_dev, m, grid, max_n, true, s);
+            rc = launch_mma(ga.data(), m, (const PmArgs*)up.args_dev, up.off_dev, grid, true, s);
             profile_end("pm_edge_mma", s, 0, nullptr, 0);
             if (rc) return rc;
         }

@@ -5,7 +5,8 @@
 // Pass 1 (grid: pixel blocks x frames): a thread walks 16 pixels of one frame; for
 // each it loads the (2Tx+2) x (2Ty+2) reference neighbourhood of u - dx_n - origin
 // once and forms all shifted lookups from it (the bilinear fractions do not depend on
-// the integer shift).  Per-shift sums are reduced over the work-group and written as
+// the integer shift): when the neighbourhood is fully valid, by interpolating its rows
+// along the fast axis once and the results along the slow axis per shift.  Per-shift sums are reduced over the work-group and written as
 // per-block partials.  Pass 2 (one wave per frame) adds the partials with compensated
 // float32 sums in a fixed order, normalises, takes the first minimum and refines.
 #include "pxst_device.hpp"
@@ -34,6 +35,7 @@ template <int TX, int TY>
 __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
     constexpr int CR = 2 * TY + 2;   // neighbourhood columns
+    constexpr int RR = 2 * TX + 2;   // neighbourhood rows
     const int blk = blockIdx.x, n = blockIdx.y;
     const size_t HW = (size_t)a.H * a.W;
     const float d0 = a.dx_in[2 * n], d1 = a.dx_in[2 * n + 1];
@@ -41,6 +43,9 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
     const float fd0 = d0 - s0, fd1 = d1 - s1;
     const uint16_t* fr = a.frames + (size_t)n * HW;
 
+    // per shift: squared residuals; the variance and count of the pixels with a valid
+    // lookup are common to all shifts for pixels whose whole neighbourhood is valid
+    // (vC, cC) and kept per shift for the others (var, cnt)
     float err[CT], var[CT];
     int cnt[CT];
 #pragma unroll
@@ -49,6 +54,8 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
         var[s] = 0.f;
         cnt[s] = 0;
     }
+    float vC = 0.f;
+    int cC = 0;
     const size_t p_begin = (size_t)blk * TR_PIX_PER_BLOCK;
     for (int m = 0; m < TR_PIX_PER_BLOCK / TR_THREADS; ++m) {
         const size_t pix = p_begin + (size_t)m * TR_THREADS + threadIdx.x;
@@ -62,51 +69,73 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
         const float Wp = a.white[pix];
         const float I = (float)fr[pix];
         const float v = I - Wp, v2 = v * v;
-        // neighbourhood rows a0 - TX .. a0 + TX + 1, columns b0 - TY .. b0 + TY + 1
-        float rowA[CR], rowB[CR];
-        auto load_row = [&](float* row, int rr) {
-            const bool rin = rr >= 0 && rr < a.Rs;
+        // neighbourhood rows a0 - TX .. a0 + TX + 1, columns b0 - TY .. b0 + TY + 1;
+        // shift (sx, sy) looks up corner rows a0 - sx, a0 - sx + 1 and columns
+        // b0 - sy, b0 - sy + 1
+        float nb[RR][CR];
+        bool all = a0 - TX >= 0 && a0 + TX + 1 < a.Rs && b0 - TY >= 0 && b0 + TY + 1 < a.Rf;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            const int rr = a0 - TX + r;
 #pragma unroll
             for (int c = 0; c < CR; ++c) {
                 const int cc = b0 - TY + c;
-                row[c] = (rin && cc >= 0 && cc < a.Rf) ? a.refv[(size_t)rr * a.Rf + cc] : qnan();
+                nb[r][c] = (rr >= 0 && rr < a.Rs && cc >= 0 && cc < a.Rf) ? a.refv[(size_t)rr * a.Rf + cc]
+                                                                         : qnan();
+                all = all && valid(nb[r][c]);
             }
-        };
-        // shift sx looks up corner rows a0 - sx and a0 - sx + 1: iterate sx from +TX down
-        load_row(rowA, a0 - TX);
+        }
+        if (all) {
+            // every lookup valid: interpolate along fs, then along ss (the fractions are
+            // the same for every shift)
+            float h[RR][CR - 1];
 #pragma unroll
-        for (int ix = 0; ix < NXs; ++ix) {
-            const int sx = TX - ix;              // row a0 - sx = a0 - TX + ix
-            load_row(rowB, a0 - sx + 1);
+            for (int r = 0; r < RR; ++r)
 #pragma unroll
-            for (int iy = 0; iy < NYs; ++iy) {
-                const int sy = TY - iy;          // column b0 - sy = b0 - TY + iy
-                const int c = iy;
-                const float v00 = rowA[c], v01 = rowA[c + 1], v10 = rowB[c], v11 = rowB[c + 1];
-                float g;
-                if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
-                    g = bilinear4(v00, v01, v10, v11, fa, fb);
-                } else {
+                for (int c = 0; c < CR - 1; ++c) h[r][c] = fmaf(fb, nb[r][c + 1] - nb[r][c], nb[r][c]);
+            const float nW = -Wp;
+#pragma unroll
+            for (int ix = 0; ix < NXs; ++ix) {
+#pragma unroll
+                for (int iy = 0; iy < NYs; ++iy) {
+                    const float g = fmaf(fa, h[ix + 1][iy] - h[ix][iy], h[ix][iy]);
+                    const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
+                    const float rr = fmaf(nW, g, I);
+                    err[s] = fmaf(rr, rr, err[s]);
+                }
+            }
+            vC += v2;
+            cC += 1;
+        } else {
+#pragma unroll
+            for (int ix = 0; ix < NXs; ++ix) {
+#pragma unroll
+                for (int iy = 0; iy < NYs; ++iy) {
+                    const float v00 = nb[ix][iy], v01 = nb[ix][iy + 1], v10 = nb[ix + 1][iy],
+                                v11 = nb[ix + 1][iy + 1];
                     const float ga = 1.f - fa, gb = 1.f - fb;
                     float num = 0.f, den = 0.f;
                     if (valid(v00)) { num = fmaf(ga * gb, v00, num); den += ga * gb; }
                     if (valid(v01)) { num = fmaf(ga * fb, v01, num); den += ga * fb; }
                     if (valid(v10)) { num = fmaf(fa * gb, v10, num); den += fa * gb; }
                     if (valid(v11)) { num = fmaf(fa * fb, v11, num); den += fa * fb; }
-                    g = den > 0.f ? num / den : qnan();
-                }
-                // candidate index: (sx + TX) * NYs + (sy + TY)
-                const int s = (sx + TX) * NYs + (sy + TY);
-                if (valid(g)) {
-                    const float rr = fmaf(-Wp, g, I);
-                    err[s] = fmaf(rr, rr, err[s]);
-                    var[s] += v2;
-                    cnt[s] += 1;
+                    const float g = den > 0.f ? num / den : qnan();
+                    // shift (sx, sy) = (TX - ix, TY - iy); candidate index (sx + TX) NYs + (sy + TY)
+                    const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
+                    if (valid(g)) {
+                        const float rr = fmaf(-Wp, g, I);
+                        err[s] = fmaf(rr, rr, err[s]);
+                        var[s] += v2;
+                        cnt[s] += 1;
+                    }
                 }
             }
-#pragma unroll
-            for (int c = 0; c < CR; ++c) rowA[c] = rowB[c];
         }
+    }
+#pragma unroll
+    for (int s = 0; s < CT; ++s) {
+        var[s] += vC;
+        cnt[s] += cC;
     }
     // work-group reduction of every per-shift sum
     __shared__ float red[TR_THREADS / 64][CT * 3];
