@@ -103,7 +103,7 @@ enum { CNT_FAST = 0, CNT_EDGE = 1, CNT_GENERIC = 2, CNT_NONE = 3, CNT_GOOD_FAST 
        CNT_GOOD_EDGE_MM = 9, CNT_MM_POS_EDGE = 10, CNT_N = 12 };
 constexpr int LIST_EDGE_MM = 3;
 // Frames with invalid lookups that a matrix-core edge tile may have: chosen per job
-// to fill the LDS, between these bounds.
+// to fill the LDS, a multiple of 32 between these bounds.
 constexpr int MM_SLOW_MIN = 32, MM_SLOW_CAP = 256;
 
 // Round up to a multiple of a such that the row pitch is 8 (mod 32) floats: an 8-wide

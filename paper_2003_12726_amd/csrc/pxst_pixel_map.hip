@@ -857,9 +857,12 @@ __host__ __device__ inline int mm_frames_padded(int n_frames) {
     return (n_frames + MM_KB - 1) / MM_KB * MM_KB;
 }
 // Extra LDS of edge tiles: slow-frame flags [NP] | slow list [S] | slow shifts int4
-// [S] | counts I [S][64] | nslow, first fast frame.
+// [S] | counts I [S][64] | nslow, first fast frame | per wave, per position of its
+// current column block, a bit mask of the slow frames whose lookup is invalid.
+__host__ __device__ inline int mm_mask_words(int smax) { return (smax + 31) / 32; }
 __host__ __device__ inline size_t mm_edge_bytes(int np, int smax) {
-    return (size_t)np * 4 + (size_t)smax * (4 + 16 + 64 * 4) + 16;
+    return (size_t)np * 4 + (size_t)smax * (4 + 16 + 64 * 4) + 16 +
+           (size_t)MM_WAVES * 16 * mm_mask_words(smax) * 4;
 }
 __host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a, bool edge,
                                                int smax) {
@@ -883,11 +886,11 @@ MmPlan mm_plan(int nx, int ny, int n_frames) {
     const int nc = nx * ny;
     p.fast = mm_lds_bytes(nc, n_frames, false, false, 0) <= MM_LDS_MAX;
     p.fast_stage = mm_lds_bytes(nc, n_frames, true, false, 0) <= MM_LDS_MAX;
+    // capacity: the largest multiple of 32 (keeps the LDS arrays 16-byte aligned) that fits
     auto cap = [&](bool stage) {
-        const size_t base = mm_lds_bytes(nc, n_frames, stage, true, 0);
-        if (base >= MM_LDS_MAX) return 0;
-        const size_t s = (MM_LDS_MAX - base) / (4 + 16 + 64 * 4);
-        return (int)(s > (size_t)MM_SLOW_CAP ? MM_SLOW_CAP : s);
+        for (int sm = MM_SLOW_CAP; sm >= 32; sm -= 32)
+            if (mm_lds_bytes(nc, n_frames, stage, true, sm) <= MM_LDS_MAX) return sm;
+        return 0;
     };
     const int s_lds = cap(true), s_glb = cap(false);
     if (s_lds >= 64 || (s_lds >= MM_SLOW_MIN && s_glb < 64)) {
@@ -928,17 +931,23 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     int4* sinfo = (int4*)(slist + SMAX);
     float* sI = (float*)(sinfo + SMAX);                        // [SMAX][64]
     int* smisc = (int*)(sI + SMAX * 64);
+    const int MW = mm_mask_words(SMAX);
+    unsigned* imask = (unsigned*)(smisc + 4) + (size_t)wave * 16 * MW;   // this wave's [16][MW]
     uint4* apk = (uint4*)(EDGE ? ext + mm_edge_bytes(NP, SMAX) : ext);   // packed frames, if staged
 
     // edge tiles: the frames whose staged region holds an invalid lookup (the test of
     // the classification), in frame order, and the first frame without one
     int nslow = 0, nref = 0;
     if (EDGE) {
-        for (int n = tid; n < N; n += MM_THREADS) {
-            const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
-            const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
-            const int r0 = T0 - s0.e, c0r = T1 - s1.e;
-            sflag[n] = rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + td.rh, c0r, c0r + td.rw) ? 0 : 1;
+        for (int n = tid; n < NP; n += MM_THREADS) {
+            int f = 0;
+            if (n < N) {
+                const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
+                const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
+                const int r0 = T0 - s0.e, c0r = T1 - s1.e;
+                f = rect_valid(a.sat, a.Rs, a.Rf, r0, r0 + td.rh, c0r, c0r + td.rw) ? 0 : 1;
+            }
+            sflag[n] = f;
         }
         __syncthreads();
         if (wave == 0) {
@@ -949,7 +958,10 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 const unsigned long long m = __ballot(f);
                 const unsigned long long fm = __ballot(n < N && !f);
                 const int before = __popcll(m & ((1ull << lane) - 1ull));
-                if (f && count + before < SMAX) slist[count + before] = n;
+                if (f && count + before < SMAX) {
+                    slist[count + before] = n;
+                    sflag[n] = count + before + 1;   // slot + 1
+                }
                 if (first < 0 && fm) first = b0 + __ffsll((long long)fm) - 1;
                 count += __popcll(m);
             }
@@ -1014,17 +1026,8 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             q.W = a.white[pix];
             const double* st = a.pstat + ((size_t)tile * 64 + p) * 4;
             // err = A - 2 W inv (S + g_q + Ib) + W^2 inv^2 C_q
-            double A = st[0], var = st[2];
-            const double Ib = st[1];
-            if (EDGE) {
-                // sums over the frames without invalid lookups
-                for (int k = 0; k < nslow; ++k) {
-                    const double I = (double)a.frames[(size_t)slist[k] * HW + pix];
-                    A -= I * I;
-                    var -= (I - Wd) * (I - Wd);
-                }
-                q.vf = var;
-            }
+            const double A = st[0], Ib = st[1], var = st[2];
+            if (EDGE) q.vf = var;
             const double s = (EDGE || var <= 0.0) ? 1.0 : 1.0 / var;
             q.zvar = var > 0.0 ? 0 : 1;
             q.be = -2.0 * Wd * inv * s;
@@ -1061,6 +1064,11 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[m][s] = mm_v4i{0, 0, 0, 0};
         double GU = 0.0, CS = 0.0;
+        if (EDGE) {
+            for (int w = lane; w < 16 * MW; w += 64) imask[w] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int kb = 0; kb < KB; ++kb) {
             // B operand: 16 frames of this lane's position, three biased bytes each;
             // branch-free so that the 32 loads of the 16 frames are in flight together
@@ -1068,11 +1076,62 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             unsigned gsum = 0;
             float2 top[16], bot[16];
             const int nb = kb * MM_KB + 16 * g;
+            // edge tiles: a frame with invalid lookups in the region (slot sl > 0) reads
+            // the corners of its own lookup, clamped into the grid (out-of-grid corners
+            // are masked below), so that its loads join the batch
+            int slot[16], row[16], col[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
-                const unsigned e4 = roff4 - fgo4[nb + t];
+                unsigned e4 = roff4 - fgo4[nb + t];
+                if (EDGE) {
+                    slot[t] = sflag[nb + t];
+                    const int4 si = sinfo[slot[t] > 0 ? slot[t] - 1 : 0];
+                    row[t] = T0 + r - si.x;
+                    col[t] = T1 + cc - si.y;
+                    const int rc = min(max(row[t], 0), a.Rs - 2), ccl = min(max(col[t], 0), Rf - 2);
+                    if (slot[t] > 0) e4 = 4u * (unsigned)(rc * Rf + ccl);
+                }
                 top[t] = *(const float2*)(refb + e4);
                 bot[t] = *(const float2*)(refb + (e4 + rf4));
+            }
+            float vals[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float4 wt = fw[nb + t];
+                vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                if (EDGE && slot[t] > 0) {
+                    // the masked lookup of the paper's interpolation (renormalised over
+                    // the valid corners), as masked_bilinear computes it
+                    const int4 si = sinfo[slot[t] - 1];
+                    const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
+                    const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
+                    const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
+                    // the clamped corners are the real ones whenever those are in the grid
+                    const float v00 = (r0 && c0) ? top[t].x : qnan();
+                    const float v01 = (r0 && c1) ? top[t].y : qnan();
+                    const float v10 = (r1 && c0) ? bot[t].x : qnan();
+                    const float v11 = (r1 && c1) ? bot[t].y : qnan();
+                    float gm;
+                    if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
+                        gm = bilinear4(v00, v01, v10, v11, fa, fb);
+                    } else {
+                        const float ga = 1.f - fa, gb = 1.f - fb;
+                        const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
+                        float num = 0.f, den = 0.f;
+                        if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
+                        if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
+                        if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
+                        if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
+                        gm = den > 0.f ? num / den : qnan();
+                    }
+                    if (valid(gm)) {
+                        vals[t] = gm * fs;
+                    } else {
+                        vals[t] = 0.f;
+                        const int k = slot[t] - 1;
+                        atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                    }
+                }
             }
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
@@ -1080,8 +1139,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int t = 4 * w + b;
-                    const float4 wt = fw[nb + t];
-                    const float v = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                    const float v = vals[t];
                     // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
                     const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
                     const int gt = (int)gu - (1 << 23);
@@ -1138,10 +1196,13 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 }
             }
         } else {
-            // frames without invalid lookups from the products (the cancellation happens
-            // in FP64; the resulting error is kept in FP32 like the terms added to it);
-            // the others term by term
-            float ef[16], es[16], vs[16], Wl[16];
+            // every valid lookup is in the products (an invalid one entered as g = 0, so
+            // its frame added I^2 to the error and (I - W)^2 to the variance); those
+            // terms are taken out again for the invalid (position, frame) pairs, which
+            // only frames with invalid lookups in the region can have.  FP64 where the
+            // subtraction can cancel.
+            double ef[16], ai[16];
+            float vi[16], Wl[16];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
 #pragma unroll
@@ -1150,34 +1211,37 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     const MmPix& P = pp[p];
                     const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
                                      65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                    ef[e] = (float)fma(P.be, S + gq, fma(P.ga, CS, P.al));
-                    es[e] = 0.f;
-                    vs[e] = 0.f;
+                    ef[e] = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                    ai[e] = 0.0;
+                    vi[e] = 0.f;
                     Wl[e] = P.W;
                 }
             }
-            int ns = 0;
-            for (int k = 0; k < nslow; ++k) {
-                const int4 si = sinfo[k];
-                const float gk = masked_bilinear(a.refv, a.Rs, Rf, T0 + r - si.x, T1 + cc - si.y,
-                                                 __int_as_float(si.z), __int_as_float(si.w));
-                if (valid(gk)) {
-                    ++ns;
+            // the invalid (position, slow frame) pairs recorded by the B operand lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int ninv = 0;
+            for (int w = 0; w < MW; ++w) {
+                unsigned bits = imask[c * MW + w];
+                ninv += __popc(bits);
+                while (bits) {
+                    const int k = w * 32 + __ffs(bits) - 1;
+                    bits &= bits - 1u;
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int e = m * 4 + i, p = m * 16 + 4 * g + i;
                             const float I = sI[k * 64 + p];
-                            const float rr = fmaf(-Wl[e], gk, I);
-                            es[e] = fmaf(rr, rr, es[e]);
+                            ai[e] = fma((double)I, (double)I, ai[e]);
                             const float v = I - Wl[e];
-                            vs[e] = fmaf(v, v, vs[e]);
+                            vi[e] = fmaf(v, v, vi[e]);
                         }
                     }
                 }
             }
-            const int nv = (N - nslow) + ns;
+            const int nv = N - ninv;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
 #pragma unroll
@@ -1185,10 +1249,10 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     const int e = m * 4 + i, p = m * 16 + 4 * g + i;
                     const int kx = r - pp[p].dc0, ky = cc - pp[p].dc1;
                     if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY) {
-                        float err = ef[e] + es[e];
-                        err = err > 0.f ? err : 0.f;
-                        const float var = (float)pp[p].vf + vs[e];
-                        ebuf[(size_t)p * NC + kx * NY + ky] = normalised_error(err, var, nv);
+                        double err = ef[e] - ai[e];
+                        err = err > 0.0 ? err : 0.0;
+                        const float var = (float)(pp[p].vf - (double)vi[e]);
+                        ebuf[(size_t)p * NC + kx * NY + ky] = normalised_error((float)err, var, nv);
                     }
                 }
             }
