@@ -121,10 +121,20 @@ __device__ void classify_item(const PmArgs& a, int tile) {
             cls = (bad == 0 && rh * rw <= a.fast_cap) ? CNT_FAST : CNT_EDGE;
         if (lane == 0) a.tiles[tile] = TileDesc{mn0, mn1, (int)rh, (int)rw};
     }
-    if (lane == 0) {
-        const int pos = cls == CNT_GENERIC ? 0 : (int)((rh * rw + 15) / 16 * 16);
-        a.tinfo[tile] = make_int4(cls, ngood, pos, 0);
+    // positions the matrix cores go through, in units of 64 pixels: the region in
+    // blocks of 16, or for tiles taken in halves the two halves' own regions at 32 pixels
+    long long pos = cls == CNT_GENERIC ? 0 : (rh * rw + 15) / 16 * 16;
+    if ((cls == CNT_FAST && (a.mm_on & 1) && (a.mm_on & 16)) || (cls == CNT_EDGE_MM && (a.mm_on & 32))) {
+        pos = 0;
+        for (int h = 0; h < 2; ++h) {
+            const bool in = good && (lane >> 5) == h;
+            const int hn0 = wave_min_i(in ? c0 : INT_MAX), hx0 = wave_max_i(in ? c0 : INT_MIN);
+            const int hn1 = wave_min_i(in ? c1 : INT_MAX), hx1 = wave_max_i(in ? c1 : INT_MIN);
+            if (hn0 <= hx0)
+                pos += ((long long)(hx0 - hn0 + a.NX) * (hx1 - hn1 + a.NY) + 15) / 16 * 8;
+        }
     }
+    if (lane == 0) a.tinfo[tile] = make_int4(cls, ngood, (int)pos, 0);
 }
 
 // Work lists of the classes in tile order and the counters, by one work-group of 1024
@@ -864,35 +874,42 @@ __host__ __device__ inline size_t mm_edge_bytes(int np, int smax) {
     return (size_t)np * 4 + (size_t)smax * (4 + 16 + 64 * 4) + 16 +
            (size_t)MM_WAVES * 16 * mm_mask_words(smax) * 4;
 }
+// LDS of one work-group: error tables of 16 mh pixels | frame table | pixel coefficients
+// | edge extras | staged packed frames.
 __host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_a, bool edge,
-                                               int smax) {
+                                               int smax, int mh) {
     const size_t np = (size_t)mm_frames_padded(n_frames);
-    const size_t e = ((size_t)64 * nc + 3) / 4 * 4 * sizeof(float);
+    const size_t e = ((size_t)16 * mh * nc + 3) / 4 * 4 * sizeof(float);
     const size_t apk = stage_a ? np / MM_KB * MM_PACK_BYTES : 0;
     return e + np * 16 + np * 4 + 64 * sizeof(MmPix) + (edge ? mm_edge_bytes((int)np, smax) : 0) + apk;
 }
 
 // Matrix-core search of one job: whether interior (fast) and edge tiles go to it, whether
-// the packed frames are staged in LDS, and the edge tiles' slow-frame capacity (the
-// largest that fits the LDS, preferring staged frames).  Depends on the job's own
-// window and frame count only.
+// the packed frames are staged in LDS, whether the tiles are searched in two halves of
+// 32 pixels (windows whose error tables of 64 pixels do not fit the LDS), and the edge
+// tiles' slow-frame capacity (the largest that fits the LDS, preferring staged frames).
+// Depends on the job's own window and frame count only.
 constexpr size_t MM_LDS_MAX = 160 * 1024;
 struct MmPlan {
-    bool fast, edge, fast_stage, edge_stage;
+    bool fast, edge, fast_stage, edge_stage, fast_half, edge_half;
     int slow_max;
 };
 MmPlan mm_plan(int nx, int ny, int n_frames) {
     MmPlan p{};
     const int nc = nx * ny;
-    p.fast = mm_lds_bytes(nc, n_frames, false, false, 0) <= MM_LDS_MAX;
-    p.fast_stage = mm_lds_bytes(nc, n_frames, true, false, 0) <= MM_LDS_MAX;
+    p.fast = mm_lds_bytes(nc, n_frames, false, false, 0, 4) <= MM_LDS_MAX;
+    p.fast_stage = mm_lds_bytes(nc, n_frames, true, false, 0, 4) <= MM_LDS_MAX;
+    if (!p.fast && mm_lds_bytes(nc, n_frames, false, false, 0, 2) <= MM_LDS_MAX) {
+        p.fast = true;
+        p.fast_half = true;
+    }
     // capacity: the largest multiple of 32 (keeps the LDS arrays 16-byte aligned) that fits
-    auto cap = [&](bool stage) {
+    auto cap = [&](bool stage, int mh) {
         for (int sm = MM_SLOW_CAP; sm >= 32; sm -= 32)
-            if (mm_lds_bytes(nc, n_frames, stage, true, sm) <= MM_LDS_MAX) return sm;
+            if (mm_lds_bytes(nc, n_frames, stage, true, sm, mh) <= MM_LDS_MAX) return sm;
         return 0;
     };
-    const int s_lds = cap(true), s_glb = cap(false);
+    const int s_lds = cap(true, 4), s_glb = cap(false, 4);
     if (s_lds >= 64 || (s_lds >= MM_SLOW_MIN && s_glb < 64)) {
         p.edge = true;
         p.edge_stage = true;
@@ -901,11 +918,18 @@ MmPlan mm_plan(int nx, int ny, int n_frames) {
         p.edge = true;
         p.edge_stage = false;
         p.slow_max = s_glb;
+    } else {
+        const int s_half = cap(false, 2);
+        if (s_half >= MM_SLOW_MIN) {
+            p.edge = true;
+            p.edge_half = true;
+            p.slow_max = s_half;
+        }
     }
     return p;
 }
 
-template <bool LDSA, bool EDGE>
+template <bool LDSA, bool EDGE, int MH>
 __device__ void pm_mma_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
     const int cnt = EDGE ? CNT_EDGE_MM : CNT_FAST;
@@ -921,7 +945,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 
     const int NP = KB * MM_KB;
     float* ebuf = smem;
-    float4* fw = (float4*)(smem + ((size_t)64 * NC + 3) / 4 * 4);
+    float4* fw = (float4*)(smem + ((size_t)16 * MH * NC + 3) / 4 * 4);
     unsigned* fgo4 = (unsigned*)(fw + NP);   // 4 * (e0 Rf + e1), modulo 2^32
     MmPix* pp = (MmPix*)(fgo4 + NP);
     char* ext = (char*)(pp + 64);
@@ -1047,271 +1071,296 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     const uint4* __restrict__ ipk =
         (LDSA ? (const uint4*)apk : a.ipk + (size_t)tile * KB * (4 * 2 * 64)) + lane;
 
-    for (int nt = wave; nt < NT; nt += MM_WAVES) {
-        const int q = nt * 16 + c;
-        const bool qv = q < Q;
-        // lanes past the region compute the region's last position and discard it
-        const int qc = qv ? q : Q - 1;
-        const int r = qc / RW, cc = qc - r * RW;
-        // byte offset into the reference before the frame shift (every looked-up pixel
-        // lies in the validated rectangle, so offsets are in [0, 4 Rs Rf))
-        const unsigned roff4 = 4u * (unsigned)((T0 + r) * Rf + (T1 + cc));
-        const unsigned rf4 = 4u * (unsigned)Rf;
-        const char* __restrict__ refb = (const char*)a.refv;
-        mm_v4i acc[4][4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc[m][s] = mm_v4i{0, 0, 0, 0};
-        double GU = 0.0, CS = 0.0;
-        if (EDGE) {
-            for (int w = lane; w < 16 * MW; w += 64) imask[w] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+    // the tile's pixels in 4 / MH parts of 16 MH pixels (row groups MH h .. MH h + MH - 1),
+    // each with the region of its own windows and its own error table (every wave
+    // finds the part's region from the pixel table)
+#pragma unroll 1
+    for (int h = 0; h < 4 / MH; ++h) {
+        int h0 = 0, h1 = 0, RWh = RW, Qh = Q;
+        if (MH < 4) {
+            const bool in = (lane >> 4) / MH == h && pp[lane].good;
+            const int mn0 = wave_min_i(in ? pp[lane].dc0 : INT_MAX);
+            const int mx0 = wave_max_i(in ? pp[lane].dc0 : INT_MIN);
+            const int mn1 = wave_min_i(in ? pp[lane].dc1 : INT_MAX);
+            const int mx1 = wave_max_i(in ? pp[lane].dc1 : INT_MIN);
+            const bool any_good = mn0 <= mx0;
+            h0 = any_good ? mn0 : 0;
+            h1 = any_good ? mn1 : 0;
+            RWh = any_good ? mx1 - mn1 + NY : 1;
+            Qh = any_good ? (mx0 - mn0 + NX) * RWh : 0;
         }
-        for (int kb = 0; kb < KB; ++kb) {
-            // B operand: 16 frames of this lane's position, three biased bytes each;
-            // branch-free so that the 32 loads of the 16 frames are in flight together
-            unsigned B0[4], B1[4], B2[4];
-            unsigned gsum = 0;
-            float2 top[16], bot[16];
-            const int nb = kb * MM_KB + 16 * g;
-            // edge tiles: a frame with invalid lookups in the region (slot sl > 0) reads
-            // the corners of its own lookup, clamped into the grid (out-of-grid corners
-            // are masked below), so that its loads join the batch
-            int slot[16], row[16], col[16];
+        const int NTh = (Qh + 15) >> 4;
+
+        for (int nt = wave; nt < NTh; nt += MM_WAVES) {
+            const int q = nt * 16 + c;
+            const bool qv = q < Qh;
+            // lanes past the region compute the region's last position and discard it;
+            // (r, cc) are coordinates in the region of the whole tile
+            const int qc = qv ? q : Qh - 1;
+            const int rq = qc / RWh;
+            const int r = rq + h0, cc = qc - rq * RWh + h1;
+            // byte offset into the reference before the frame shift (every looked-up pixel
+            // lies in the validated rectangle, so offsets are in [0, 4 Rs Rf))
+            const unsigned roff4 = 4u * (unsigned)((T0 + r) * Rf + (T1 + cc));
+            const unsigned rf4 = 4u * (unsigned)Rf;
+            const char* __restrict__ refb = (const char*)a.refv;
+            mm_v4i acc[MH][4];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                unsigned e4 = roff4 - fgo4[nb + t];
-                if (EDGE) {
-                    slot[t] = sflag[nb + t];
-                    const int4 si = sinfo[slot[t] > 0 ? slot[t] - 1 : 0];
-                    row[t] = T0 + r - si.x;
-                    col[t] = T1 + cc - si.y;
-                    const int rc = min(max(row[t], 0), a.Rs - 2), ccl = min(max(col[t], 0), Rf - 2);
-                    if (slot[t] > 0) e4 = 4u * (unsigned)(rc * Rf + ccl);
-                }
-                top[t] = *(const float2*)(refb + e4);
-                bot[t] = *(const float2*)(refb + (e4 + rf4));
+            for (int m = 0; m < MH; ++m)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[m][s] = mm_v4i{0, 0, 0, 0};
+            double GU = 0.0, CS = 0.0;
+            if (EDGE) {
+                for (int w = lane; w < 16 * MW; w += 64) imask[w] = 0u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            float vals[16];
+            for (int kb = 0; kb < KB; ++kb) {
+                // B operand: 16 frames of this lane's position, three biased bytes each;
+                // branch-free so that the 32 loads of the 16 frames are in flight together
+                unsigned B0[4], B1[4], B2[4];
+                unsigned gsum = 0;
+                float2 top[16], bot[16];
+                const int nb = kb * MM_KB + 16 * g;
+                // edge tiles: a frame with invalid lookups in the region (slot sl > 0) reads
+                // the corners of its own lookup, clamped into the grid (out-of-grid corners
+                // are masked below), so that its loads join the batch
+                int slot[16], row[16], col[16];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const float4 wt = fw[nb + t];
-                vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
-                if (EDGE && slot[t] > 0) {
-                    // the masked lookup of the paper's interpolation (renormalised over
-                    // the valid corners), as masked_bilinear computes it
-                    const int4 si = sinfo[slot[t] - 1];
-                    const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
-                    const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
-                    const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
-                    // the clamped corners are the real ones whenever those are in the grid
-                    const float v00 = (r0 && c0) ? top[t].x : qnan();
-                    const float v01 = (r0 && c1) ? top[t].y : qnan();
-                    const float v10 = (r1 && c0) ? bot[t].x : qnan();
-                    const float v11 = (r1 && c1) ? bot[t].y : qnan();
-                    float gm;
-                    if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
-                        gm = bilinear4(v00, v01, v10, v11, fa, fb);
-                    } else {
-                        const float ga = 1.f - fa, gb = 1.f - fb;
-                        const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
-                        float num = 0.f, den = 0.f;
-                        if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
-                        if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
-                        if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
-                        if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
-                        gm = den > 0.f ? num / den : qnan();
+                for (int t = 0; t < 16; ++t) {
+                    unsigned e4 = roff4 - fgo4[nb + t];
+                    if (EDGE) {
+                        slot[t] = sflag[nb + t];
+                        const int4 si = sinfo[slot[t] > 0 ? slot[t] - 1 : 0];
+                        row[t] = T0 + r - si.x;
+                        col[t] = T1 + cc - si.y;
+                        const int rc = min(max(row[t], 0), a.Rs - 2), ccl = min(max(col[t], 0), Rf - 2);
+                        if (slot[t] > 0) e4 = 4u * (unsigned)(rc * Rf + ccl);
                     }
-                    if (valid(gm)) {
-                        vals[t] = gm * fs;
-                    } else {
-                        vals[t] = 0.f;
-                        const int k = slot[t] - 1;
-                        atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                    top[t] = *(const float2*)(refb + e4);
+                    bot[t] = *(const float2*)(refb + (e4 + rf4));
+                }
+                float vals[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const float4 wt = fw[nb + t];
+                    vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                    if (EDGE && slot[t] > 0) {
+                        // the masked lookup of the paper's interpolation (renormalised over
+                        // the valid corners), as masked_bilinear computes it
+                        const int4 si = sinfo[slot[t] - 1];
+                        const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
+                        const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
+                        const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
+                        // the clamped corners are the real ones whenever those are in the grid
+                        const float v00 = (r0 && c0) ? top[t].x : qnan();
+                        const float v01 = (r0 && c1) ? top[t].y : qnan();
+                        const float v10 = (r1 && c0) ? bot[t].x : qnan();
+                        const float v11 = (r1 && c1) ? bot[t].y : qnan();
+                        float gm;
+                        if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
+                            gm = bilinear4(v00, v01, v10, v11, fa, fb);
+                        } else {
+                            const float ga = 1.f - fa, gb = 1.f - fb;
+                            const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
+                            float num = 0.f, den = 0.f;
+                            if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
+                            if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
+                            if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
+                            if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
+                            gm = den > 0.f ? num / den : qnan();
+                        }
+                        if (valid(gm)) {
+                            vals[t] = gm * fs;
+                        } else {
+                            vals[t] = 0.f;
+                            const int k = slot[t] - 1;
+                            atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                unsigned u[4];
+                for (int w = 0; w < 4; ++w) {
+                    unsigned u[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int t = 4 * w + b;
-                    const float v = vals[t];
-                    // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
-                    const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
-                    const int gt = (int)gu - (1 << 23);
-                    CS = fma((double)gt, (double)gt, CS);
-                    gsum += gu;
-                    u[b] = gu;
+                    for (int b = 0; b < 4; ++b) {
+                        const int t = 4 * w + b;
+                        const float v = vals[t];
+                        // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
+                        const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
+                        const int gt = (int)gu - (1 << 23);
+                        CS = fma((double)gt, (double)gt, CS);
+                        gsum += gu;
+                        u[b] = gu;
+                    }
+                    const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
+                    const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
+                    const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
+                    const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
+                    B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
+                    B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
+                    B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
                 }
-                const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
-                const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
-                const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
-                const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
-                B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
-                B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
-                B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
-            }
-            GU += (double)gsum;
-            const mm_v4i b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
-            const mm_v4i b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
-            const mm_v4i b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
-            const uint4* ak = ipk + (size_t)kb * (4 * 2 * 64);
+                GU += (double)gsum;
+                const mm_v4i b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
+                const mm_v4i b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
+                const mm_v4i b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
+                const uint4* ak = ipk + (size_t)kb * (4 * 2 * 64);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const mm_v4i a0 = mm_as_v4i(ak[(m * 2) * 64]);
-                const mm_v4i a1 = mm_as_v4i(ak[(m * 2 + 1) * 64]);
-                acc[m][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[m][0], 0, 0, 0);
-                acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[m][1], 0, 0, 0);
-                acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[m][1], 0, 0, 0);
-                acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b2, acc[m][2], 0, 0, 0);
-                acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[m][2], 0, 0, 0);
-                acc[m][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b2, acc[m][3], 0, 0, 0);
-            }
-        }
-        // column sums of the position over the four lane groups (same sum in all four)
-        GU += __shfl_xor(GU, 16, 64);
-        GU += __shfl_xor(GU, 32, 64);
-        CS += __shfl_xor(CS, 16, 64);
-        CS += __shfl_xor(CS, 32, 64);
-        const double gq = 128.0 * 257.0 * GU - kconst;
-        if (!EDGE) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int p = m * 16 + 4 * g + i;
-                    const MmPix P = pp[p];
-                    const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
-                                     65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                    double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
-                    v = v > 0.0 ? v : 0.0;
-                    const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
-                    const int kx = r - P.dc0, ky = cc - P.dc1;
-                    if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
-                        ebuf[(size_t)p * NC + kx * NY + ky] = E;
+                for (int m = 0; m < MH; ++m) {
+                    const int mg = h * MH + m;   // row group of the tile
+                    const mm_v4i a0 = mm_as_v4i(ak[(mg * 2) * 64]);
+                    const mm_v4i a1 = mm_as_v4i(ak[(mg * 2 + 1) * 64]);
+                    acc[m][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[m][0], 0, 0, 0);
+                    acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[m][1], 0, 0, 0);
+                    acc[m][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[m][1], 0, 0, 0);
+                    acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b2, acc[m][2], 0, 0, 0);
+                    acc[m][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[m][2], 0, 0, 0);
+                    acc[m][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b2, acc[m][3], 0, 0, 0);
                 }
             }
-        } else {
-            // every valid lookup is in the products (an invalid one entered as g = 0, so
-            // its frame added I^2 to the error and (I - W)^2 to the variance); those
-            // terms are taken out again for the invalid (position, frame) pairs, which
-            // only frames with invalid lookups in the region can have.  FP64 where the
-            // subtraction can cancel.
-            double ef[16], ai[16];
-            float vi[16], Wl[16];
+            // column sums of the position over the four lane groups (same sum in all four)
+            GU += __shfl_xor(GU, 16, 64);
+            GU += __shfl_xor(GU, 32, 64);
+            CS += __shfl_xor(CS, 16, 64);
+            CS += __shfl_xor(CS, 32, 64);
+            const double gq = 128.0 * 257.0 * GU - kconst;
+            if (!EDGE) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+                for (int m = 0; m < MH; ++m) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int e = m * 4 + i, p = m * 16 + 4 * g + i;
-                    const MmPix& P = pp[p];
-                    const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
-                                     65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                    ef[e] = fma(P.be, S + gq, fma(P.ga, CS, P.al));
-                    ai[e] = 0.0;
-                    vi[e] = 0.f;
-                    Wl[e] = P.W;
+                    for (int i = 0; i < 4; ++i) {
+                        const int pl = m * 16 + 4 * g + i, p = h * MH * 16 + pl;
+                        const MmPix P = pp[p];
+                        const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                                         65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
+                        double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                        v = v > 0.0 ? v : 0.0;
+                        const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
+                        const int kx = r - P.dc0, ky = cc - P.dc1;
+                        if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
+                            ebuf[(size_t)pl * NC + kx * NY + ky] = E;
+                    }
                 }
-            }
-            // the invalid (position, slow frame) pairs recorded by the B operand lanes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            int ninv = 0;
-            for (int w = 0; w < MW; ++w) {
-                unsigned bits = imask[c * MW + w];
-                ninv += __popc(bits);
-                while (bits) {
-                    const int k = w * 32 + __ffs(bits) - 1;
-                    bits &= bits - 1u;
+            } else {
+                // every valid lookup is in the products (an invalid one entered as g = 0, so
+                // its frame added I^2 to the error and (I - W)^2 to the variance); those
+                // terms are taken out again for the invalid (position, frame) pairs, which
+                // only frames with invalid lookups in the region can have.  FP64 where the
+                // subtraction can cancel.
+                double ef[4 * MH], ai[4 * MH];
+                float vi[4 * MH], Wl[4 * MH];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
+                for (int m = 0; m < MH; ++m) {
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int e = m * 4 + i, p = m * 16 + 4 * g + i;
-                            const float I = sI[k * 64 + p];
-                            ai[e] = fma((double)I, (double)I, ai[e]);
-                            const float v = I - Wl[e];
-                            vi[e] = fmaf(v, v, vi[e]);
+                    for (int i = 0; i < 4; ++i) {
+                        const int e = m * 4 + i, p = h * MH * 16 + m * 16 + 4 * g + i;
+                        const MmPix& P = pp[p];
+                        const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
+                                         65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
+                        ef[e] = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                        ai[e] = 0.0;
+                        vi[e] = 0.f;
+                        Wl[e] = P.W;
+                    }
+                }
+                // the invalid (position, slow frame) pairs recorded by the B operand lanes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                int ninv = 0;
+                for (int w = 0; w < MW; ++w) {
+                    unsigned bits = imask[c * MW + w];
+                    ninv += __popc(bits);
+                    while (bits) {
+                        const int k = w * 32 + __ffs(bits) - 1;
+                        bits &= bits - 1u;
+#pragma unroll
+                        for (int m = 0; m < MH; ++m) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const int e = m * 4 + i, p = h * MH * 16 + m * 16 + 4 * g + i;
+                                const float I = sI[k * 64 + p];
+                                ai[e] = fma((double)I, (double)I, ai[e]);
+                                const float v = I - Wl[e];
+                                vi[e] = fmaf(v, v, vi[e]);
+                            }
+                        }
+                    }
+                }
+                const int nv = N - ninv;
+#pragma unroll
+                for (int m = 0; m < MH; ++m) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int e = m * 4 + i, pl = m * 16 + 4 * g + i, p = h * MH * 16 + pl;
+                        const int kx = r - pp[p].dc0, ky = cc - pp[p].dc1;
+                        if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY) {
+                            double err = ef[e] - ai[e];
+                            err = err > 0.0 ? err : 0.0;
+                            const float var = (float)(pp[p].vf - (double)vi[e]);
+                            ebuf[(size_t)pl * NC + kx * NY + ky] = normalised_error((float)err, var, nv);
                         }
                     }
                 }
             }
-            const int nv = N - ninv;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int e = m * 4 + i, p = m * 16 + 4 * g + i;
-                    const int kx = r - pp[p].dc0, ky = cc - pp[p].dc1;
-                    if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY) {
-                        double err = ef[e] - ai[e];
-                        err = err > 0.0 ? err : 0.0;
-                        const float var = (float)(pp[p].vf - (double)vi[e]);
-                        ebuf[(size_t)p * NC + kx * NY + ky] = normalised_error((float)err, var, nv);
-                    }
-                }
-            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // first minimum per pixel (8 lanes per pixel), then refinement and output
-    {
-        const int p = tid >> 3, sub = tid & 7;
-        const MmPix P = pp[p];
-        float be = INFINITY;
-        int bk = INT_MAX;
-        if (P.good) {
-            const float* e = ebuf + (size_t)p * NC;
-            for (int k = sub; k < NC; k += 8) {
-                const float v = e[k];
-                if (better(v, k, be, bk)) {
-                    be = v;
-                    bk = k;
-                }
-            }
-        }
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            const float e2 = __shfl_xor(be, o, 64);
-            const int k2 = __shfl_xor(bk, o, 64);
-            if (better(e2, k2, be, bk)) {
-                be = e2;
-                bk = k2;
-            }
-        }
-        const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
-        if (sub == 0 && i < a.H && j < a.W) {
-            const size_t pix = (size_t)i * a.W + j;
-            if (!P.good || !isfinite(be)) {
-                write_unchanged(a, pix, HW);
-            } else {
-                const int bx = bk / NY, by = bk - bx * NY;
-                float ox = 0.f, oy = 0.f;
-                if (a.refine) {
-                    float st[9];
-                    const float* e = ebuf + (size_t)p * NC;
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) {
-                        const int kx = bx + t / 3 - 1, ky = by + t % 3 - 1;
-                        st[t] = (kx >= 0 && kx < NX && ky >= 0 && ky < NY) ? e[kx * NY + ky] : INFINITY;
+        // first minimum per pixel (TPP lanes per pixel), then refinement and output
+        {
+            constexpr int TPP = MM_THREADS / (16 * MH);
+            const int pl = tid / TPP, sub = tid % TPP, p = h * MH * 16 + pl;
+            const MmPix P = pp[p];
+            float be = INFINITY;
+            int bk = INT_MAX;
+            if (P.good) {
+                const float* e = ebuf + (size_t)pl * NC;
+                for (int k = sub; k < NC; k += TPP) {
+                    const float v = e[k];
+                    if (better(v, k, be, bk)) {
+                        be = v;
+                        bk = k;
                     }
-                    refine_at(st, bx, by, NX, NY, ox, oy);
                 }
-                const int c0 = P.dc0 + td.cmin0, c1 = P.dc1 + td.cmin1;
-                a.u_out[pix] = (float)(c0 + bx - a.rx) + ox;
-                a.u_out[HW + pix] = (float)(c1 + by - a.ry) + oy;
-                if (a.err_out) a.err_out[pix] = be;
-                if (a.arg_out) a.arg_out[pix] = bk;
+            }
+#pragma unroll
+            for (int o = 1; o < TPP; o <<= 1) {
+                const float e2 = __shfl_xor(be, o, 64);
+                const int k2 = __shfl_xor(bk, o, 64);
+                if (better(e2, k2, be, bk)) {
+                    be = e2;
+                    bk = k2;
+                }
+            }
+            const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+            if (sub == 0 && i < a.H && j < a.W) {
+                const size_t pix = (size_t)i * a.W + j;
+                if (!P.good || !isfinite(be)) {
+                    write_unchanged(a, pix, HW);
+                } else {
+                    const int bx = bk / NY, by = bk - bx * NY;
+                    float ox = 0.f, oy = 0.f;
+                    if (a.refine) {
+                        float st[9];
+                        const float* e = ebuf + (size_t)pl * NC;
+#pragma unroll
+                        for (int t = 0; t < 9; ++t) {
+                            const int kx = bx + t / 3 - 1, ky = by + t % 3 - 1;
+                            st[t] = (kx >= 0 && kx < NX && ky >= 0 && ky < NY) ? e[kx * NY + ky] : INFINITY;
+                        }
+                        refine_at(st, bx, by, NX, NY, ox, oy);
+                    }
+                    const int c0 = P.dc0 + td.cmin0, c1 = P.dc1 + td.cmin1;
+                    a.u_out[pix] = (float)(c0 + bx - a.rx) + ox;
+                    a.u_out[HW + pix] = (float)(c1 + by - a.ry) + oy;
+                    if (a.err_out) a.err_out[pix] = be;
+                    if (a.arg_out) a.arg_out[pix] = bk;
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // ------------------------------------------------------------------------ wrappers
@@ -1342,14 +1391,18 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
 
 PXST_WRAP(k_classify, 64, classify_item)
 PXST_WRAP(k_pm_generic, 256, pm_generic_item)
-__device__ void pm_mma_fast_lds(const PmArgs& a, int slot) { pm_mma_item<true, false>(a, slot); }
-__device__ void pm_mma_fast_glb(const PmArgs& a, int slot) { pm_mma_item<false, false>(a, slot); }
-__device__ void pm_mma_edge_lds(const PmArgs& a, int slot) { pm_mma_item<true, true>(a, slot); }
-__device__ void pm_mma_edge_glb(const PmArgs& a, int slot) { pm_mma_item<false, true>(a, slot); }
+__device__ void pm_mma_fast_lds(const PmArgs& a, int slot) { pm_mma_item<true, false, 4>(a, slot); }
+__device__ void pm_mma_fast_glb(const PmArgs& a, int slot) { pm_mma_item<false, false, 4>(a, slot); }
+__device__ void pm_mma_edge_lds(const PmArgs& a, int slot) { pm_mma_item<true, true, 4>(a, slot); }
+__device__ void pm_mma_edge_glb(const PmArgs& a, int slot) { pm_mma_item<false, true, 4>(a, slot); }
+__device__ void pm_mma_fast_half(const PmArgs& a, int slot) { pm_mma_item<false, false, 2>(a, slot); }
+__device__ void pm_mma_edge_half(const PmArgs& a, int slot) { pm_mma_item<false, true, 2>(a, slot); }
 PXST_WRAP(k_pm_mma_lds, MM_THREADS, pm_mma_fast_lds)
 PXST_WRAP(k_pm_mma_glb, MM_THREADS, pm_mma_fast_glb)
 PXST_WRAP(k_pm_mma_edge_lds, MM_THREADS, pm_mma_edge_lds)
 PXST_WRAP(k_pm_mma_edge_glb, MM_THREADS, pm_mma_edge_glb)
+PXST_WRAP(k_pm_mma_half, MM_THREADS, pm_mma_fast_half)
+PXST_WRAP(k_pm_mma_edge_half, MM_THREADS, pm_mma_edge_half)
 
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
@@ -1506,33 +1559,48 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     a.fscale = (const int*)(ws + L.fscale);
     a.kblocks = L.kblocks;
     const MmPlan mp = mm_plan(a.NX, a.NY, g.N);
-    a.mm_on = (mp.fast ? 1 : 0) | (mp.edge ? 2 : 0) | (mp.fast_stage ? 4 : 0) | (mp.edge_stage ? 8 : 0);
+    a.mm_on = (mp.fast ? 1 : 0) | (mp.edge ? 2 : 0) | (mp.fast_stage ? 4 : 0) | (mp.edge_stage ? 8 : 0) |
+              (mp.fast_half ? 16 : 0) | (mp.edge_half ? 32 : 0);
     a.mm_slow_max = mp.slow_max;
     return a;
 }
 
 // One launch of the matrix-core search (interior or edge tiles) for one job
 // (dev_jobs == nullptr: host_args[0] is passed by value) or a batch of jobs with the
-// same window and the same kernel choice (their host-side arguments in host_args).
+// same window and the same kernel choice (their host-side arguments in host_args; all
+// of them search whole tiles or all of them halves).
 // The frames are staged in LDS when every job of the launch stages them; the LDS size
 // is the largest any job needs.
 int launch_mma(const PmArgs* host_args, int nargs, const PmArgs* dev_jobs, const int* off, int grid,
                bool edge, hipStream_t s) {
-    bool stage = true;
-    for (int j = 0; j < nargs; ++j) stage = stage && (host_args[j].mm_on & (edge ? 8 : 4)) != 0;
+    const bool half = (host_args[0].mm_on & (edge ? 32 : 16)) != 0;
+    bool stage = !half;
+    for (int j = 0; j < nargs; ++j) {
+        stage = stage && (host_args[j].mm_on & (edge ? 8 : 4)) != 0;
+        if (((host_args[j].mm_on & (edge ? 32 : 16)) != 0) != half) {
+            set_error("matrix-core search: jobs of one launch differ in tile halves");
+            return PXST_EINVAL;
+        }
+    }
     size_t sh = 0;
     for (int j = 0; j < nargs; ++j) {
         const PmArgs& x = host_args[j];
-        sh = std::max(sh, mm_lds_bytes(x.NX * x.NY, x.N, stage, edge, x.mm_slow_max));
+        sh = std::max(sh, mm_lds_bytes(x.NX * x.NY, x.N, stage, edge, x.mm_slow_max, half ? 2 : 4));
+    }
+    if (sh > MM_LDS_MAX) {
+        set_error("matrix-core search: %zu bytes of LDS exceed the limit", sh);
+        return PXST_EINVAL;
     }
     if (dev_jobs == nullptr) {
-        const PmKernel kern = edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
-                                   : (stage ? k_pm_mma_lds : k_pm_mma_glb);
+        const PmKernel kern = half ? (edge ? k_pm_mma_edge_half : k_pm_mma_half)
+                              : edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
+                                     : (stage ? k_pm_mma_lds : k_pm_mma_glb);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, host_args[0]);
     } else {
-        const PmBatchKernel kern = edge ? (stage ? k_pm_mma_edge_lds_batch : k_pm_mma_edge_glb_batch)
-                                        : (stage ? k_pm_mma_lds_batch : k_pm_mma_glb_batch);
+        const PmBatchKernel kern = half ? (edge ? k_pm_mma_edge_half_batch : k_pm_mma_half_batch)
+                                   : edge ? (stage ? k_pm_mma_edge_lds_batch : k_pm_mma_edge_glb_batch)
+                                          : (stage ? k_pm_mma_lds_batch : k_pm_mma_glb_batch);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, dev_jobs, off, nargs);
     }

@@ -13,7 +13,7 @@ import pytest
 import oracle
 import paper_2003_12726_amd as pxst
 from synth import make_scan, spec_for, random_small_scan, exact_scan, CONFIGS
-from synth.scans import cached_scan
+from synth.scans import ScanSpec, cached_scan
 from gpu_util import (dev_scan, to_dev, empty, ref_rel_error, compare_argmin, emin_bound, U_TOL_PX,
                       REF_TOL_REL, ERR_TOL_REL)
 
@@ -198,6 +198,36 @@ def test_pixel_map_large_window_ragged():
     s = random_small_scan(det=(33, 45), n_frames=5, seed=25, window=(15, 15))
     ref, w = oracle_state(s)
     check_pixel_map(s, ref, w, s.dx0, s.u0, (15, 15), True, label="ragged R=15")
+
+
+@pytest.mark.parametrize("r,n_frames,mask", [(13, 49, "ones"), (15, 150, "parity")])
+def test_pixel_map_large_window_tile_halves(r, n_frames, mask):
+    """Windows whose error tables of a whole 8x8 tile do not fit the LDS (31x31 and
+    27x27 candidates): the matrix-core search takes each tile as two halves of 32
+    pixels, interior and edge tiles alike.  Served-stream job shape (128x128, speckle
+    reference, Gaussian white field); sampled pixels plus the detector's corners."""
+    gx = int(np.ceil(np.sqrt(n_frames)))
+    spec = ScanSpec(name=f"halves{r}", det=(128, 128), n_grid=(gx, int(np.ceil(n_frames / gx))),
+                    step=4.0, jitter=0.5, disp_ss=(float(r), r / 2.0), disp_fs=(float(r), r / 2.0),
+                    window=(r, r), iters=1, ref=None, ref_sigma=1.5, ref_contrast=0.15, white="gauss",
+                    white_sigma=64.0, white_mean=4000.0, refine=True, n_frames=n_frames, seed=77 + r)
+    s = make_scan(spec, mask=mask)
+    ref, w = oracle_state(s)
+    rng = np.random.default_rng(103)
+    rows = np.concatenate([rng.integers(0, 128, 160), [0, 0, 127, 127, 64]])
+    cols = np.concatenate([rng.integers(0, 128, 160), [0, 127, 0, 127, 64]])
+    pxst.profile_enable(True)
+    try:
+        for fam in ("pm_fast_int8_ops", "pm_edge_mma", "pm_edge"):
+            pxst.profile_read(fam)
+        check_pixel_map(s, ref, w, s.dx0, s.u0, (r, r), True, pixels=(rows, cols),
+                        label=f"tile halves R={r}")
+        _, n_fast, ops = pxst.profile_read("pm_fast_int8_ops")
+        _, n_edge, _ = pxst.profile_read("pm_edge_mma")
+    finally:
+        pxst.profile_enable(False)
+    # both matrix-core launches ran, and interior tiles were searched on them
+    assert n_fast == 1 and ops > 0 and n_edge == 1
 
 
 def test_pixel_map_in_place_and_all_masked():
