@@ -178,7 +178,7 @@ Layout make_layout(const Geom& g, int tr_ct) {
     L.fscale = take(sizeof(int));
     const size_t nblk_tr = (HW + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK;
     L.tr_part = take((size_t)g.N * nblk_tr * (tr_ct > 0 ? tr_ct : 1) * 3 * sizeof(float));
-    const size_t per_err = (size_t)ERR_THREADS * ERR_PIX_PER_THREAD_CFG;
+    const size_t per_err = (size_t)ERR_THREADS;
     const size_t nblk_err = (HW + per_err - 1) / per_err;
     L.err_part = take((size_t)g.N * nblk_err * sizeof(double));
     L.err_pix = take((size_t)g.N * sizeof(double) + sizeof(double));

@@ -13,8 +13,6 @@ namespace pxst {
 
 namespace {
 
-constexpr int ERR_PIX_PER_THREAD = ERR_PIX_PER_THREAD_CFG;
-
 __global__ void k_sigma2(const uint16_t* __restrict__ frames, const float* __restrict__ white,
                          const uint8_t* __restrict__ mask, int N, size_t HW, float* __restrict__ s2) {
     const size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,57 +47,118 @@ struct ErrArgs {
     int N, H, W, Rs, Rf, o0, o1, nblk;
 };
 
+// Lookup of Sec. 4 from four corner values (NaN: invalid or outside the grid).
+__device__ inline float masked_bilinear4(float v00, float v01, float v10, float v11, float fa, float fb) {
+    if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
+        const float h0 = fmaf(fb, v01 - v00, v00);
+        const float h1 = fmaf(fb, v11 - v10, v10);
+        return fmaf(fa, h1 - h0, h0);
+    }
+    const float ga = 1.f - fa, gb = 1.f - fb;
+    const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
+    float num = 0.f, den = 0.f;
+    if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
+    if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
+    if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
+    if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
+    return den > 0.f ? num / den : qnan();
+}
+
+// Sums of ERR_FB per-lane values over the wave, fixed order: three exchange steps that
+// each halve the values a lane keeps (lane bit 5, 4, 3 picks the half), then three
+// plain steps over lane bits 2, 1, 0.  Lane l ends with the sum of value
+// 4 b5 + 2 b4 + b3 (b = bits of l).
+constexpr int ERR_FB = 8;
+__device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
+#pragma unroll
+    for (int st = 0; st < 3; ++st) {
+        const int off = 32 >> st, half = ERR_FB >> (st + 1);
+        const bool hi = (lane & off) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const double send = hi ? v[k] : v[k + half];
+            const double keep = hi ? v[k + half] : v[k];
+            v[k] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    double r = v[0];
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+    return r;
+}
+
+// One thread per pixel; frames in groups of ERR_FB whose loads are all issued before
+// the group is evaluated.  Per-frame sums of the wave go to LDS, then one partial per
+// block and frame to the workspace.
 __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
     extern __shared__ double wsum_sh[];   // [N][waves]
     constexpr int WAVES = ERR_THREADS / 64;
     const size_t HW = (size_t)a.H * a.W;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    size_t pix[ERR_PIX_PER_THREAD];
-    bool use[ERR_PIX_PER_THREAD];
-    float Wp[ERR_PIX_PER_THREAD], s2[ERR_PIX_PER_THREAD], u0[ERR_PIX_PER_THREAD],
-        u1[ERR_PIX_PER_THREAD];
-    float pS[ERR_PIX_PER_THREAD], pC[ERR_PIX_PER_THREAD];
+    const size_t pix = (size_t)blockIdx.x * ERR_THREADS + threadIdx.x;
+    const bool inb = pix < HW;
+    const size_t pc = inb ? pix : 0;
+    const bool use = inb && a.mask[pc] != 0 && a.s2[pc] > 0.f;
+    const float Wp = a.white[pc];
+    const float s2 = a.s2[pc];
+    const float u0 = a.u[pc], u1 = a.u[HW + pc];
+    const float f0 = floorf(u0), f1 = floorf(u1);
+    const float fu0 = u0 - f0, fu1 = u1 - f1;
+    const int i0 = (int)f0 - a.o0, i1 = (int)f1 - a.o1;
+    float pS = 0.f, pC = 0.f;
+    for (int n0 = 0; n0 < a.N; n0 += ERR_FB) {
+        float v[ERR_FB][4], I[ERR_FB], fa[ERR_FB], fb[ERR_FB];
+        unsigned ok[ERR_FB];
 #pragma unroll
-    for (int m = 0; m < ERR_PIX_PER_THREAD; ++m) {
-        pix[m] = ((size_t)blockIdx.x * ERR_PIX_PER_THREAD + m) * ERR_THREADS + threadIdx.x;
-        const bool inb = pix[m] < HW;
-        use[m] = inb && a.mask[pix[m]] != 0 && a.s2[pix[m]] > 0.f;
-        Wp[m] = inb ? a.white[pix[m]] : 0.f;
-        s2[m] = inb ? a.s2[pix[m]] : 1.f;
-        u0[m] = inb ? a.u[pix[m]] : 0.f;
-        u1[m] = inb ? a.u[HW + pix[m]] : 0.f;
-        pS[m] = 0.f;
-        pC[m] = 0.f;
-    }
-    for (int n = 0; n < a.N; ++n) {
-        const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
-        const float sd0 = floorf(d0), sd1 = floorf(d1);
-        const float fd0 = d0 - sd0, fd1 = d1 - sd1;
-        double fsum = 0.0;
+        for (int t = 0; t < ERR_FB; ++t) {
+            const int n = min(n0 + t, a.N - 1);
+            const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+            const float sd0 = floorf(d0), sd1 = floorf(d1);
+            const float t0 = fu0 - (d0 - sd0), t1 = fu1 - (d1 - sd1);
+            const int r = i0 - (int)sd0 - (t0 < 0.f ? 1 : 0);
+            const int c = i1 - (int)sd1 - (t1 < 0.f ? 1 : 0);
+            fa[t] = t0 < 0.f ? t0 + 1.f : t0;
+            fb[t] = t1 < 0.f ? t1 + 1.f : t1;
+            // corner flags: bit 0 row r, bit 1 row r + 1, bit 2 column c, bit 3 column c + 1
+            ok[t] = ((unsigned)r < (unsigned)a.Rs ? 1u : 0u) | ((unsigned)(r + 1) < (unsigned)a.Rs ? 2u : 0u) |
+                    ((unsigned)c < (unsigned)a.Rf ? 4u : 0u) | ((unsigned)(c + 1) < (unsigned)a.Rf ? 8u : 0u);
+            const int ra = min(max(r, 0), a.Rs - 1), rb = min(max(r + 1, 0), a.Rs - 1);
+            const int ca = min(max(c, 0), a.Rf - 1), cb = min(max(c + 1, 0), a.Rf - 1);
+            v[t][0] = a.refv[(size_t)ra * a.Rf + ca];
+            v[t][1] = a.refv[(size_t)ra * a.Rf + cb];
+            v[t][2] = a.refv[(size_t)rb * a.Rf + ca];
+            v[t][3] = a.refv[(size_t)rb * a.Rf + cb];
+            I[t] = (float)a.frames[(size_t)n * HW + pc];
+        }
+        double e[ERR_FB];
 #pragma unroll
-        for (int m = 0; m < ERR_PIX_PER_THREAD; ++m) {
-            if (!use[m]) continue;
-            const float f0 = floorf(u0[m]), f1 = floorf(u1[m]);
-            const float t0 = (u0[m] - f0) - fd0, t1 = (u1[m] - f1) - fd1;
-            const int a0 = (int)f0 - (int)sd0 - a.o0 - (t0 < 0.f ? 1 : 0);
-            const int b0 = (int)f1 - (int)sd1 - a.o1 - (t1 < 0.f ? 1 : 0);
-            const float g = masked_bilinear(a.refv, a.Rs, a.Rf, a0, b0, t0 < 0.f ? t0 + 1.f : t0,
-                                            t1 < 0.f ? t1 + 1.f : t1);
-            if (valid(g)) {
-                const float rr = fmaf(-Wp[m], g, (float)a.frames[(size_t)n * HW + pix[m]]);
-                const float eps = rr * rr / s2[m];
-                kahan_add(pS[m], pC[m], eps);
-                fsum += (double)eps;
+        for (int t = 0; t < ERR_FB; ++t) {
+            float g;
+            if (__builtin_expect(ok[t] == 15u && valid(v[t][0]) && valid(v[t][1]) && valid(v[t][2]) &&
+                                     valid(v[t][3]), 1)) {
+                const float h0 = fmaf(fb[t], v[t][1] - v[t][0], v[t][0]);
+                const float h1 = fmaf(fb[t], v[t][3] - v[t][2], v[t][2]);
+                g = fmaf(fa[t], h1 - h0, h0);
+            } else {
+                const unsigned k = ok[t];
+                const float q = qnan();
+                g = masked_bilinear4((k & 5u) == 5u ? v[t][0] : q, (k & 9u) == 9u ? v[t][1] : q,
+                                     (k & 6u) == 6u ? v[t][2] : q, (k & 10u) == 10u ? v[t][3] : q, fa[t],
+                                     fb[t]);
+            }
+            e[t] = 0.0;
+            if (use && n0 + t < a.N && valid(g)) {
+                const float rr = fmaf(-Wp, g, I[t]);
+                const float eps = rr * rr / s2;
+                kahan_add(pS, pC, eps);
+                e[t] = (double)eps;
             }
         }
-        fsum = wave_sum<double>(fsum);
-        if (lane == 0) wsum_sh[(size_t)n * WAVES + wave] = fsum;
+        const double fsum = wave_sum8(e, lane);
+        const int f = n0 + ((lane >> 3) & 7);
+        if ((lane & 7) == 0 && f < a.N) wsum_sh[(size_t)f * WAVES + wave] = fsum;
     }
-    if (a.pixel_err) {
-#pragma unroll
-        for (int m = 0; m < ERR_PIX_PER_THREAD; ++m)
-            if (pix[m] < HW) a.pixel_err[pix[m]] = use[m] ? pS[m] : 0.f;
-    }
+    if (a.pixel_err && inb) a.pixel_err[pix] = use ? pS : 0.f;
     __syncthreads();
     for (int n = threadIdx.x; n < a.N; n += ERR_THREADS) {
         double acc = 0.0;
@@ -158,7 +217,7 @@ int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const fl
     a.Rf = g.Rf;
     a.o0 = g.o0;
     a.o1 = g.o1;
-    const size_t per_block = (size_t)ERR_THREADS * ERR_PIX_PER_THREAD;
+    const size_t per_block = (size_t)ERR_THREADS;
     a.nblk = (int)((g.HW() + per_block - 1) / per_block);
     a.part = (double*)(ws + L.err_part);
     a.frame_err = (double*)(ws + L.err_pix);

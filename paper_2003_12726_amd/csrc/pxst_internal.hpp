@@ -36,7 +36,6 @@ constexpr int TR_THREADS = 256;
 constexpr int TR_CT_MAX = (2 * PXST_MAX_TR_RADIUS + 1) * (2 * PXST_MAX_TR_RADIUS + 1);
 // Error evaluation: pixels per work-group.
 constexpr int ERR_THREADS = 256;
-constexpr int ERR_PIX_PER_THREAD_CFG = 1;
 
 // Inverse-map (reference gather) cell grid: capacity per axis.
 inline int grid_h(const Geom& g) { return 2 * (g.H > g.Rs ? g.H : g.Rs) + 8; }

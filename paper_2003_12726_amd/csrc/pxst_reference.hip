@@ -166,17 +166,23 @@ __global__ void k_cell_start(const unsigned* __restrict__ keys, int n, unsigned 
     cstart[c] = (unsigned)lo;
 }
 
-// Per sorted entry: fractions of u, white-field, pixel index and cell coordinates.
+// Per sorted entry: fractions of u, white-field and the cell in grid coordinates packed
+// as (row << 16) | column (all 1s outside the grid; both fit 16 bits since detector and
+// reference sides are at most 16384), plus the cell coordinates themselves.
 __global__ void k_pixel_data(const float* __restrict__ u, const float* __restrict__ white,
                              const unsigned* __restrict__ vals, int HW, int n_entries, int o0, int o1,
-                             float4* __restrict__ pdata, int2* __restrict__ bsort) {
+                             const GridInfo* __restrict__ gi, int GH, int GW, float4* __restrict__ pdata,
+                             int2* __restrict__ bsort) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_entries) return;
     const unsigned k = vals[e];
     const float u0 = u[k], u1 = u[HW + k];
     const float f0 = floorf(u0), f1 = floorf(u1);
-    pdata[e] = make_float4(u0 - f0, u1 - f1, white[k], __uint_as_float(k));
-    bsort[e] = make_int2(cell_coord(u0, o0), cell_coord(u1, o1));
+    const int b0 = cell_coord(u0, o0), b1 = cell_coord(u1, o1);
+    const int r = b0 - gi->g0, c = b1 - gi->g1;
+    const unsigned pack = (r >= 0 && r < GH && c >= 0 && c < GW) ? ((unsigned)r << 16) | (unsigned)c : ~0u;
+    pdata[e] = make_float4(u0 - f0, u1 - f1, white[k], __uint_as_float(pack));
+    bsort[e] = make_int2(b0, b1);
 }
 
 // Bilinear weight that reference coordinate p receives from a point whose position
@@ -203,6 +209,7 @@ struct GatherArgs {
     const unsigned* cstart;
     const float4* pdata;
     const int2* bsort;
+    const unsigned* pidx;     // pixel index of each sorted entry
     const GridInfo* gi;
     int N, H, W, Rs, Rf, o0, o1, GH, GW;
     int nchunks;              // frame chunks (grid z); partials go to part when > 1
@@ -237,7 +244,7 @@ __device__ inline void gather_entry(const GatherArgs& a, unsigned e, int n, size
         part = fmaf(wi, I, part);
         dpart += (double)wi * (double)pd.z;
     } else {
-        const unsigned k = __float_as_uint(pd.w);
+        const unsigned k = a.pidx[e];
         const float u0 = a.u[k], u1 = a.u[HW + k];
         const float f0 = floorf(u0), f1 = floorf(u1);
         const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
@@ -439,8 +446,8 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 // The reference update proper: every work-group owns a tile of RS_TR x RS_TC reference
 // pixels and, frame by frame, walks the cells of the inverted map whose points can put
 // a bilinear corner on the tile (rows of cells are contiguous runs of sorted entries,
-// one lane per entry), adding each corner's value M W I w and weight M W^2 w into LDS
-// bins.  The terms are rounded to integer multiples of a power-of-two quantum and
+// streamed 64 at a time per wave), adding each corner's value M W I w and weight
+// M W^2 w into LDS bins.  The terms are rounded to integer multiples of a power-of-two quantum and
 // summed as 64-bit integers.  The quantum comes from max |W| and from the number of
 // terms a reference pixel can receive at most (frames x good pixels), so that no sum
 // can leave the 63-bit range: terms get 43 bits when that bound allows (36 bits for a
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 // term).  The sums are exact, so the LDS atomic additions give the same result in any
 // order (bitwise reproducible).  Frame chunks (grid z) write exact partial sums that a
 // second pass adds; the quotient is formed in FP64.
-constexpr int RS_TR = 16, RS_TC = 62, RS_THREADS = 256;
+constexpr int RS_TR = 16, RS_TC = 56, RS_THREADS = 256;
 
 struct SplatArgs {
     const uint16_t* fsort;
@@ -463,20 +470,6 @@ struct SplatArgs {
     double* wsum;
     float* refv;
 };
-
-// Corners of a point at (b - s) + t, t in (-1, 1), along one axis: plo with weight wlo
-// and plo + 1 with weight whi.
-__device__ inline void splat_axis(int b, int s, float t, int& plo, float& wlo, float& whi) {
-    if (t >= 0.f) {
-        plo = b - s;
-        wlo = 1.f - t;
-        whi = t;
-    } else {
-        plo = b - s - 1;
-        wlo = -t;
-        whi = 1.f + t;
-    }
-}
 
 // Quantum exponents: |W I| 2^fn < 2^T and W^2 2^fd < 2^T for every term (counts are at
 // most 65535), T = min(43, 62 - bits(N n_good)): a sum of at most N n_good terms stays
@@ -493,42 +486,99 @@ __device__ inline void splat_scales(float wmax, int n_frames, int n_good, int& f
     fd = T - e2;
 }
 
-__device__ inline unsigned long long quantise(double t) {
-    return (unsigned long long)(long long)rint(t);
+// The product a b rounded once to the nearest integer (ties to even), as a 64-bit two's
+// complement integer, for |a b| < 2^51: the fused a b + 1.5 2^52 leaves that integer in
+// the low mantissa bits of a double whose exponent stays fixed, so the difference of
+// the bit patterns is the integer.
+__device__ inline unsigned long long quantise(double a, double b) {
+    constexpr double MAGIC = 6755399441055744.0;   // 1.5 * 2^52, bits 0x4338000000000000
+    const unsigned long long x = (unsigned long long)__double_as_longlong(__fma_rn(a, b, MAGIC));
+    // the low word of MAGIC's bits is zero: the subtraction only touches the high word
+    const unsigned hi = (unsigned)(x >> 32) - 0x43380000u;
+    return ((unsigned long long)hi << 32) | (unsigned)x;
 }
 
-__device__ inline void splat_entry(const SplatArgs& a, unsigned e, int n, int s0, int s1, float fd0,
-                                   float fd1, int P0, int P1, double sn, double sd,
+// Bins of a tile with a border of 2 pixels on every side: a point of the cell block of a
+// tile (cells whose points can reach the tile) has all four corners inside, so adding
+// them needs no test; the border's sums are discarded.
+constexpr int RS_PR = RS_TR + 4, RS_PC = RS_TC + 4;
+// Cell rows of a tile's block per wave: RS_TR + 2 rows over 4 waves.
+constexpr int RS_KR = (RS_TR + 2 + 3) / 4;
+static_assert(RS_THREADS == 256, "four waves per tile");
+
+// Lower corner (tile coordinates) and weights of a point along one axis: cell c minus
+// the frame shift, t the fraction of u minus that of the shift, in (-1, 1).
+__device__ inline void splat_axis(int c, float t, int& lo, float& wl, float& wh) {
+    if (t >= 0.f) {
+        lo = c;
+        wl = 1.f - t;
+        wh = t;
+    } else {
+        lo = c - 1;
+        wl = -t;
+        wh = 1.f + t;
+    }
+}
+
+// Adds the four corners of a point of the cell block (i0 in [-1, RS_TR], j0 in
+// [-1, RS_TC]); vn / vd: the quantised value and weight before the bilinear factor.
+__device__ inline void splat_block(int i0, int j0, float t0, float t1, double vn, double vd,
                                    unsigned long long* bn, unsigned long long* bd) {
-    const float4 pd = a.pdata[e];
-    const int2 b = a.bsort[e];
-    const double I = (double)a.fsort[(size_t)n * a.HW + e];
-    int p0, p1;
+    int i, j;
     float wl0, wh0, wl1, wh1;
-    splat_axis(b.x, s0, pd.x - fd0, p0, wl0, wh0);
-    splat_axis(b.y, s1, pd.y - fd1, p1, wl1, wh1);
-    const double Wd = (double)pd.z;
-    const double vn = Wd * I * sn, vd = Wd * Wd * sd;
-    const int i0 = p0 - P0, j0 = p1 - P1;
+    splat_axis(i0, t0, i, wl0, wh0);
+    splat_axis(j0, t1, j, wl1, wh1);
+    const int b = (i + 2) * RS_PC + (j + 2);
 #pragma unroll
     for (int di = 0; di < 2; ++di) {
 #pragma unroll
         for (int dj = 0; dj < 2; ++dj) {
-            const int i = i0 + di, j = j0 + dj;
-            const float w = (di ? wh0 : wl0) * (dj ? wh1 : wl1);
-            if ((unsigned)i < (unsigned)RS_TR && (unsigned)j < (unsigned)RS_TC && w != 0.f) {
-                atomicAdd(&bn[i * RS_TC + j], quantise((double)w * vn));
-                atomicAdd(&bd[i * RS_TC + j], quantise((double)w * vd));
+            const double w = (double)((di ? wh0 : wl0) * (dj ? wh1 : wl1));
+            const int q = b + di * RS_PC + dj;
+            atomicAdd(&bn[q], quantise(w, vn));
+            atomicAdd(&bd[q], quantise(w, vd));
+        }
+    }
+}
+
+// Same for a point anywhere (good pixels outside the cell grid): corners outside the
+// tile are skipped.
+__device__ inline void splat_any(int i0, int j0, float t0, float t1, double vn, double vd,
+                                 unsigned long long* bn, unsigned long long* bd) {
+    int i, j;
+    float wl0, wh0, wl1, wh1;
+    splat_axis(i0, t0, i, wl0, wh0);
+    splat_axis(j0, t1, j, wl1, wh1);
+#pragma unroll
+    for (int di = 0; di < 2; ++di) {
+#pragma unroll
+        for (int dj = 0; dj < 2; ++dj) {
+            const int ii = i + di, jj = j + dj;
+            if ((unsigned)ii < (unsigned)RS_TR && (unsigned)jj < (unsigned)RS_TC) {
+                const double w = (double)((di ? wh0 : wl0) * (dj ? wh1 : wl1));
+                const int q = (ii + 2) * RS_PC + (jj + 2);
+                atomicAdd(&bn[q], quantise(w, vn));
+                atomicAdd(&bd[q], quantise(w, vd));
             }
         }
     }
 }
 
+// Reference tile of RS_TR x RS_TC pixels, frames of one chunk (grid z).  For each frame
+// whose shifted cell block meets the cells' bounding box, wave w takes the block's cell
+// rows w, w + 4, ... and each row's entries 64 at a time (a row of the block holds about
+// RS_TC + 2 entries when u maps one detector pixel per reference pixel).  Loop bounds
+// and cell-table reads are the same for every lane of a wave (scalar).
 __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
-    __shared__ unsigned long long bn[RS_TR * RS_TC], bd[RS_TR * RS_TC];
+    constexpr int WAVES = RS_THREADS / 64;
+    // value and weight sums (separate arrays: a wave's 64-bit additions to neighbouring
+    // pixels then fall on neighbouring 8-byte words)
+    __shared__ unsigned long long bn[RS_PR * RS_PC], bd[RS_PR * RS_PC];
     const int P1 = blockIdx.x * RS_TC, P0 = blockIdx.y * RS_TR;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < RS_TR * RS_TC; i += RS_THREADS) {
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const unsigned lane = (unsigned)(tid & 63);
+    for (int i = tid; i < RS_PR * RS_PC; i += RS_THREADS) {
         bn[i] = 0ull;
         bd[i] = 0ull;
     }
@@ -546,32 +596,83 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
         const float fs0 = floorf(d0), fs1 = floorf(d1);
         const float fd0 = d0 - fs0, fd1 = d1 - fs1;
         const int s0 = (int)fs0, s1 = (int)fs1;
-        // cells whose points can reach the tile: rows P0 - 1 + s0 .. P0 + RS_TR + s0
-        const int r_lo = max(P0 - 1 + s0 - gi.g0, 0), r_hi = min(P0 + RS_TR + s0 - gi.g0, a.GH - 1);
-        const int c_lo = max(P1 - 1 + s1 - gi.g1, 0), c_hi = min(P1 + RS_TC + s1 - gi.g1, a.GW - 1);
-        if (c_lo <= c_hi) {
-            for (int r = r_lo + wave; r <= r_hi; r += RS_THREADS / 64) {
-                const unsigned eb = a.cstart[(unsigned)r * a.GW + c_lo];
-                const unsigned ee = a.cstart[(unsigned)r * a.GW + c_hi + 1];
-                for (unsigned e = eb + lane; e < ee; e += 64)
-                    splat_entry(a, e, n, s0, s1, fd0, fd1, P0, P1, sn, sd, bn, bd);
+        // cells whose points can reach the tile: rows P0 - 1 + s0 .. P0 + RS_TR + s0 and
+        // columns P1 - 1 + s1 .. P1 + RS_TC + s1, within the grid and the bounding box
+        const int r_lo = max(max(P0 - 1 + s0, gi.bmin0) - gi.g0, 0);
+        const int r_hi = min(min(P0 + RS_TR + s0, gi.bmax0) - gi.g0, a.GH - 1);
+        const int c_lo = max(max(P1 - 1 + s1, gi.bmin1) - gi.g1, 0);
+        const int c_hi = min(min(P1 + RS_TC + s1, gi.bmax1) - gi.g1, a.GW - 1);
+        if (c_lo <= c_hi && r_lo + wave <= r_hi) {
+            const int K0 = gi.g0 - s0 - P0, K1 = gi.g1 - s1 - P1;
+            const uint16_t* __restrict__ fr = a.fsort + (size_t)n * a.HW;
+            // the wave's rows: entry ranges first, then the first 64 entries of every row
+            // loaded together, then the rest
+            unsigned eb[RS_KR], ee[RS_KR];
+#pragma unroll
+            for (int k = 0; k < RS_KR; ++k) {
+                const int r = r_lo + wave + k * WAVES;
+                eb[k] = ee[k] = 0u;
+                if (r <= r_hi) {
+                    eb[k] = a.cstart[(unsigned)r * a.GW + c_lo];
+                    ee[k] = a.cstart[(unsigned)r * a.GW + c_hi + 1];
+                }
+            }
+            float4 pd[RS_KR];
+            unsigned I[RS_KR];
+#pragma unroll
+            for (int k = 0; k < RS_KR; ++k) {
+                const unsigned e = eb[k] + lane;
+                pd[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                I[k] = 0u;
+                if (e < ee[k]) {
+                    pd[k] = a.pdata[e];
+                    I[k] = fr[e];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RS_KR; ++k) {
+                if (eb[k] + lane < ee[k]) {
+                    const unsigned pk = __float_as_uint(pd[k].w);
+                    const double Wd = (double)pd[k].z;
+                    splat_block((int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, pd[k].x - fd0, pd[k].y - fd1,
+                                Wd * (double)I[k] * sn, Wd * Wd * sd, bn, bd);
+                }
+            }
+            for (int k = 0; k < RS_KR; ++k) {
+                for (unsigned e0 = eb[k] + 64u; e0 < ee[k]; e0 += 64u) {
+                    const unsigned e = e0 + lane;
+                    if (e < ee[k]) {
+                        const float4 q = a.pdata[e];
+                        const unsigned pk = __float_as_uint(q.w);
+                        const double Wd = (double)q.z;
+                        splat_block((int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, q.x - fd0, q.y - fd1,
+                                    Wd * (double)fr[e] * sn, Wd * Wd * sd, bn, bd);
+                    }
+                }
             }
         }
         // good pixels outside the cell grid (none for a sensible map)
-        for (unsigned e = ov_begin + tid; e < ov_end; e += RS_THREADS)
-            splat_entry(a, e, n, s0, s1, fd0, fd1, P0, P1, sn, sd, bn, bd);
+        for (unsigned e = ov_begin + tid; e < ov_end; e += RS_THREADS) {
+            const float4 po = a.pdata[e];
+            const int2 b = a.bsort[e];
+            const double Wd = (double)po.z;
+            splat_any(b.x - s0 - P0, b.y - s1 - P1, po.x - fd0, po.y - fd1,
+                      Wd * (double)a.fsort[(size_t)n * a.HW + e] * sn, Wd * Wd * sd, bn, bd);
+        }
     }
     __syncthreads();
     const size_t RR = (size_t)a.Rs * a.Rf;
     for (int i = tid; i < RS_TR * RS_TC; i += RS_THREADS) {
-        const int p0 = P0 + i / RS_TC, p1 = P1 + i % RS_TC;
+        const int ti = i / RS_TC, tj = i % RS_TC;
+        const int p0 = P0 + ti, p1 = P1 + tj;
         if (p0 >= a.Rs || p1 >= a.Rf) continue;
         const size_t p = (size_t)p0 * a.Rf + p1;
+        const int q = (ti + 2) * RS_PC + (tj + 2);
         if (a.nchunks > 1) {
-            a.part[(size_t)blockIdx.z * RR + p] = make_longlong2((long long)bn[i], (long long)bd[i]);
+            a.part[(size_t)blockIdx.z * RR + p] = make_longlong2((long long)bn[q], (long long)bd[q]);
         } else {
-            const double num = (double)(long long)bn[i] * ldexp(1.0, -fn);
-            const double den = (double)(long long)bd[i] * ldexp(1.0, -fd);
+            const double num = (double)(long long)bn[q] * ldexp(1.0, -fn);
+            const double den = (double)(long long)bd[q] * ldexp(1.0, -fd);
             const float val = den > 0.0 ? (float)(num / den) : 0.f;
             a.ref[p] = val;
             a.wsum[p] = den;
@@ -678,7 +779,7 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     hipLaunchKernelGGL(k_cell_start, dim3(grid_blocks((size_t)ncells + 3, 256)), dim3(256), 0, s,
                        keys2, HW, ncells + 2, cstart);
     hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals2,
-                       HW, HW, g.o0, g.o1, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
+                       HW, HW, g.o0, g.o1, gi, GH, GW, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
     hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), g.N), dim3(256), 0, s, sc.frames,
                        vals2, HW, (uint16_t*)(ws + L.fsort));
     return check_hip(hipGetLastError(), "inverse map");
@@ -694,6 +795,7 @@ static GatherArgs gather_args(const Geom& g, const pxst_scan& sc, const float* u
     a.cstart = (const unsigned*)(ws + L.cstart);
     a.pdata = (const float4*)(ws + L.pdata);
     a.bsort = (const int2*)(ws + L.bsort);
+    a.pidx = (const unsigned*)(ws + L.vals2);
     a.gi = (const GridInfo*)(ws + L.ginfo);
     a.N = g.N;
     a.H = g.H;
