@@ -12,7 +12,7 @@
 
 namespace pxst {
 
-size_t sort_temp_bound(size_t n);
+size_t scan_temp_bound(size_t n);
 
 // ---------------------------------------------------------------------------- errors
 static thread_local char g_err[512] = "";
@@ -145,10 +145,9 @@ Layout make_layout(const Geom& g, int tr_ct) {
     L.ginfo = take(sizeof(GridInfo));
     L.gpart = take(((HW + GRID_THREADS - 1) / GRID_THREADS) * sizeof(GridPart));
     L.keys = take(HW * 4);
-    L.keys2 = take(HW * 4);
-    L.vals = take(HW * 4);
     L.vals2 = take(HW * 4);
     const size_t ncells = (size_t)grid_h(g) * (size_t)grid_w(g);
+    L.ccount = take((ncells + 3) * 4);
     L.cstart = take((ncells + 3) * 4);
     L.pdata = take(HW * 16);
     L.bsort = take(HW * 8);
@@ -164,8 +163,8 @@ Layout make_layout(const Geom& g, int tr_ct) {
         L.ref_chunks = (int)chunks;
         L.rpart = take(chunks > 1 ? chunks * RRs * sizeof(RefPart) : 1);
     }
-    L.sort_tmp_bytes = sort_temp_bound(HW);
-    L.sort_tmp = take(L.sort_tmp_bytes);
+    L.scan_tmp_bytes = scan_temp_bound(ncells + 3);
+    L.scan_tmp = take(L.scan_tmp_bytes);
     const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);
     L.tiles = take(ntiles * sizeof(TileDesc));
     L.lists = take(4 * ntiles * sizeof(int));

@@ -17,7 +17,7 @@
 // cells around p + floor(dx_n) (only those can put a corner on p), with compensated
 // float32 sums over frames and float64 weight sums; frame chunks (grid z) are combined
 // in chunk order, so every sum has a fixed order.
-#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restr
 __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __restrict__ part,
                                                               int nparts, GridInfo* gi, int GH,
                                                               int GW) {
-    __shared__ GridPart wp[GRID_THREADS];
+    __shared__ GridPart wp[GRID_THREADS / 64];
     GridPart t;
     t.bmin0 = t.bmin1 = INT_MAX;
     t.bmax0 = t.bmax1 = INT_MIN;
@@ -104,10 +104,20 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __
         t.sum1 += p.sum1;
         t.n_good += p.n_good;
     }
-    wp[threadIdx.x] = t;
+    // exact operations (min, max, integer sums): the order does not change the result
+    t.bmin0 = wave_min_i(t.bmin0);
+    t.bmax0 = wave_max_i(t.bmax0);
+    t.bmin1 = wave_min_i(t.bmin1);
+    t.bmax1 = wave_max_i(t.bmax1);
+    t.sum0 = wave_sum<long long>(t.sum0);
+    t.sum1 = wave_sum<long long>(t.sum1);
+    t.n_good = wave_sum<int>(t.n_good);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t.wmax = fmaxf(t.wmax, __shfl_xor(t.wmax, o, 64));
+    if ((threadIdx.x & 63) == 0) wp[threadIdx.x >> 6] = t;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int q = 1; q < GRID_THREADS; ++q) {
+    for (int q = 1; q < GRID_THREADS / 64; ++q) {
         t.bmin0 = min(t.bmin0, wp[q].bmin0);
         t.bmax0 = max(t.bmax0, wp[q].bmax0);
         t.bmin1 = min(t.bmin1, wp[q].bmin1);
@@ -136,45 +146,120 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __
     gi->g1 = e1 <= GW ? t.bmin1 - 1 : (int)(t.sum1 / t.n_good) - GW / 2;
 }
 
-__global__ void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask, int HW, int o0,
-                       int o1, const GridInfo* __restrict__ gi, int GH, int GW,
-                       unsigned* __restrict__ keys, unsigned* __restrict__ vals) {
+// The inverted map is a counting sort of the pixels by cell key (cell index in the
+// grid; ncells: good pixel outside the grid; ncells + 1: bad pixel) that leaves the
+// pixels of every key in pixel order, as a stable sort would:
+//   counts per key -> exclusive scan = cstart (first entry of every key) -> pixels of
+//   grid cells placed with atomic slot counters -> every cell's few entries sorted by
+//   pixel index; good pixels outside the grid placed in pixel order by one work-group.
+// Bad pixels are counted but not placed (no pass reads them).
+__global__ void k_fill_u32(unsigned* __restrict__ p, size_t n, unsigned v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask,
+                                              int HW, int o0, int o1, const GridInfo* __restrict__ gi,
+                                              int GH, int GW, unsigned* __restrict__ keys,
+                                              unsigned* __restrict__ cnt) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= HW) return;
     const unsigned ncells = (unsigned)GH * (unsigned)GW;
     unsigned key = ncells + KEY_INVALID_OFF;
-    if (mask[k]) {
+    if (k < HW && mask[k]) {
         const int c0 = cell_coord(u[k], o0) - gi->g0;
         const int c1 = cell_coord(u[HW + k], o1) - gi->g1;
         key = (c0 >= 0 && c0 < GH && c1 >= 0 && c1 < GW) ? (unsigned)c0 * GW + c1
                                                           : ncells + KEY_OVERFLOW_OFF;
     }
-    keys[k] = key;
-    vals[k] = (unsigned)k;
+    if (k < HW) {
+        keys[k] = key;
+        if (key < ncells) atomicAdd(&cnt[key], 1u);
+    }
+    // the two special keys: one addition per wave
+    const unsigned long long mo = __ballot(k < HW && key == ncells + KEY_OVERFLOW_OFF);
+    const unsigned long long mi = __ballot(k < HW && key == ncells + KEY_INVALID_OFF);
+    if ((threadIdx.x & 63) == 0) {
+        if (mo) atomicAdd(&cnt[ncells + KEY_OVERFLOW_OFF], (unsigned)__popcll(mo));
+        if (mi) atomicAdd(&cnt[ncells + KEY_INVALID_OFF], (unsigned)__popcll(mi));
+    }
 }
 
-// cstart[c] = first sorted position whose key is >= c, for c in [0, ncells + 2].
-__global__ void k_cell_start(const unsigned* __restrict__ keys, int n, unsigned ncells_p2,
-                             unsigned* __restrict__ cstart) {
-    const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > ncells_p2) return;
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (keys[mid] < c) lo = mid + 1; else hi = mid;
+// Places the pixels of grid cells: slot = remaining count - 1 (the order inside a cell
+// is fixed afterwards).
+__global__ void k_cell_scatter(const unsigned* __restrict__ keys, int HW, unsigned ncells,
+                               const unsigned* __restrict__ cstart, unsigned* __restrict__ cnt,
+                               unsigned* __restrict__ vals) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= HW) return;
+    const unsigned key = keys[k];
+    if (key < ncells) {
+        const unsigned r = atomicSub(&cnt[key], 1u) - 1u;
+        vals[cstart[key] + r] = (unsigned)k;
     }
-    cstart[c] = (unsigned)lo;
+}
+
+// Good pixels outside the grid, in pixel order (one work-group; nothing to do for a
+// sensible map).
+constexpr int OV_THREADS = 1024;
+__global__ __launch_bounds__(OV_THREADS) void k_overflow_order(const unsigned* __restrict__ keys, int HW,
+                                                               unsigned ncells,
+                                                               const unsigned* __restrict__ cstart,
+                                                               unsigned* __restrict__ vals) {
+    constexpr int WAVES = OV_THREADS / 64;
+    __shared__ unsigned wc[WAVES];
+    const unsigned ob = cstart[ncells + KEY_OVERFLOW_OFF], oe = cstart[ncells + KEY_OVERFLOW_OFF + 1];
+    if (oe == ob) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned base = ob;
+    for (int k0 = 0; k0 < HW; k0 += OV_THREADS) {
+        const int k = k0 + threadIdx.x;
+        const bool f = k < HW && keys[k] == ncells + KEY_OVERFLOW_OFF;
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) wc[wave] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned before = 0, total = 0;
+        for (int w = 0; w < WAVES; ++w) {
+            before += w < wave ? wc[w] : 0u;
+            total += wc[w];
+        }
+        if (f) vals[base + before + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (unsigned)k;
+        base += total;
+        __syncthreads();
+    }
+}
+
+// Sorts every grid cell's entries by pixel index (shell sort; a cell holds one or two
+// pixels when u maps about one pixel per reference pixel).
+__global__ void k_cell_order(const unsigned* __restrict__ cstart, unsigned ncells, unsigned* __restrict__ vals) {
+    const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const unsigned b = cstart[c], n = cstart[c + 1] - b;
+    if (n < 2) return;
+    unsigned* v = vals + b;
+    unsigned gap = 1;
+    while (gap * 3 + 1 < n) gap = gap * 3 + 1;
+    for (; gap > 0; gap /= 3) {
+        for (unsigned i = gap; i < n; ++i) {
+            const unsigned x = v[i];
+            unsigned j = i;
+            while (j >= gap && v[j - gap] > x) {
+                v[j] = v[j - gap];
+                j -= gap;
+            }
+            v[j] = x;
+        }
+    }
 }
 
 // Per sorted entry: fractions of u, white-field and the cell in grid coordinates packed
 // as (row << 16) | column (all 1s outside the grid; both fit 16 bits since detector and
 // reference sides are at most 16384), plus the cell coordinates themselves.
 __global__ void k_pixel_data(const float* __restrict__ u, const float* __restrict__ white,
-                             const unsigned* __restrict__ vals, int HW, int n_entries, int o0, int o1,
-                             const GridInfo* __restrict__ gi, int GH, int GW, float4* __restrict__ pdata,
-                             int2* __restrict__ bsort) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n_entries) return;
+                             const unsigned* __restrict__ vals, int HW, const unsigned* __restrict__ n_good,
+                             int o0, int o1, const GridInfo* __restrict__ gi, int GH, int GW,
+                             float4* __restrict__ pdata, int2* __restrict__ bsort) {
+    const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= *n_good) return;
     const unsigned k = vals[e];
     const float u0 = u[k], u1 = u[HW + k];
     const float f0 = floorf(u0), f1 = floorf(u1);
@@ -222,10 +307,10 @@ struct GatherArgs {
 // fsort[n][e] = frames[n][vals[e]]: a frame value of a sorted entry is then read at the
 // entry's own index, not through its pixel index.
 __global__ void k_sort_frames(const uint16_t* __restrict__ frames, const unsigned* __restrict__ vals,
-                              int HW, uint16_t* __restrict__ fsort) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+                              int HW, const unsigned* __restrict__ n_good, uint16_t* __restrict__ fsort) {
+    const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = blockIdx.y;
-    if (e < HW) fsort[n * HW + e] = frames[n * HW + vals[e]];
+    if (e < *n_good) fsort[n * HW + e] = frames[n * HW + vals[e]];
 }
 
 // Contribution of sorted entry e in frame n to reference pixel (p0, p1): value and weight.
@@ -721,10 +806,10 @@ inline unsigned grid_blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1
 
 }  // namespace
 
-size_t sort_temp_bound(size_t n) {
-    // radix sort of (u32 key, u32 value) pairs: two scratch copies plus histograms and
-    // look-back state; generous bound, checked against the queried size at run time.
-    return n * 16 + (size_t)(8 << 20);
+size_t scan_temp_bound(size_t n) {
+    // exclusive scan of n counts: look-back state of one or two words per block of at
+    // least 64 items; generous bound, checked against the queried size at run time.
+    return n / 64 * 16 + (size_t)(1 << 20);
 }
 
 int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv, int* sat,
@@ -750,38 +835,38 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     const int GH = grid_h(g), GW = grid_w(g);
     GridInfo* gi = (GridInfo*)(ws + L.ginfo);
     unsigned* keys = (unsigned*)(ws + L.keys);
-    unsigned* keys2 = (unsigned*)(ws + L.keys2);
-    unsigned* vals = (unsigned*)(ws + L.vals);
-    unsigned* vals2 = (unsigned*)(ws + L.vals2);
+    unsigned* cnt = (unsigned*)(ws + L.ccount);
+    unsigned* vals = (unsigned*)(ws + L.vals2);
     unsigned* cstart = (unsigned*)(ws + L.cstart);
     const unsigned nparts = grid_blocks(HW, GRID_THREADS);
     GridPart* gpart = (GridPart*)(ws + L.gpart);
+    const unsigned ncells = (unsigned)GH * (unsigned)GW;
+    const size_t nkeys = (size_t)ncells + 3;   // cells, outside the grid, bad, end
     hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, sc.white, HW,
                        g.o0, g.o1, gpart);
     hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(GRID_THREADS), 0, s, gpart, (int)nparts, gi, GH,
                        GW);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(nkeys, 256)), dim3(256), 0, s, cnt, nkeys, 0u);
     hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
-                       g.o1, gi, GH, GW, keys, vals);
-    const unsigned ncells = (unsigned)GH * (unsigned)GW;
-    unsigned bits = 1;
-    while (bits < 32 && ((1ull << bits) <= (unsigned long long)ncells + 1)) ++bits;
+                       g.o1, gi, GH, GW, keys, cnt);
     size_t tb = 0;
-    hipError_t e = rocprim::radix_sort_pairs(nullptr, tb, keys, keys2, vals, vals2, (size_t)HW, 0,
-                                             bits, s);
-    if (e != hipSuccess) return check_hip(e, "radix sort size query");
-    if (tb > L.sort_tmp_bytes) {
-        set_error("internal: radix sort needs %zu scratch bytes, %zu reserved", tb, L.sort_tmp_bytes);
+    hipError_t e = rocprim::exclusive_scan(nullptr, tb, cnt, cstart, 0u, nkeys, rocprim::plus<unsigned>(), s);
+    if (e != hipSuccess) return check_hip(e, "cell scan size query");
+    if (tb > L.scan_tmp_bytes) {
+        set_error("internal: cell scan needs %zu scratch bytes, %zu reserved", tb, L.scan_tmp_bytes);
         return PXST_EWORKSPACE;
     }
-    e = rocprim::radix_sort_pairs(ws + L.sort_tmp, tb, keys, keys2, vals, vals2, (size_t)HW, 0, bits,
-                                  s);
-    if (e != hipSuccess) return check_hip(e, "radix sort");
-    hipLaunchKernelGGL(k_cell_start, dim3(grid_blocks((size_t)ncells + 3, 256)), dim3(256), 0, s,
-                       keys2, HW, ncells + 2, cstart);
-    hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals2,
-                       HW, HW, g.o0, g.o1, gi, GH, GW, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
+    e = rocprim::exclusive_scan(ws + L.scan_tmp, tb, cnt, cstart, 0u, nkeys, rocprim::plus<unsigned>(), s);
+    if (e != hipSuccess) return check_hip(e, "cell scan");
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, keys, HW, ncells,
+                       cstart, cnt, vals);
+    hipLaunchKernelGGL(k_overflow_order, dim3(1), dim3(OV_THREADS), 0, s, keys, HW, ncells, cstart, vals);
+    hipLaunchKernelGGL(k_cell_order, dim3(grid_blocks(ncells, 256)), dim3(256), 0, s, cstart, ncells, vals);
+    const unsigned* n_good = cstart + ncells + KEY_INVALID_OFF;   // entries of good pixels
+    hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals,
+                       HW, n_good, g.o0, g.o1, gi, GH, GW, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
     hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), g.N), dim3(256), 0, s, sc.frames,
-                       vals2, HW, (uint16_t*)(ws + L.fsort));
+                       vals, HW, n_good, (uint16_t*)(ws + L.fsort));
     return check_hip(hipGetLastError(), "inverse map");
 }
 
