@@ -786,7 +786,7 @@ struct MmPix {
     int dc0, dc1;  // window centre relative to the tile's smallest centre
     int zvar;      // var == 0
     int good;
-    int pad;
+    int eo;        // error-table index of position (r, c) is eo + r NY + c
 };
 
 // Frames of a tile as the A operand (rows = the tile's 64 pixels in four groups of 16,
@@ -1042,10 +1042,13 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
         q.al = q.be = q.ga = q.vf = 0.0;
         q.W = 0.f;
         q.zvar = 0;
-        q.pad = 0;
+        q.eo = 0;
         if (q.good) {
             q.dc0 = window_centre(a.u_in[pix]) - td.cmin0;
             q.dc1 = window_centre(a.u_in[HW + pix]) - td.cmin1;
+            // this pixel's table (of the part of 16 MH pixels it belongs to) at candidate
+            // (r - dc0, c - dc1)
+            q.eo = (p & (16 * MH - 1)) * NC - (q.dc0 * NY + q.dc1);
             const double Wd = (double)a.white[pix];
             q.W = a.white[pix];
             const double* st = a.pstat + ((size_t)tile * 64 + p) * 4;
@@ -1225,21 +1228,36 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             CS += __shfl_xor(CS, 16, 64);
             CS += __shfl_xor(CS, 32, 64);
             const double gq = 128.0 * 257.0 * GU - kconst;
+            const int rN = r * NY + cc;
+            // S = sum_s 256^s acc_s; with at most 3 K-blocks |acc_s| <= 2^21 KB, so the two
+            // low and the two high classes can be combined exactly in 32 bits first
+            auto contraction = [&](int m, int i) -> double {
+                if (KB <= 3) {
+                    const int lo = acc[m][0][i] + (acc[m][1][i] << 8);
+                    const int hi = acc[m][2][i] + (acc[m][3][i] << 8);
+                    return fma(65536.0, (double)hi, (double)lo);
+                }
+                return (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] + 65536.0 * (double)acc[m][2][i] +
+                       16777216.0 * (double)acc[m][3][i];
+            };
             if (!EDGE) {
 #pragma unroll
                 for (int m = 0; m < MH; ++m) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int pl = m * 16 + 4 * g + i, p = h * MH * 16 + pl;
-                        const MmPix P = pp[p];
+                        const int p = h * MH * 16 + m * 16 + 4 * g + i;
+                        // (the error formed on every lane and the table index from the
+                        // candidate: measured faster for interior tiles than the edge
+                        // tiles' form below)
+                        const MmPix& P = pp[p];
+                        const int kx = r - P.dc0, ky = cc - P.dc1;
                         const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
                                          65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
                         double v = fma(P.be, S + gq, fma(P.ga, CS, P.al));
                         v = v > 0.0 ? v : 0.0;
                         const float E = P.zvar ? (v == 0.0 ? 0.f : INFINITY) : (float)v;
-                        const int kx = r - P.dc0, ky = cc - P.dc1;
                         if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY)
-                            ebuf[(size_t)pl * NC + kx * NY + ky] = E;
+                            ebuf[(size_t)(m * 16 + 4 * g + i) * NC + kx * NY + ky] = E;
                     }
                 }
             } else {
@@ -1256,9 +1274,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     for (int i = 0; i < 4; ++i) {
                         const int e = m * 4 + i, p = h * MH * 16 + m * 16 + 4 * g + i;
                         const MmPix& P = pp[p];
-                        const double S = (double)acc[m][0][i] + 256.0 * (double)acc[m][1][i] +
-                                         65536.0 * (double)acc[m][2][i] + 16777216.0 * (double)acc[m][3][i];
-                        ef[e] = fma(P.be, S + gq, fma(P.ga, CS, P.al));
+                        ef[e] = fma(P.be, contraction(m, i) + gq, fma(P.ga, CS, P.al));
                         ai[e] = 0.0;
                         vi[e] = 0.f;
                         Wl[e] = P.W;
@@ -1293,13 +1309,13 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 for (int m = 0; m < MH; ++m) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int e = m * 4 + i, pl = m * 16 + 4 * g + i, p = h * MH * 16 + pl;
+                        const int e = m * 4 + i, p = h * MH * 16 + m * 16 + 4 * g + i;
                         const int kx = r - pp[p].dc0, ky = cc - pp[p].dc1;
                         if (qv && (unsigned)kx < (unsigned)NX && (unsigned)ky < (unsigned)NY) {
                             double err = ef[e] - ai[e];
                             err = err > 0.0 ? err : 0.0;
                             const float var = (float)(pp[p].vf - (double)vi[e]);
-                            ebuf[(size_t)pl * NC + kx * NY + ky] = normalised_error((float)err, var, nv);
+                            ebuf[pp[p].eo + rN] = normalised_error((float)err, var, nv);
                         }
                     }
                 }
