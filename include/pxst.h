@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define PXST_ABI_VERSION 2
+#define PXST_ABI_VERSION 3
 
 #define PXST_OK 0
 #define PXST_EINVAL (-1)       /* null pointer, bad size or misaligned pointer        */
@@ -100,20 +100,27 @@ typedef struct {
 #define PXST_REF_BF16 2
 
 /* Main-loop options (Sec. 2.2): n_iter iterations of (i) reference update,
- * (ii) pixel-map update with window `pm`, (iii) translation update with window
- * `tr` when update_dx != 0, (iv) total error; ref_mode selects the arithmetic of
- * every reference update of the loop (PXST_REF_*). */
+ * (ii) pixel-map update with window `pm`, then its regularisation when pm_sigma > 0
+ * or pm_integrate != 0 (see pxst_regularise_pixel_map), (iii) translation update
+ * with window `tr` when update_dx != 0, (iv) total error; ref_mode selects the
+ * arithmetic of every reference update of the loop (PXST_REF_*).  pm_sigma: finite,
+ * 0 <= pm_sigma with int(4 pm_sigma + 0.5) <= 256; pm_integrate: 0 or 1. */
 typedef struct {
     int32_t n_iter;
     pxst_window pm;
     int32_t update_dx;
     pxst_window tr;
     int32_t ref_mode;
+    float pm_sigma;
+    int32_t pm_integrate;
 } pxst_solve_opts;
 
 /* Workspace bytes that every entry point below needs for this geometry and these
- * windows (opts may be NULL: reference update and error only).  Returns 0 and sets
- * the last error when the arguments are invalid. */
+ * windows (opts may be NULL: reference update and error only).  With
+ * opts->pm_integrate != 0 the workspace also holds the buffers of the map
+ * integration (two H x W and the H x H and W x W float64 matrices), which
+ * pxst_regularise_pixel_map with integrate != 0 requires.  Returns 0 and sets the
+ * last error when the arguments are invalid. */
 size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts);
 
 /*
@@ -196,6 +203,31 @@ int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, cons
                float* ref_err, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Pixel-map regularisation -- Sec. 2.2.2, closing paragraphs: optionally a Gaussian
+ * filter of the map ("sigma"), then optionally the irrotational constraint
+ * ("integrate": the map is replaced by the gradient of its least-squares potential).
+ *   filter     each component convolved along both axes with exp(-k^2/(2 sigma^2)),
+ *              |k| <= int(4 sigma + 0.5), normalised to unit sum; the nearest pixel
+ *              is repeated outside the detector; sigma = 0: no filter
+ *   integrate  Phi minimises sum (Phi[i+1,j]-Phi[i,j]-(u0[i,j]+u0[i+1,j])/2)^2
+ *              + sum (Phi[i,j+1]-Phi[i,j]-(u1[i,j]+u1[i,j+1])/2)^2 over all pixels
+ *              (solved exactly: the normal equations are diagonal in the DCT-II
+ *              basis); u becomes the gradient of Phi by central differences,
+ *              second-order one-sided at the edges (first order along an axis of two
+ *              pixels; an axis of one pixel keeps its component)
+ * The filter runs first, then the integration.
+ *   u_in  [2][H][W] float32 (in)     u_out [2][H][W] float32 (out; may equal u_in)
+ * sigma: finite, >= 0, int(4 sigma + 0.5) <= 256 (else PXST_EINVAL /
+ * PXST_EUNSUPPORTED); integrate: 0 or 1.  The workspace must come from
+ * pxst_workspace_bytes with opts->pm_integrate = 1 when integrate = 1
+ * (PXST_EWORKSPACE otherwise).  Ordered on `stream`; the library holds one rocBLAS
+ * handle per device for the transforms.
+ */
+int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u_out, float sigma,
+                              int32_t integrate, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream);
+
+/*
  * Main loop -- Sec. 2.2.  For k = 0..n_iter-1:
  *   (ref, wsum) <- reference update from (u, dx)
  *   u           <- pixel-map update with opts->pm
@@ -244,12 +276,14 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
 /* Kernel timing for benchmarks: when enabled, the library brackets each launch of
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
- * Families: "pm_fast", "pm_edge", "pm_generic", "ref_gather", "tr_partial",
- * "err_pixels", and "pm_fast_int8_ops" (the interior-tile search on the matrix
- * cores, counting int8 operations).  pxst_profile_read returns the total
- * milliseconds, the number of timed launches and the work units of the family
- * (candidate evaluations, or int8 operations for "pm_fast_int8_ops"), and resets
- * the family. */
+ * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "ref_gather",
+ * "tr_partial", "err_pixels", "pm_fast_int8_ops" (the interior-tile search on the
+ * matrix cores, counting int8 operations), "reg_filter" and "reg_integrate" (the
+ * map regularisation).  pxst_profile_read returns the total milliseconds, the
+ * number of timed launches and the work units of the family (candidate evaluations;
+ * int8 operations for "pm_fast_int8_ops"; output values times taps for
+ * "reg_filter"; float64 operations of the transforms for "reg_integrate"), and
+ * resets the family. */
 int pxst_profile_enable(int32_t on);
 int pxst_profile_read(const char* family, double* total_ms, int64_t* launches,
                       int64_t* work_units);

@@ -46,7 +46,8 @@ class CScan(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("pm", Window), ("update_dx", ctypes.c_int32),
-                ("tr", Window), ("ref_mode", ctypes.c_int32)]
+                ("tr", Window), ("ref_mode", ctypes.c_int32), ("pm_sigma", ctypes.c_float),
+                ("pm_integrate", ctypes.c_int32)]
 
 
 class CJob(ctypes.Structure):
@@ -58,8 +59,8 @@ class CJob(ctypes.Structure):
 SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_reference_ex",
            "pxst_update_pixel_map",
            "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
-           "pxst_batch_iterate", "pxst_profile_enable", "pxst_profile_read", "pxst_last_error",
-           "pxst_abi_version")
+           "pxst_batch_iterate", "pxst_regularise_pixel_map", "pxst_profile_enable",
+           "pxst_profile_read", "pxst_last_error", "pxst_abi_version")
 
 _lib = None
 
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_batch_workspace_bytes.argtypes = [i32]
     lib.pxst_batch_workspace_bytes.restype = sz
     lib.pxst_batch_iterate.argtypes = [P(CJob), i32, vp, sz, vp]
+    lib.pxst_regularise_pixel_map.argtypes = [P(Geom), vp, vp, ctypes.c_float, i32, vp, sz, vp]
     lib.pxst_profile_enable.argtypes = [i32]
     lib.pxst_profile_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64),
                                       P(ctypes.c_int64)]
@@ -92,7 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_abi_version.restype = i32
     for name in ("pxst_update_reference", "pxst_update_reference_ex", "pxst_update_pixel_map",
                  "pxst_update_translations",
-                 "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_profile_enable",
+                 "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_regularise_pixel_map",
+                 "pxst_profile_enable",
                  "pxst_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -137,9 +140,11 @@ REF_MODES = {"exact": 0, "fp32": 1, "bf16": 2}   # PXST_REF_EXACT, _FP32, _BF16
 
 
 def make_opts(n_iter: int, pm: Sequence[int], refine: bool = True, update_dx: bool = False,
-              tr: Sequence[int] = (2, 2), tr_refine: bool = True, ref_mode: str = "exact") -> SolveOpts:
+              tr: Sequence[int] = (2, 2), tr_refine: bool = True, ref_mode: str = "exact",
+              sigma: float = 0.0, integrate: bool = False) -> SolveOpts:
     return SolveOpts(int(n_iter), make_window(pm[0], pm[1], refine), int(bool(update_dx)),
-                     make_window(tr[0], tr[1], tr_refine), REF_MODES[ref_mode])
+                     make_window(tr[0], tr[1], tr_refine), REF_MODES[ref_mode], float(sigma),
+                     int(bool(integrate)))
 
 
 @dataclasses.dataclass
@@ -226,6 +231,16 @@ def solve(scan: Scan, opts: SolveOpts, u, dx, ref, wsum, err_hist=None, ws=None,
     p, n = _ws(ws)
     _check(lib.pxst_solve(ctypes.byref(scan.c()), ctypes.byref(opts), _ptr(u), _ptr(dx), _ptr(ref),
                           _ptr(wsum), _ptr(err_hist), p, n, _stream(stream)))
+
+
+def regularise_pixel_map(geom: Geom, u_in, u_out, sigma: float = 0.0, integrate: bool = False, ws=None,
+                         stream=None):
+    """Pixel-map regularisation (Sec. 2.2.2): Gaussian filter, then the irrotational
+    constraint; the workspace must be laid out with integrate when it is asked for."""
+    lib = load_library()
+    p, n = _ws(ws)
+    _check(lib.pxst_regularise_pixel_map(ctypes.byref(geom), _ptr(u_in), _ptr(u_out), float(sigma),
+                                         int(bool(integrate)), p, n, _stream(stream)))
 
 
 def batch_iterate(jobs: Sequence[CJob], batch_ws=None, stream=None):

@@ -2,6 +2,7 @@
 // and kernel timing.  Kernels live in the other translation units.
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -129,7 +130,7 @@ BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const st
 // --------------------------------------------------------------------------- layout
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(const Geom& g, int tr_ct) {
+Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -181,6 +182,17 @@ Layout make_layout(const Geom& g, int tr_ct) {
     const size_t nblk_err = (HW + per_err - 1) / per_err;
     L.err_part = take((size_t)g.N * nblk_err * sizeof(double));
     L.err_pix = take((size_t)g.N * sizeof(double) + sizeof(double));
+    L.gw = take((2 * GF_MAXR + 1) * sizeof(double));
+    L.gtmp = take(2 * HW * sizeof(double));
+    // the integration buffers come last: a workspace laid out with them also serves
+    // every call that does not integrate
+    L.integ = integ;
+    if (integ) {
+        L.dct_h = take((size_t)g.H * g.H * sizeof(double));
+        L.dct_w = take((size_t)g.W * g.W * sizeof(double));
+        L.ibuf0 = take(HW * sizeof(double));
+        L.ibuf1 = take(HW * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -284,13 +296,30 @@ int32_t pxst_abi_version(void) { return PXST_ABI_VERSION; }
 
 const char* pxst_last_error(void) { return g_err; }
 
+static int check_regularise_opts(float sigma, int integrate) {
+    if (!(sigma >= 0.f) || !std::isfinite(sigma)) {
+        set_error("sigma must be finite and >= 0 (got %g)", (double)sigma);
+        return PXST_EINVAL;
+    }
+    if ((int)(4.0 * (double)sigma + 0.5) > GF_MAXR) {
+        set_error("sigma %g exceeds the filter limit (radius int(4 sigma + 0.5) <= %d)", (double)sigma, GF_MAXR);
+        return PXST_EUNSUPPORTED;
+    }
+    if (integrate != 0 && integrate != 1) {
+        set_error("integrate must be 0 or 1 (got %d)", integrate);
+        return PXST_EINVAL;
+    }
+    return PXST_OK;
+}
+
 size_t pxst_workspace_bytes(const pxst_geom* geom, const pxst_solve_opts* opts) {
     if (check_geom(geom)) return 0;
     if (opts) {
         if (check_window(opts->pm, PXST_MAX_PM_RADIUS, "pixel-map")) return 0;
         if (opts->update_dx && check_window(opts->tr, PXST_MAX_TR_RADIUS, "translation")) return 0;
     }
-    return make_layout(geom_of(*geom), tr_ct_of(opts)).total;
+    if (opts && check_regularise_opts(opts->pm_sigma, opts->pm_integrate)) return 0;
+    return make_layout(geom_of(*geom), tr_ct_of(opts), opts && opts->pm_integrate).total;
 }
 
 static int check_ref_mode(int mode) {
@@ -394,6 +423,18 @@ int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, cons
     return PXST_OK;
 }
 
+int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u_out, float sigma,
+                              int32_t integrate, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc;
+    if ((rc = check_geom(geom))) return rc;
+    if ((rc = check_regularise_opts(sigma, integrate))) return rc;
+    if ((rc = check_ptr(u_in, 4, "u_in")) || (rc = check_ptr(u_out, 4, "u_out"))) return rc;
+    const Geom g = geom_of(*geom);
+    const Layout L = make_layout(g, TR_CT_MAX, integrate != 0);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    return launch_regularise(g, u_in, u_out, sigma, integrate, (char*)ws, L, stream);
+}
+
 int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, float* dx, float* ref,
                double* wsum, double* err_hist, void* ws, size_t ws_bytes, hipStream_t stream) {
     int rc;
@@ -410,12 +451,13 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     if (opts->update_dx && (rc = check_window(opts->tr, PXST_MAX_TR_RADIUS, "translation")))
         return rc;
     if ((rc = check_ref_mode(opts->ref_mode))) return rc;
+    if ((rc = check_regularise_opts(opts->pm_sigma, opts->pm_integrate))) return rc;
     if ((rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
         (rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
         (rc = check_ptr(err_hist, 8, "err_hist", false)))
         return rc;
     const Geom g = geom_of(scan->geom);
-    const Layout L = make_layout(g, tr_ct_of(opts));
+    const Layout L = make_layout(g, tr_ct_of(opts), opts->pm_integrate != 0);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     char* w = (char*)ws;
     float* refv = (float*)(w + L.refv);
@@ -432,6 +474,9 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
                                              (int*)(w + L.fscale), stream))) return rc;
         if ((rc = launch_pixel_map(g, *scan, refv, sat, dx, u, opts->pm, u, nullptr, nullptr, w, L,
                                    stream)))
+            return rc;
+        if ((opts->pm_sigma > 0.f || opts->pm_integrate) &&
+            (rc = launch_regularise(g, u, u, opts->pm_sigma, opts->pm_integrate, w, L, stream)))
             return rc;
         if (opts->update_dx &&
             (rc = launch_translations(g, *scan, refv, u, dx, opts->tr, dx, nullptr, nullptr, w, L,
@@ -506,11 +551,12 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         if (J.opts.update_dx && (rc = check_window(J.opts.tr, PXST_MAX_TR_RADIUS, "translation")))
             return rc;
         if ((rc = check_ref_mode(J.opts.ref_mode))) return rc;
+        if ((rc = check_regularise_opts(J.opts.pm_sigma, J.opts.pm_integrate))) return rc;
         if ((rc = check_ptr(J.u, 4, "u")) || (rc = check_ptr(J.dx, 4, "dx")) ||
             (rc = check_ptr(J.ref, 4, "ref")) || (rc = check_ptr(J.wsum, 8, "wsum")) ||
             (rc = check_ptr(J.err_hist, 8, "err_hist", false)))
             return rc;
-        const Layout L = make_layout(geom_of(J.scan.geom), tr_ct_of(&J.opts));
+        const Layout L = make_layout(geom_of(J.scan.geom), tr_ct_of(&J.opts), J.opts.pm_integrate != 0);
         if ((rc = check_ws(J.ws, J.ws_bytes, L.total))) return rc;
     }
     if (n_jobs == 0) return PXST_OK;
@@ -552,7 +598,7 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
     std::vector<JobState> st(n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
         st[j].g = geom_of(jobs[j].scan.geom);
-        st[j].L = make_layout(st[j].g, tr_ct_of(&jobs[j].opts));
+        st[j].L = make_layout(st[j].g, tr_ct_of(&jobs[j].opts), jobs[j].opts.pm_integrate != 0);
         st[j].w = (char*)jobs[j].ws;
         st[j].refv = (float*)(st[j].w + st[j].L.refv);
     }
@@ -591,11 +637,14 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         pm.push_back(d);
     }
     if (!rc) rc = launch_pixel_map_batch(pm.data(), (int)pm.size(), ar, stream);
-    // (iii) translations and (iv) total error
+    // (iii) regularisation of the map, translations and (iv) total error
     for (int j = 0; j < n_jobs && !rc; ++j) {
         const pxst_job& J = jobs[j];
         if (J.iter >= J.opts.n_iter) continue;
-        if (J.opts.update_dx)
+        if (J.opts.pm_sigma > 0.f || J.opts.pm_integrate)
+            rc = launch_regularise(st[j].g, J.u, J.u, J.opts.pm_sigma, J.opts.pm_integrate, st[j].w, st[j].L,
+                                   stream);
+        if (!rc && J.opts.update_dx)
             rc = launch_translations(st[j].g, J.scan, st[j].refv, J.u, J.dx, J.opts.tr, J.dx, nullptr,
                                      nullptr, st[j].w, st[j].L, stream);
         if (!rc)

@@ -82,10 +82,18 @@ struct Layout {
     size_t tr_part;
     // error
     size_t err_part, err_pix;
+    // pixel-map regularisation: filter weights and pass buffer; DCT matrices and two
+    // [H][W] float64 buffers of the integration (only when integ)
+    size_t gw, gtmp;
+    bool integ;
+    size_t dct_h, dct_w, ibuf0, ibuf1;
     size_t total;
 };
 
-Layout make_layout(const Geom& g, int tr_ct);
+// Largest filter radius (|k| <= int(4 sigma + 0.5)) of the pixel-map regularisation.
+constexpr int GF_MAXR = 256;
+
+Layout make_layout(const Geom& g, int tr_ct, bool integ = false);
 
 // Tile descriptor of the pixel-map search.
 struct TileDesc {
@@ -192,6 +200,10 @@ int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, c
                         hipStream_t s);
 
 // sigma2[i, j] = (1/N) sum M (I - W)^2 into ws s2.
+// Pixel-map regularisation: filter (sigma > 0), then the irrotational constraint
+// (integrate != 0; the layout must hold the integration buffers).  u_out may be u_in.
+int launch_regularise(const Geom& g, const float* u_in, float* u_out, float sigma, int integrate, char* ws,
+                      const Layout& L, hipStream_t s);
 int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
 
 // Figures of merit.

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(pxst.SYMBOLS)
-    assert pxst.abi_version() == 2
+    assert pxst.abi_version() == 3
 
 
 def test_workspace_bytes_grows_with_problem(lib):
@@ -127,3 +127,27 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_regularise_argument_checks(lib):
+    """Pixel-map regularisation: sigma and integrate are validated, and integration needs
+    a workspace laid out with its buffers -- all before any GPU work."""
+    g = pxst.make_geom(4, (16, 24), (40, 40), (-10, -10))
+    P = 0x4000
+    big = 1 << 30
+    f = ctypes.c_float
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), P, P, f(-1.0), 0, P, big, None) == pxst.PXST_EINVAL
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), P, P, f(float("nan")), 0, P, big, None) == pxst.PXST_EINVAL
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), P, P, f(100.0), 0, P, big, None) == pxst.PXST_EUNSUPPORTED
+    assert "sigma" in pxst.last_error()
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), P, P, f(1.0), 2, P, big, None) == pxst.PXST_EINVAL
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), None, P, f(1.0), 0, P, big, None) == pxst.PXST_EINVAL
+    # the integration buffers are part of the workspace only when asked for
+    plain = pxst.workspace_bytes(g, pxst.make_opts(1, (2, 2)))
+    integ = pxst.workspace_bytes(g, pxst.make_opts(1, (2, 2), integrate=True))
+    assert integ >= plain + 2 * 16 * 24 * 8 + (16 * 16 + 24 * 24) * 8
+    assert lib.pxst_regularise_pixel_map(ctypes.byref(g), P, P, f(1.0), 1, 0x100000, plain, None) == \
+        pxst.PXST_EWORKSPACE
+    # solve options carry the same checks
+    o = pxst.make_opts(1, (2, 2), sigma=-2.0)
+    assert lib.pxst_workspace_bytes(ctypes.byref(g), ctypes.byref(o)) == 0
