@@ -32,6 +32,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 PEAK_INT8_MFMA_TOPS = 5000.0   # dense int8 matrix-core peak
+PEAK_FP64_TFLOPS = 78.6        # float64 (vector and matrix)
 FLOP_PER_EVAL = 4   # r = I - W g (1 FMA) and E += r^2 (1 FMA)
 
 
@@ -292,6 +293,47 @@ def time_steps(job, steps, warmup):
     return wall, lat
 
 
+def regularisation_bench(scan, dev, reps: int = 10, sigma: float = 5.0):
+    """Pixel-map regularisation of the realistic map: Gaussian filter (sigma 5) then the
+    irrotational constraint, timed per family with HIP events."""
+    import torch
+    import paper_2003_12726_amd as pxst
+    H, W = scan.det
+    g = pxst.make_geom(scan.n_frames, scan.det, scan.ref_shape, scan.origin)
+    ws = pxst.alloc_workspace(g, pxst.make_opts(1, scan.window, integrate=True), device=dev)
+    u = torch.from_numpy(scan.u0).to(dev)
+    v = torch.empty_like(u)
+    for _ in range(2):
+        pxst.regularise_pixel_map(g, u, v, sigma, True, ws)
+    torch.cuda.synchronize()
+    pxst.profile_enable(True)
+    for fam in ("reg_filter", "reg_integrate"):
+        pxst.profile_read(fam)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pxst.regularise_pixel_map(g, u, v, sigma, True, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    f_ms, f_n, f_work = pxst.profile_read("reg_filter")
+    i_ms, i_n, i_work = pxst.profile_read("reg_integrate")
+    pxst.profile_enable(False)
+    HW = H * W
+    f_avg, i_avg = f_ms / max(f_n, 1), i_ms / max(i_n, 1)
+    # algorithmic bytes of the two filter passes: float32 map in, float64 intermediate
+    # out and back in, float32 map out
+    f_bytes = 2 * HW * (4 + 8) * 2
+    i_flops = i_work / max(i_n, 1)
+    return {
+        "workload": f"{H}x{W} map, Gaussian filter sigma {sigma:g} then least-squares integration",
+        "ms_per_call": 1000.0 * wall / reps,
+        "filter_ms": f_avg,
+        "filter_GBps": f_bytes / (f_avg * 1e-3) / 1e9 if f_n else None,
+        "integrate_ms": i_avg,
+        "integrate_fp64_TFLOPs": i_flops / (i_avg * 1e-3) / 1e12 if i_n else None,
+        "integrate_fp64_frac": (i_flops / (i_avg * 1e-3) / 1e12) / PEAK_FP64_TFLOPS if i_n else None,
+    }
+
+
 def pct(xs, q):
     if not xs:
         return None
@@ -414,6 +456,8 @@ def main():
         }
         del dj
         torch.cuda.empty_cache()
+
+    out["regularisation"] = regularisation_bench(scan, dev)
 
     if served_rows is not None:
         torch.cuda.empty_cache()
