@@ -12,6 +12,7 @@ from .pxst_oracle import (  # noqa: F401
     round_half_up,
     update_reference,
     update_pixel_map,
+    update_pixel_map_fractional,
     quadratic_refine,
     update_translations,
     pixel_variance,

@@ -287,6 +287,88 @@ def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=
     return res
 
 
+def update_pixel_map_fractional(frames, white, mask, ref, w, dx, u, origin, window, steps,
+                                pixels=None, return_errors=False):
+    """Pixel-map search on a grid finer than the pixel (Sec. 2.2.2: the error evaluated
+    at non-integer positions through the interpolation of Sec. 4, instead of the
+    paraboloid refinement).
+
+    Readings: ``steps`` s is odd; the candidates of a good pixel are ``c + m / s`` per
+    axis with ``c = round_half_up(u)`` and ``m`` in [-(r s + (s-1)/2), r s + (s-1)/2]
+    (the integer window, each integer point with its (s-1)/2 fine neighbours on both
+    sides); each candidate's error is the normalised error of Sec. 2.2.2 with every
+    lookup at ``c + m / s - dx_n - origin``; first minimum in fine-grid order (slow axis
+    outer); no paraboloid.  argmin is the fine-grid index ``m0' * n1 + m1'`` with
+    ``m' = m + r s + (s-1)/2`` and ``n1`` the fine candidates along the fast axis.
+    Bad pixels and pixels without a finite candidate keep their map value with error
+    +inf and index -1.  Returns (u_out, err_min, argmin) like update_pixel_map.
+    """
+    s = int(steps)
+    if s < 1 or s % 2 == 0:
+        raise ValueError("steps must be odd and >= 1")
+    h = (s - 1) // 2
+    frames = np.asarray(frames)
+    W, M, ref, dx, u = _f64(white), _f64(mask), _f64(ref), _f64(dx), _f64(u)
+    V = _f64(w) > 0
+    H, Wd = W.shape
+    rx, ry = int(window[0]), int(window[1])
+    Mx, My = rx * s + h, ry * s + h
+    if pixels is None:
+        rows, cols = np.meshgrid(np.arange(H), np.arange(Wd), indexing="ij")
+        rows, cols = rows.ravel(), cols.ravel()
+    else:
+        rows, cols = np.asarray(pixels[0]).ravel(), np.asarray(pixels[1]).ravel()
+    u_sel = u[:, rows, cols].copy()
+    out_u = u_sel.copy()
+    out_e = np.full(rows.shape[0], INF)
+    out_k = np.full(rows.shape[0], -1, dtype=np.int64)
+    good = M[rows, cols] > 0
+    E_all = None
+    if good.any():
+        gr, gc = rows[good], cols[good]
+        c = round_half_up(u_sel[:, good])
+        P = gr.shape[0]
+        N = frames.shape[0]
+        I = np.stack([_f64(frames[n])[gr, gc] for n in range(N)])
+        Wp = W[gr, gc]
+        fx = (np.arange(-Mx, Mx + 1) / s)[:, None, None]
+        fy = (np.arange(-My, My + 1) / s)[None, :, None]
+        err = np.zeros((2 * Mx + 1, 2 * My + 1, P))
+        var = np.zeros_like(err)
+        nv = np.zeros_like(err)
+        for n in range(N):
+            a = c[0][None, None, :] + fx - dx[n, 0] - origin[0]
+            b = c[1][None, None, :] + fy - dx[n, 1] - origin[1]
+            g, ok = bilinear_gather(ref, V, a, b)
+            r = I[n][None, None, :] - Wp[None, None, :] * g
+            err += np.where(ok, r * r, 0.0)
+            v = I[n] - Wp
+            var += np.where(ok, (v * v)[None, None, :], 0.0)
+            nv += ok
+        E = _normalised(err, var, nv)
+        E_all = E
+        flat = E.reshape(-1, P)
+        k = np.argmin(flat, axis=0)
+        emin = flat[k, np.arange(P)]
+        found = np.isfinite(emin)
+        m0 = k // (2 * My + 1) - Mx
+        m1 = k % (2 * My + 1) - My
+        nu = c.copy()
+        nu[0] += m0 / s
+        nu[1] += m1 / s
+        gi = np.nonzero(good)[0]
+        out_u[:, gi[found]] = nu[:, found]
+        out_e[gi[found]] = emin[found]
+        out_k[gi[found]] = k[found]
+    if pixels is None:
+        res = (out_u.reshape(2, H, Wd), out_e.reshape(H, Wd), out_k.reshape(H, Wd))
+    else:
+        res = (out_u, out_e, out_k)
+    if return_errors:
+        return res + (E_all,)
+    return res
+
+
 # ----------------------------------------------------------------------- Sec. 2.2.3
 
 def update_translations(frames, white, mask, ref, w, u, dx, origin, window, refine=True,
