@@ -60,6 +60,7 @@ extern "C" {
  * 16384 x 16384. */
 #define PXST_MAX_PM_RADIUS 15
 #define PXST_MAX_TR_RADIUS 2
+#define PXST_MAX_FRAC_STEPS 15
 
 /* Scan geometry. */
 typedef struct {
@@ -171,6 +172,28 @@ int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double*
                           void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Pixel-map search on a fine grid -- Sec. 2.2.2: the error evaluated at non-integer
+ * positions through the interpolation of Sec. 4, in place of the paraboloid.
+ * For each good pixel the candidates are c + m / steps per axis, c = round-half-up(u_in),
+ * m in [-(r steps + (steps-1)/2), r steps + (steps-1)/2] with r the window radius of
+ * that axis (window.refine is ignored: no paraboloid); the error of a candidate is the
+ * normalised error of pxst_update_pixel_map with every lookup at
+ * (c + m/steps) - dx[n] - origin.  The first minimum in fine-grid order (slow axis
+ * outer) is taken:
+ *   u_out   [2][H][W] float32  c + m/steps at the minimum (u_in where none; may be u_in)
+ *   err_min [H][W]    float32  its normalised error (+inf where none), may be NULL
+ *   argmin  [H][W]    int32    fine index m0' * n1 + m1', m' = m + r steps + (steps-1)/2,
+ *                              n1 = 2 (r_fs steps + (steps-1)/2) + 1; -1 where none; may be NULL
+ * steps: odd, 1 <= steps <= PXST_MAX_FRAC_STEPS (PXST_EINVAL / PXST_EUNSUPPORTED).
+ * Cost: steps^2 integer searches (the fine classes are integer searches with the
+ * translations moved by -q/steps).  Same workspace and errors as pxst_update_pixel_map.
+ */
+int pxst_update_pixel_map_fractional(const pxst_scan* scan, const float* ref, const double* wsum,
+                                     const float* dx, const float* u_in, pxst_window window,
+                                     int32_t steps, float* u_out, float* err_min, int32_t* argmin,
+                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Translation update -- Sec. 2.2.3.  For frame n and integer shift s in the
  * window, the candidate translation is dx_in[n] + s and its error integrates over
  * the good pixels with a valid lookup at u - (dx_in[n] + s) - origin:
@@ -276,7 +299,8 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
 /* Kernel timing for benchmarks: when enabled, the library brackets each launch of
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
- * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "ref_gather",
+ * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "pm_frac" (a whole
+ * fractional-step search), "ref_gather",
  * "tr_partial", "err_pixels", "pm_fast_int8_ops" (the interior-tile search on the
  * matrix cores, counting int8 operations), "reg_filter" and "reg_integrate" (the
  * map regularisation).  pxst_profile_read returns the total milliseconds, the

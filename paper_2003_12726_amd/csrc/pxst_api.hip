@@ -182,6 +182,12 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     const size_t nblk_err = (HW + per_err - 1) / per_err;
     L.err_part = take((size_t)g.N * nblk_err * sizeof(double));
     L.err_pix = take((size_t)g.N * sizeof(double) + sizeof(double));
+    L.frac_dx = take((size_t)g.N * 2 * sizeof(float));
+    L.frac_u = take(2 * HW * sizeof(float));
+    L.frac_e = take(HW * sizeof(float));
+    L.frac_k = take(HW * sizeof(int));
+    L.frac_be = take(HW * sizeof(float));
+    L.frac_bk = take(HW * sizeof(int));
     L.gw = take((2 * GF_MAXR + 1) * sizeof(double));
     L.gtmp = take(2 * HW * sizeof(double));
     // the integration buffers come last: a workspace laid out with them also serves
@@ -374,6 +380,40 @@ int pxst_update_pixel_map(const pxst_scan* scan, const float* ref, const double*
     if ((rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
     return launch_pixel_map(g, *scan, refv, sat, dx, u_in, window, u_out, err_min, argmin, w, L,
                             stream);
+}
+
+int pxst_update_pixel_map_fractional(const pxst_scan* scan, const float* ref, const double* wsum,
+                                     const float* dx, const float* u_in, pxst_window window, int32_t steps,
+                                     float* u_out, float* err_min, int32_t* argmin, void* ws, size_t ws_bytes,
+                                     hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(dx, 4, "dx")) || (rc = check_ptr(u_in, 4, "u_in")) ||
+        (rc = check_ptr(u_out, 4, "u_out")) || (rc = check_ptr(err_min, 4, "err_min", false)) ||
+        (rc = check_ptr(argmin, 4, "argmin", false)))
+        return rc;
+    if ((rc = check_window(window, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
+    if (steps < 1 || steps % 2 == 0) {
+        set_error("steps must be odd and >= 1 (got %d)", steps);
+        return PXST_EINVAL;
+    }
+    if (steps > PXST_MAX_FRAC_STEPS) {
+        set_error("at most %d steps per pixel are supported", PXST_MAX_FRAC_STEPS);
+        return PXST_EUNSUPPORTED;
+    }
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    int* sat = (int*)(w + L.sat);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, sat, (int*)(w + L.sat_tmp),
+                                        (float*)(w + L.rowmax), (int*)(w + L.fscale), stream)))
+        return rc;
+    if ((rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
+    return launch_pixel_map_fractional(g, *scan, refv, sat, dx, u_in, window, steps, u_out, err_min, argmin, w,
+                                       L, stream);
 }
 
 int pxst_update_translations(const pxst_scan* scan, const float* ref, const double* wsum,

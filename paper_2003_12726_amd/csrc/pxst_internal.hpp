@@ -85,6 +85,8 @@ struct Layout {
     // pixel-map regularisation: filter weights and pass buffer; DCT matrices and two
     // [H][W] float64 buffers of the integration (only when integ)
     size_t gw, gtmp;
+    // fractional-step search: shifted translations, one class's result, the best so far
+    size_t frac_dx, frac_u, frac_e, frac_k, frac_be, frac_bk;
     bool integ;
     size_t dct_h, dct_w, ibuf0, ibuf1;
     size_t total;
@@ -204,6 +206,12 @@ int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, c
 // (integrate != 0; the layout must hold the integration buffers).  u_out may be u_in.
 int launch_regularise(const Geom& g, const float* u_in, float* u_out, float sigma, int integrate, char* ws,
                       const Layout& L, hipStream_t s);
+// Fractional-step pixel-map search: steps^2 integer searches with shifted translations,
+// combined per pixel (no paraboloid).  u_out may be u_in.
+int launch_pixel_map_fractional(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
+                                const float* dx, const float* u_in, const pxst_window& win, int steps,
+                                float* u_out, float* err_min, int32_t* argmin, char* ws, const Layout& L,
+                                hipStream_t s);
 int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
 
 // Figures of merit.
