@@ -13,6 +13,7 @@ from .pxst_oracle import (  # noqa: F401
     update_reference,
     update_pixel_map,
     update_pixel_map_fractional,
+    split_half_pixel_maps,
     quadratic_refine,
     update_translations,
     pixel_variance,

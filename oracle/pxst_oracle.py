@@ -196,12 +196,13 @@ def _refine_at(Egrid, kx, ky, rx, ry):
     return 0.0, 0.0
 
 
-def _pixel_errors(frames, W, ref, V, dx, origin, rows, cols, c0, c1, rx, ry):
+def _pixel_errors(frames, W, ref, V, dx, origin, rows, cols, c0, c1, rx, ry, use=None):
     """Normalised error for every candidate of the selected pixels: E[kx, ky, p].
 
     Follows the loop of Sec. 2.2.2: for each candidate (slow-scan index outer,
     fast-scan inner) the error and variance are summed over frames in frame order,
-    counting only frames whose reference lookup is valid.
+    counting only frames whose reference lookup is valid.  ``use`` (N, P) booleans, if
+    given, keep only the (frame, pixel) terms it marks.
     """
     P = rows.shape[0]
     N = frames.shape[0]
@@ -216,6 +217,8 @@ def _pixel_errors(frames, W, ref, V, dx, origin, rows, cols, c0, c1, rx, ry):
         a = c0[None, None, :] + kx - dx[n, 0] - origin[0]
         b = c1[None, None, :] + ky - dx[n, 1] - origin[1]
         g, ok = bilinear_gather(ref, V, a, b)
+        if use is not None:
+            ok = ok & use[n][None, None, :]
         r = I[n][None, None, :] - Wp[None, None, :] * g
         err += np.where(ok, r * r, 0.0)
         v = I[n] - Wp
@@ -225,7 +228,7 @@ def _pixel_errors(frames, W, ref, V, dx, origin, rows, cols, c0, c1, rx, ry):
 
 
 def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=True,
-                     pixels=None, return_errors=False):
+                     pixels=None, return_errors=False, frame_mask=None):
     """Pixel-map update of Sec. 2.2.2.
 
     For each good pixel the candidates are the integer points ``c + k`` with
@@ -235,6 +238,8 @@ def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=
     candidate is empty, keep their map value with error +inf and index -1.
 
     ``pixels``: optional (rows, cols) subset; outputs then cover only those pixels.
+    ``frame_mask``: optional (N, H, W) booleans; only the marked (frame, pixel) terms
+    enter the sums (the data-set halves of the split-half analysis).
     Returns (u_out, err_min, argmin) -- full arrays, or per-subset arrays; with
     ``return_errors`` also the candidate errors E[kx, ky, p] of the good pixels (and,
     when it is "sums", the unnormalised (err, var, count) grids as well).
@@ -258,7 +263,8 @@ def update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine=
     if good.any():
         gr, gc = rows[good], cols[good]
         c = round_half_up(u_sel[:, good])
-        E, sums = _pixel_errors(frames, W, ref, V, dx, origin, gr, gc, c[0], c[1], rx, ry)
+        use = None if frame_mask is None else np.asarray(frame_mask, dtype=bool)[:, gr, gc]
+        E, sums = _pixel_errors(frames, W, ref, V, dx, origin, gr, gc, c[0], c[1], rx, ry, use)
         E_all = (E, sums) if return_errors == "sums" else E
         flat = E.reshape(-1, E.shape[-1])
         k = np.argmin(flat, axis=0)                       # first minimum
@@ -367,6 +373,32 @@ def update_pixel_map_fractional(frames, white, mask, ref, w, dx, u, origin, wind
     if return_errors:
         return res + (E_all,)
     return res
+
+
+def split_half_pixel_maps(frames, white, mask, ref, w, dx, u, origin, window, half, refine=True,
+                          hist_range=1.0, nbins=64):
+    """Split-half analysis (Sec. 2.3, additional analysis): every pixel of every frame
+    belongs to one of two halves (``half`` (N, H, W) in {0, 1}, drawn by the caller);
+    a pixel map is searched from each half against the same reference, and the
+    differences of the two maps are histogrammed per axis as an uncertainty estimate.
+
+    Readings: the searches are the update of Sec. 2.2.2 restricted to the half's
+    (frame, pixel) terms; the histogram takes the good pixels with a result in both
+    halves, per axis, ``nbins`` equal bins over [-hist_range, hist_range] (values
+    outside are not counted, the last bin includes its upper edge: numpy's rule).
+    Returns (u_a, u_b, hist (2, nbins) int64).
+    """
+    half = np.asarray(half)
+    ua, ea, ka = update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine,
+                                  frame_mask=(half == 0))
+    ub, eb, kb = update_pixel_map(frames, white, mask, ref, w, dx, u, origin, window, refine,
+                                  frame_mask=(half == 1))
+    both = (_f64(mask) > 0) & (ka >= 0) & (kb >= 0)
+    hist = np.zeros((2, int(nbins)), dtype=np.int64)
+    for ax in range(2):
+        d = (ua[ax] - ub[ax])[both]
+        hist[ax] = np.histogram(d, bins=int(nbins), range=(-hist_range, hist_range))[0]
+    return ua, ub, hist
 
 
 # ----------------------------------------------------------------------- Sec. 2.2.3
