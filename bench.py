@@ -369,6 +369,42 @@ def fractional_bench(scan, dev, reps: int = 3, steps: int = 3):
             "ms_per_search": avg, "evals_per_s": evals / (avg * 1e-3) if n else None}
 
 
+def split_half_bench(scan, dev, reps: int = 2):
+    """Split-half analysis of the realistic scan (window +-10 px with refinement, random
+    halves of the (frame, pixel) terms, 64-bin histograms), timed with HIP events."""
+    import numpy as np
+    import torch
+    import paper_2003_12726_amd as pxst
+    H, W = scan.det
+    f16 = scan.frames.view(np.int16)
+    sc = pxst.Scan(torch.from_numpy(f16).to(dev), torch.from_numpy(scan.white).to(dev),
+                   torch.from_numpy(scan.mask).to(dev), scan.ref_shape, scan.origin)
+    ws = pxst.alloc_workspace(sc.geom, pxst.make_opts(1, scan.window), device=dev)
+    ref = torch.from_numpy(scan.ref_true.astype(np.float32)).to(dev)
+    wsum = torch.ones(scan.ref_shape, dtype=torch.float64, device=dev)
+    dx = torch.from_numpy(scan.dx0).to(dev)
+    u = torch.from_numpy(scan.u0).to(dev)
+    half = torch.from_numpy(np.random.default_rng(5).integers(0, 2, scan.frames.shape).astype(np.uint8)).to(dev)
+    ua, ub = torch.empty_like(u), torch.empty_like(u)
+    hist = torch.empty((2, 64), dtype=torch.int32, device=dev)
+    win = pxst.make_window(scan.window[0], scan.window[1], True)
+    pxst.split_half_pixel_map(sc, ref, wsum, dx, u, win, half, ua, ub, 1.0, 64, hist, ws)
+    torch.cuda.synchronize()
+    pxst.profile_enable(True)
+    pxst.profile_read("pm_split")
+    for _ in range(reps):
+        pxst.split_half_pixel_map(sc, ref, wsum, dx, u, win, half, ua, ub, 1.0, 64, hist, ws)
+    torch.cuda.synchronize()
+    ms, n, _ = pxst.profile_read("pm_split")
+    pxst.profile_enable(False)
+    nc = (2 * scan.window[0] + 1) * (2 * scan.window[1] + 1)
+    evals = int((scan.mask > 0).sum()) * nc * scan.n_frames   # both halves together
+    avg = ms / max(n, 1)
+    return {"workload": f"{H}x{W}, {scan.n_frames} frames split at random per (frame, pixel), "
+                        f"window +-{scan.window[0]} px with refinement, 64-bin histograms",
+            "ms_per_analysis": avg, "evals_per_s": evals / (avg * 1e-3) if n else None}
+
+
 def pct(xs, q):
     if not xs:
         return None
@@ -494,6 +530,7 @@ def main():
 
     out["regularisation"] = regularisation_bench(scan, dev)
     out["fractional_search"] = fractional_bench(scan, dev)
+    out["split_half"] = split_half_bench(scan, dev)
 
     if served_rows is not None:
         torch.cuda.empty_cache()

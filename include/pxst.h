@@ -194,6 +194,32 @@ int pxst_update_pixel_map_fractional(const pxst_scan* scan, const float* ref, co
                                      void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Split-half analysis -- Sec. 2.3 (additional analysis): every pixel of every frame
+ * belongs to one of two halves of the data set; a pixel map is searched from each half
+ * against the same reference, and the per-axis differences of the two maps are
+ * histogrammed as an estimate of the uncertainty.
+ *   half   [N][H][W] uint8 (in)  0: the term belongs to half A, 1: to half B (the
+ *                                 caller draws the assignment)
+ *   u_a, u_b [2][H][W] float32 (out)  the search of pxst_update_pixel_map (window,
+ *                                 refine) over the terms of half A / B only; pixels
+ *                                 without a result keep u_in.  Must not alias u_in
+ *                                 or each other.
+ *   hist   [2][nbins] int32 (out, may be NULL)  per axis, counts of u_a - u_b over the
+ *                                 good pixels with a result in both halves, in nbins
+ *                                 equal bins over [-hist_range, hist_range] (the last
+ *                                 bin includes its upper edge, values outside are not
+ *                                 counted)
+ * hist_range finite > 0 and 1 <= nbins <= 65536 when hist is given (PXST_EINVAL).
+ * The halves give every pixel its own subset of frames, so this search runs on the
+ * vector ALUs (no matrix-core contraction).  Same workspace as pxst_update_pixel_map.
+ */
+int pxst_split_half_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum,
+                              const float* dx, const float* u_in, pxst_window window,
+                              const uint8_t* half, float* u_a, float* u_b, float hist_range,
+                              int32_t nbins, int32_t* hist, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Translation update -- Sec. 2.2.3.  For frame n and integer shift s in the
  * window, the candidate translation is dx_in[n] + s and its error integrates over
  * the good pixels with a valid lookup at u - (dx_in[n] + s) - origin:
@@ -300,7 +326,7 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
  * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "pm_frac" (a whole
- * fractional-step search), "ref_gather",
+ * fractional-step search), "pm_split" (both split-half searches), "ref_gather",
  * "tr_partial", "err_pixels", "pm_fast_int8_ops" (the interior-tile search on the
  * matrix cores, counting int8 operations), "reg_filter" and "reg_integrate" (the
  * map regularisation).  pxst_profile_read returns the total milliseconds, the

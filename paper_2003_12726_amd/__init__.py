@@ -57,7 +57,7 @@ class CJob(ctypes.Structure):
 
 
 SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_reference_ex",
-           "pxst_update_pixel_map", "pxst_update_pixel_map_fractional",
+           "pxst_update_pixel_map", "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map",
            "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
            "pxst_batch_iterate", "pxst_regularise_pixel_map", "pxst_profile_enable",
            "pxst_profile_read", "pxst_last_error", "pxst_abi_version")
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_update_pixel_map.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_update_pixel_map_fractional.argtypes = [P(CScan), vp, vp, vp, vp, Window, i32, vp, vp, vp, vp,
                                                      sz, vp]
+    lib.pxst_split_half_pixel_map.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, ctypes.c_float,
+                                              i32, vp, vp, sz, vp]
     lib.pxst_update_translations.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_error.argtypes = [P(CScan), vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pxst_solve.argtypes = [P(CScan), P(SolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
@@ -95,7 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_last_error.restype = ctypes.c_char_p
     lib.pxst_abi_version.restype = i32
     for name in ("pxst_update_reference", "pxst_update_reference_ex", "pxst_update_pixel_map",
-                 "pxst_update_pixel_map_fractional",
+                 "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map",
                  "pxst_update_translations",
                  "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_regularise_pixel_map",
                  "pxst_profile_enable",
@@ -216,6 +218,17 @@ def update_pixel_map_fractional(scan: Scan, ref, wsum, dx, u_in, window: Window,
     _check(lib.pxst_update_pixel_map_fractional(ctypes.byref(scan.c()), _ptr(ref), _ptr(wsum), _ptr(dx),
                                                 _ptr(u_in), window, int(steps), _ptr(u_out), _ptr(err_min),
                                                 _ptr(argmin), p, n, _stream(stream)))
+
+
+def split_half_pixel_map(scan: Scan, ref, wsum, dx, u_in, window: Window, half, u_a, u_b,
+                         hist_range: float = 1.0, nbins: int = 64, hist=None, ws=None, stream=None):
+    """Split-half analysis (Sec. 2.3): pixel maps from the two halves of the (frame,
+    pixel) terms marked by half (uint8 0/1) and the histogram of their differences."""
+    lib = load_library()
+    p, n = _ws(ws)
+    _check(lib.pxst_split_half_pixel_map(ctypes.byref(scan.c()), _ptr(ref), _ptr(wsum), _ptr(dx), _ptr(u_in),
+                                         window, _ptr(half), _ptr(u_a), _ptr(u_b), float(hist_range),
+                                         int(nbins), _ptr(hist), p, n, _stream(stream)))
 
 
 def update_translations(scan: Scan, ref, wsum, u, dx_in, window: Window, dx_out, err_min=None,

@@ -416,6 +416,36 @@ int pxst_update_pixel_map_fractional(const pxst_scan* scan, const float* ref, co
                                        L, stream);
 }
 
+int pxst_split_half_pixel_map(const pxst_scan* scan, const float* ref, const double* wsum, const float* dx,
+                              const float* u_in, pxst_window window, const uint8_t* half, float* u_a, float* u_b,
+                              float hist_range, int32_t nbins, int32_t* hist, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(dx, 4, "dx")) || (rc = check_ptr(u_in, 4, "u_in")) || (rc = check_ptr(half, 1, "half")) ||
+        (rc = check_ptr(u_a, 4, "u_a")) || (rc = check_ptr(u_b, 4, "u_b")) ||
+        (rc = check_ptr(hist, 4, "hist", false)))
+        return rc;
+    if (u_a == u_in || u_b == u_in || u_a == u_b) {
+        set_error("u_a, u_b and u_in must be distinct arrays");
+        return PXST_EINVAL;
+    }
+    if ((rc = check_window(window, PXST_MAX_PM_RADIUS, "pixel-map"))) return rc;
+    if (hist && (!(hist_range > 0.f) || !std::isfinite(hist_range) || nbins < 1 || nbins > 65536)) {
+        set_error("histogram: range must be finite and > 0, 1 <= nbins <= 65536");
+        return PXST_EINVAL;
+    }
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    char* w = (char*)ws;
+    float* refv = (float*)(w + L.refv);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
+    return launch_split_half(g, *scan, refv, dx, u_in, window, half, u_a, u_b, (double)hist_range, nbins, hist, w,
+                             L, stream);
+}
+
 int pxst_update_translations(const pxst_scan* scan, const float* ref, const double* wsum,
                              const float* u, const float* dx_in, pxst_window window, float* dx_out,
                              float* err_min, int32_t* argmin, void* ws, size_t ws_bytes,

@@ -212,6 +212,11 @@ int launch_pixel_map_fractional(const Geom& g, const pxst_scan& sc, const float*
                                 const float* dx, const float* u_in, const pxst_window& win, int steps,
                                 float* u_out, float* err_min, int32_t* argmin, char* ws, const Layout& L,
                                 hipStream_t s);
+// Split-half analysis: two pixel-map searches, one per half of the (frame, pixel) terms,
+// and the histogram of their differences (hist may be null).
+int launch_split_half(const Geom& g, const pxst_scan& sc, const float* refv, const float* dx, const float* u_in,
+                      const pxst_window& win, const uint8_t* half, float* u_a, float* u_b, double hist_range,
+                      int nbins, int32_t* hist, char* ws, const Layout& L, hipStream_t s);
 int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
 
 // Figures of merit.
