@@ -14,6 +14,9 @@ from .pxst_oracle import (  # noqa: F401
     update_pixel_map,
     update_pixel_map_fractional,
     split_half_pixel_maps,
+    linear_map,
+    reference_contrast,
+    defocus_sweep,
     quadratic_refine,
     update_translations,
     pixel_variance,

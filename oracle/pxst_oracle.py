@@ -401,6 +401,44 @@ def split_half_pixel_maps(frames, white, mask, ref, w, dx, u, origin, window, ha
     return ua, ub, hist
 
 
+def linear_map(shape, scale, centre=None):
+    """Pixel map of a pure magnification change on a fixed reference grid (Sec. 2.1:
+    u = x for an ideal lens at the nominal magnification; a different magnification
+    scales the detector coordinates about a fixed point).  Reading: u[0] = c0 + s0 (i -
+    c0), u[1] = c1 + s1 (j - c1), c the detector centre ((H-1)/2, (W-1)/2) unless given."""
+    H, W = shape
+    c0, c1 = ((H - 1) / 2.0, (W - 1) / 2.0) if centre is None else (float(centre[0]), float(centre[1]))
+    ii, jj = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    return np.stack([c0 + float(scale[0]) * (ii - c0), c1 + float(scale[1]) * (jj - c1)])
+
+
+def reference_contrast(ref, w):
+    """Contrast of a reference image: variance over mean squared of the pixels with a
+    positive weight sum (reading of "the image will lack contrast"); 0 without any."""
+    ref, sel = _f64(ref), _f64(w) > 0
+    if not sel.any():
+        return 0.0
+    v = ref[sel]
+    m = v.mean()
+    return float(((v - m) ** 2).mean() / (m * m)) if m != 0 else 0.0
+
+
+def defocus_sweep(frames, white, mask, dx, origin, ref_shape, scales, centre=None):
+    """Defocus by registration (Sec. 2.1, fit_defocus_registration): a reference image is
+    built (Sec. 2.2.1) from the linear map of every candidate magnification (given as
+    per-axis scale factors of the map), and the candidate with the greatest contrast
+    (first maximum) is chosen.  The maps are rounded to float32, as the GPU holds them.
+    Returns (contrast per candidate, index of the best)."""
+    H, W = _f64(white).shape
+    out = []
+    for sc in np.asarray(scales, dtype=np.float64).reshape(-1, 2):
+        u = linear_map((H, W), sc, centre).astype(np.float32)
+        ref, w = update_reference(frames, white, mask, u, dx, origin, ref_shape)
+        out.append(reference_contrast(ref.astype(np.float32), w))
+    c = np.array(out)
+    return c, int(np.argmax(c))
+
+
 # ----------------------------------------------------------------------- Sec. 2.2.3
 
 def update_translations(frames, white, mask, ref, w, u, dx, origin, window, refine=True,
