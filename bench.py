@@ -405,6 +405,35 @@ def split_half_bench(scan, dev, reps: int = 2):
             "ms_per_analysis": avg, "evals_per_s": evals / (avg * 1e-3) if n else None}
 
 
+def defocus_bench(scan, dev):
+    """Defocus-by-registration sweep of the realistic scan: 5 x 5 per-axis map scales
+    around 1 (reference update and contrast per candidate), timed with HIP events."""
+    import numpy as np
+    import torch
+    import paper_2003_12726_amd as pxst
+    H, W = scan.det
+    f16 = scan.frames.view(np.int16)
+    sc = pxst.Scan(torch.from_numpy(f16).to(dev), torch.from_numpy(scan.white).to(dev),
+                   torch.from_numpy(scan.mask).to(dev), scan.ref_shape, scan.origin)
+    ws = pxst.alloc_workspace(sc.geom, None, device=dev)
+    dx = torch.from_numpy(scan.dx0).to(dev)
+    scales = np.array([(a, b) for a in (0.98, 0.99, 1.0, 1.01, 1.02) for b in (0.98, 0.99, 1.0, 1.01, 1.02)],
+                      dtype=np.float32)
+    c = torch.empty(len(scales), dtype=torch.float64, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+    pxst.defocus_sweep(sc, dx, scales[:2], c, best, None, ws)
+    torch.cuda.synchronize()
+    pxst.profile_enable(True)
+    pxst.profile_read("defocus_sweep")
+    pxst.defocus_sweep(sc, dx, scales, c, best, None, ws)
+    torch.cuda.synchronize()
+    ms, n, _ = pxst.profile_read("defocus_sweep")
+    pxst.profile_enable(False)
+    return {"workload": f"{H}x{W}, {scan.n_frames} frames, 25 candidate map scales (5 x 5 around 1)",
+            "ms_per_sweep": ms, "ms_per_candidate": ms / len(scales),
+            "best_scale": [float(x) for x in scales[int(best.cpu().numpy()[0])]]}
+
+
 def pct(xs, q):
     if not xs:
         return None
@@ -531,6 +560,7 @@ def main():
     out["regularisation"] = regularisation_bench(scan, dev)
     out["fractional_search"] = fractional_bench(scan, dev)
     out["split_half"] = split_half_bench(scan, dev)
+    out["defocus_sweep"] = defocus_bench(scan, dev)
 
     if served_rows is not None:
         torch.cuda.empty_cache()

@@ -220,6 +220,25 @@ int pxst_split_half_pixel_map(const pxst_scan* scan, const float* ref, const dou
                               size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Defocus by registration -- Sec. 2.1 (fit_defocus_registration): a reference image is
+ * built (Sec. 2.2.1, exact arithmetic) from the map of every candidate magnification,
+ * and the candidate whose reference has the greatest contrast is chosen.
+ *   scales  [n_cand][2] float32, HOST memory (in)  per-axis scale factors s of the
+ *                       linear map u = c + s (x - c) of a magnification change on the
+ *                       fixed reference grid (scan geometry), x the detector pixel
+ *   centre_ss, centre_fs  the fixed point c; NaN: the detector centre ((H-1)/2, (W-1)/2)
+ *   dx      [N][2] float32 (in)
+ *   contrast [n_cand] float64 (out)  variance / mean^2 of the reference pixels with a
+ *                       positive weight sum (0 when there are none)
+ *   best    [1] int32 (out, may be NULL)  index of the first maximum of contrast
+ * n_cand >= 1 and finite scales (PXST_EINVAL).  Uses the reference-update part of the
+ * workspace; candidates run one after the other on `stream`.
+ */
+int pxst_defocus_sweep(const pxst_scan* scan, const float* dx, const float* scales, int32_t n_cand,
+                       float centre_ss, float centre_fs, double* contrast, int32_t* best,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Translation update -- Sec. 2.2.3.  For frame n and integer shift s in the
  * window, the candidate translation is dx_in[n] + s and its error integrates over
  * the good pixels with a valid lookup at u - (dx_in[n] + s) - origin:
@@ -326,7 +345,8 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
  * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "pm_frac" (a whole
- * fractional-step search), "pm_split" (both split-half searches), "ref_gather",
+ * fractional-step search), "pm_split" (both split-half searches), "defocus_sweep",
+ * "ref_gather",
  * "tr_partial", "err_pixels", "pm_fast_int8_ops" (the interior-tile search on the
  * matrix cores, counting int8 operations), "reg_filter" and "reg_integrate" (the
  * map regularisation).  pxst_profile_read returns the total milliseconds, the

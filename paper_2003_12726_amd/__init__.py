@@ -58,7 +58,7 @@ class CJob(ctypes.Structure):
 
 SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_reference_ex",
            "pxst_update_pixel_map", "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map",
-           "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
+           "pxst_defocus_sweep", "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
            "pxst_batch_iterate", "pxst_regularise_pixel_map", "pxst_profile_enable",
            "pxst_profile_read", "pxst_last_error", "pxst_abi_version")
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                      sz, vp]
     lib.pxst_split_half_pixel_map.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, ctypes.c_float,
                                               i32, vp, vp, sz, vp]
+    lib.pxst_defocus_sweep.argtypes = [P(CScan), vp, P(ctypes.c_float), i32, ctypes.c_float, ctypes.c_float, vp,
+                                       vp, vp, sz, vp]
     lib.pxst_update_translations.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_error.argtypes = [P(CScan), vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pxst_solve.argtypes = [P(CScan), P(SolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
@@ -97,7 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_last_error.restype = ctypes.c_char_p
     lib.pxst_abi_version.restype = i32
     for name in ("pxst_update_reference", "pxst_update_reference_ex", "pxst_update_pixel_map",
-                 "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map",
+                 "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map", "pxst_defocus_sweep",
                  "pxst_update_translations",
                  "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_regularise_pixel_map",
                  "pxst_profile_enable",
@@ -229,6 +231,19 @@ def split_half_pixel_map(scan: Scan, ref, wsum, dx, u_in, window: Window, half, 
     _check(lib.pxst_split_half_pixel_map(ctypes.byref(scan.c()), _ptr(ref), _ptr(wsum), _ptr(dx), _ptr(u_in),
                                          window, _ptr(half), _ptr(u_a), _ptr(u_b), float(hist_range),
                                          int(nbins), _ptr(hist), p, n, _stream(stream)))
+
+
+def defocus_sweep(scan: Scan, dx, scales, contrast, best=None, centre=None, ws=None, stream=None):
+    """Defocus by registration (Sec. 2.1): reference contrast for every candidate pair of
+    per-axis map scales (host array [n, 2]); best receives the first maximum."""
+    import numpy as np
+    lib = load_library()
+    p, n = _ws(ws)
+    sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float32).reshape(-1, 2))
+    c = (float("nan"), float("nan")) if centre is None else (float(centre[0]), float(centre[1]))
+    _check(lib.pxst_defocus_sweep(ctypes.byref(scan.c()), _ptr(dx),
+                                  sc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(sc.shape[0]), c[0], c[1],
+                                  _ptr(contrast), _ptr(best), p, n, _stream(stream)))
 
 
 def update_translations(scan: Scan, ref, wsum, u, dx_in, window: Window, dx_out, err_min=None,

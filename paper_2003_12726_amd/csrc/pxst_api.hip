@@ -188,6 +188,10 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     L.frac_k = take(HW * sizeof(int));
     L.frac_be = take(HW * sizeof(float));
     L.frac_bk = take(HW * sizeof(int));
+    L.sweep_u = take(2 * HW * sizeof(float));
+    L.sweep_ref = take(RR * sizeof(float));
+    L.sweep_w = take(RR * sizeof(double));
+    L.sweep_part = take(3 * SWEEP_BLOCKS * sizeof(double));
     L.gw = take((2 * GF_MAXR + 1) * sizeof(double));
     L.gtmp = take(2 * HW * sizeof(double));
     // the integration buffers come last: a workspace laid out with them also serves
@@ -444,6 +448,35 @@ int pxst_split_half_pixel_map(const pxst_scan* scan, const float* ref, const dou
     if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
     return launch_split_half(g, *scan, refv, dx, u_in, window, half, u_a, u_b, (double)hist_range, nbins, hist, w,
                              L, stream);
+}
+
+int pxst_defocus_sweep(const pxst_scan* scan, const float* dx, const float* scales, int32_t n_cand,
+                       float centre_ss, float centre_fs, double* contrast, int32_t* best, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(dx, 4, "dx")) || (rc = check_ptr(contrast, 8, "contrast")) ||
+        (rc = check_ptr(best, 4, "best", false)))
+        return rc;
+    if (n_cand < 1 || !scales) {
+        set_error("the sweep needs at least one candidate (n_cand = %d) and its scales", n_cand);
+        return PXST_EINVAL;
+    }
+    for (int k = 0; k < 2 * n_cand; ++k)
+        if (!std::isfinite(scales[k])) {
+            set_error("scale %d is not finite", k);
+            return PXST_EINVAL;
+        }
+    const Geom g = geom_of(scan->geom);
+    const Layout L = make_layout(g, TR_CT_MAX);
+    if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+    const double c0 = std::isnan(centre_ss) ? 0.5 * (g.H - 1) : (double)centre_ss;
+    const double c1 = std::isnan(centre_fs) ? 0.5 * (g.W - 1) : (double)centre_fs;
+    if (!std::isfinite(c0) || !std::isfinite(c1)) {
+        set_error("centre must be finite or NaN");
+        return PXST_EINVAL;
+    }
+    return launch_defocus_sweep(g, *scan, dx, scales, n_cand, c0, c1, contrast, best, (char*)ws, L, stream);
 }
 
 int pxst_update_translations(const pxst_scan* scan, const float* ref, const double* wsum,

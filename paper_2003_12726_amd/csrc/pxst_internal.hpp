@@ -87,11 +87,15 @@ struct Layout {
     size_t gw, gtmp;
     // fractional-step search: shifted translations, one class's result, the best so far
     size_t frac_dx, frac_u, frac_e, frac_k, frac_be, frac_bk;
+    // defocus sweep: a candidate's map, reference, weights and contrast partials
+    size_t sweep_u, sweep_ref, sweep_w, sweep_part;
     bool integ;
     size_t dct_h, dct_w, ibuf0, ibuf1;
     size_t total;
 };
 
+// Work-groups of the contrast reduction of the defocus sweep.
+constexpr int SWEEP_BLOCKS = 256;
 // Largest filter radius (|k| <= int(4 sigma + 0.5)) of the pixel-map regularisation.
 constexpr int GF_MAXR = 256;
 
@@ -217,6 +221,11 @@ int launch_pixel_map_fractional(const Geom& g, const pxst_scan& sc, const float*
 int launch_split_half(const Geom& g, const pxst_scan& sc, const float* refv, const float* dx, const float* u_in,
                       const pxst_window& win, const uint8_t* half, float* u_a, float* u_b, double hist_range,
                       int nbins, int32_t* hist, char* ws, const Layout& L, hipStream_t s);
+// Defocus sweep: reference update and contrast for every candidate scale pair (scales
+// in host memory), first maximum into best (may be null).
+int launch_defocus_sweep(const Geom& g, const pxst_scan& sc, const float* dx, const float* scales, int n_cand,
+                         double c0, double c1, double* contrast, int32_t* best, char* ws, const Layout& L,
+                         hipStream_t s);
 int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
 
 // Figures of merit.
