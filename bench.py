@@ -448,6 +448,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-divergent", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the regularisation, fractional, split-half and defocus sections")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--served-jobs", type=int, default=64)
     ap.add_argument("--served-speedup", type=float, default=50.0)
@@ -557,10 +559,11 @@ def main():
         del dj
         torch.cuda.empty_cache()
 
-    out["regularisation"] = regularisation_bench(scan, dev)
-    out["fractional_search"] = fractional_bench(scan, dev)
-    out["split_half"] = split_half_bench(scan, dev)
-    out["defocus_sweep"] = defocus_bench(scan, dev)
+    if not args.no_extras:
+        out["regularisation"] = regularisation_bench(scan, dev)
+        out["fractional_search"] = fractional_bench(scan, dev)
+        out["split_half"] = split_half_bench(scan, dev)
+        out["defocus_sweep"] = defocus_bench(scan, dev)
 
     if served_rows is not None:
         torch.cuda.empty_cache()

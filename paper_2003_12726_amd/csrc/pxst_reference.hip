@@ -306,11 +306,22 @@ struct GatherArgs {
 
 // fsort[n][e] = frames[n][vals[e]]: a frame value of a sorted entry is then read at the
 // entry's own index, not through its pixel index.
+// One thread per entry and a group of SF_FRAMES frames (grid y): the pixel index is read
+// once per group.
+constexpr int SF_FRAMES = 16;
 __global__ void k_sort_frames(const uint16_t* __restrict__ frames, const unsigned* __restrict__ vals,
-                              int HW, const unsigned* __restrict__ n_good, uint16_t* __restrict__ fsort) {
+                              int HW, int N, const unsigned* __restrict__ n_good, uint16_t* __restrict__ fsort) {
     const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t n = blockIdx.y;
-    if (e < *n_good) fsort[n * HW + e] = frames[n * HW + vals[e]];
+    if (e >= *n_good) return;
+    const size_t k = vals[e];
+    const int n0 = blockIdx.y * SF_FRAMES, n1 = min(N, n0 + SF_FRAMES);
+    uint16_t v[SF_FRAMES];
+#pragma unroll
+    for (int t = 0; t < SF_FRAMES; ++t)
+        if (n0 + t < n1) v[t] = frames[(size_t)(n0 + t) * HW + k];
+#pragma unroll
+    for (int t = 0; t < SF_FRAMES; ++t)
+        if (n0 + t < n1) fsort[(size_t)(n0 + t) * HW + e] = v[t];
 }
 
 // Contribution of sorted entry e in frame n to reference pixel (p0, p1): value and weight.
@@ -865,8 +876,8 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     const unsigned* n_good = cstart + ncells + KEY_INVALID_OFF;   // entries of good pixels
     hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals,
                        HW, n_good, g.o0, g.o1, gi, GH, GW, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
-    hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), g.N), dim3(256), 0, s, sc.frames,
-                       vals, HW, n_good, (uint16_t*)(ws + L.fsort));
+    hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), (g.N + SF_FRAMES - 1) / SF_FRAMES), dim3(256), 0,
+                       s, sc.frames, vals, HW, g.N, n_good, (uint16_t*)(ws + L.fsort));
     return check_hip(hipGetLastError(), "inverse map");
 }
 

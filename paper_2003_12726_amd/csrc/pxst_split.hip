@@ -145,17 +145,36 @@ __device__ inline int hist_bin(double d, double R, int nb) {
     return k;
 }
 
-__global__ void k_split_hist(const float* __restrict__ ua, const float* __restrict__ ub, const int* __restrict__ ka,
-                             const int* __restrict__ kb, const uint8_t* __restrict__ mask, size_t HW, double R,
-                             int nb, int* __restrict__ hist) {
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= HW) return;
-    if (!mask[p] || ka[p] < 0 || kb[p] < 0) return;
-    for (int ax = 0; ax < 2; ++ax) {
-        const double d = (double)ua[ax * HW + p] - (double)ub[ax * HW + p];
-        const int k = hist_bin(d, R, nb);
-        if (k >= 0) atomicAdd(&hist[ax * nb + k], 1);
+// Counts per work-group in LDS (bins of both axes, up to HIST_LDS of them), then one
+// global addition per non-empty bin; beyond that, global additions per value.
+constexpr int HIST_LDS = 8192, HIST_THREADS = 256, HIST_PIX = 4096;
+__global__ __launch_bounds__(HIST_THREADS) void k_split_hist(const float* __restrict__ ua, const float* __restrict__ ub,
+                                                             const int* __restrict__ ka, const int* __restrict__ kb,
+                                                             const uint8_t* __restrict__ mask, size_t HW, double R,
+                                                             int nb, int* __restrict__ hist) {
+    __shared__ int lh[HIST_LDS];
+    const bool local = 2 * nb <= HIST_LDS;
+    if (local)
+        for (int i = threadIdx.x; i < 2 * nb; i += HIST_THREADS) lh[i] = 0;
+    __syncthreads();
+    const size_t p0 = (size_t)blockIdx.x * HIST_PIX;
+    const size_t p1 = min(HW, p0 + HIST_PIX);
+    for (size_t p = p0 + threadIdx.x; p < p1; p += HIST_THREADS) {
+        if (!mask[p] || ka[p] < 0 || kb[p] < 0) continue;
+        for (int ax = 0; ax < 2; ++ax) {
+            const double d = (double)ua[ax * HW + p] - (double)ub[ax * HW + p];
+            const int k = hist_bin(d, R, nb);
+            if (k < 0) continue;
+            if (local)
+                atomicAdd(&lh[ax * nb + k], 1);
+            else
+                atomicAdd(&hist[ax * nb + k], 1);
+        }
     }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < 2 * nb; i += HIST_THREADS)
+            if (lh[i]) atomicAdd(&hist[i], lh[i]);
 }
 
 }  // namespace
@@ -196,8 +215,8 @@ int launch_split_half(const Geom& g, const pxst_scan& sc, const float* refv, con
     profile_end("pm_split", s, 0, nullptr, 0);
     if (hist) {
         hipLaunchKernelGGL(k_fill_i32, dim3((2 * nbins + 255) / 256), dim3(256), 0, s, hist, 2 * nbins, 0);
-        hipLaunchKernelGGL(k_split_hist, dim3((unsigned)((HW + 255) / 256)), dim3(256), 0, s, u_a, u_b, ka, kb,
-                           sc.mask, HW, hist_range, nbins, hist);
+        hipLaunchKernelGGL(k_split_hist, dim3((unsigned)((HW + HIST_PIX - 1) / HIST_PIX)), dim3(HIST_THREADS), 0, s,
+                           u_a, u_b, ka, kb, sc.mask, HW, hist_range, nbins, hist);
     }
     return check_hip(hipGetLastError(), "split-half pixel maps");
 }
