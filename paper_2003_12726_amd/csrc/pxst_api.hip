@@ -174,6 +174,16 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     L.kblocks = (g.N + MM_KB - 1) / MM_KB;
     L.ipk = take(ntiles * (size_t)L.kblocks * MM_PACK_BYTES);
     L.pstat = take(ntiles * 64 * 4 * sizeof(double));
+    {
+        const size_t pb = 3 * RR * (size_t)L.kblocks * MM_KB;
+        L.planes_on = pb <= PLANES_MAX;
+        if (L.planes_on) {
+            L.planes = take(pb);
+            L.pcs = take(RR * sizeof(double));
+            L.pgu = take(RR * sizeof(double));
+            L.prow = take((size_t)g.Rs * 2 * sizeof(int));
+        }
+    }
     L.rowmax = take((size_t)g.Rs * sizeof(float));
     L.fscale = take(sizeof(int));
     const size_t nblk_tr = (HW + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK;

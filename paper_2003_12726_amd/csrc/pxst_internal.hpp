@@ -78,6 +78,10 @@ struct Layout {
     size_t ipk, pstat;        // frames packed as int8 matrix operands; per-pixel frame sums
     size_t rowmax, fscale;    // per-row max |reference| and the fixed-point exponent
     int kblocks;              // frame K-blocks of the packed frames
+    // interior tiles' B operand planes per reference position and their column sums
+    // (when planes_on: 3 Rs Rf NP bytes within PLANES_MAX)
+    bool planes_on;
+    size_t planes, pcs, pgu, prow;
     // translations
     size_t tr_part;
     // error
@@ -94,6 +98,8 @@ struct Layout {
     size_t total;
 };
 
+// Largest precomputed operand planes (3 Rs Rf x padded frames bytes).
+constexpr size_t PLANES_MAX = (size_t)2 << 30;
 // Work-groups of the contrast reduction of the defocus sweep.
 constexpr int SWEEP_BLOCKS = 256;
 // Largest filter radius (|k| <= int(4 sigma + 0.5)) of the pixel-map regularisation.

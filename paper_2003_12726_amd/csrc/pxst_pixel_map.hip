@@ -56,6 +56,12 @@ struct PmArgs {
     int mm_on;          // bits: interior tiles / edge tiles on the matrix cores, frames
                         // staged in LDS for interior / edge tiles
     int mm_slow_max;    // slow-frame capacity of a matrix-core edge tile
+    // interior tiles' B operand precomputed per reference position (null: generated in
+    // the search kernel): three byte planes [3][Rs Rf][NP] of the positions relative to
+    // frame 0's integer shift, and per position the column sums sum g~^2 and sum G~
+    const uint8_t* planes;
+    const double* pcs;
+    const double* pgu;
 };
 
 
@@ -929,7 +935,192 @@ MmPlan mm_plan(int nx, int ny, int n_frames) {
     return p;
 }
 
-template <bool LDSA, bool EDGE, int MH>
+// Frame-table entry of the matrix-core search: the bilinear weights of the frame's
+// fractional shift scaled by 2^F (zero weights for padding frames and frames left out),
+// and the byte offset of its integer shift, 4 (e0 Rf + e1) modulo 2^32.
+__device__ inline void mm_frame_entry(const PmArgs& a, int nn, bool zero, float fs, float4& w, unsigned& go4) {
+    const AxisShift s0 = axis_shift(a.dx[2 * nn], a.o0);
+    const AxisShift s1 = axis_shift(a.dx[2 * nn + 1], a.o1);
+    go4 = 4u * (unsigned)(s0.e * a.Rf + s1.e);
+    const float t0 = s0.t, t1 = s1.t;
+    w = zero ? make_float4(0.f, 0.f, 0.f, 0.f)
+             : make_float4((1.f - t0) * (1.f - t1) * fs, (1.f - t0) * t1 * fs, t0 * (1.f - t1) * fs, t0 * t1 * fs);
+}
+
+// The 16 values of one lane's (position, 16 frames) as the three biased byte operands,
+// with the rounding of g 2^F to an integer offset by 2^23 (from the bits of
+// v + 1.5 2^23, |v| < 2^22); gt = rounded value, gu = gt + 2^23.
+__device__ inline void mm_pack_b(const float (&vals)[16], unsigned (&B0)[4], unsigned (&B1)[4], unsigned (&B2)[4],
+                                 double& CS, unsigned& gsum) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        unsigned u[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int t = 4 * w + b;
+            const unsigned gu = __float_as_uint(vals[t] + 12582912.f) - 0x4AC00000u;
+            const int gt = (int)gu - (1 << 23);
+            CS = fma((double)gt, (double)gt, CS);
+            gsum += gu;
+            u[b] = gu;
+        }
+        const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
+        const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
+        const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
+        const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
+        B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
+        B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
+        B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
+    }
+}
+
+// Column span [x, y] per plane row of the interior tiles' region positions (relative to
+// frame 0's integer shift); spans start empty (x > y).
+__global__ void k_planes_span_clear(int2* __restrict__ prow, int Rs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < Rs) prow[r] = make_int2(INT_MAX, INT_MIN);
+}
+// One work-group per row of tiles: the union of its interior tiles' regions (a band of
+// plane rows with one column span, a superset of the exact spans), then one atomic pair
+// per plane row of the band.
+__global__ __launch_bounds__(256) void k_planes_span(const PmArgs a, int2* __restrict__ prow) {
+    __shared__ int red[4][4];
+    const int ty = blockIdx.x;
+    const int e00 = axis_shift(a.dx[0], a.o0).e, e01 = axis_shift(a.dx[1], a.o1).e;
+    int rlo = INT_MAX, rhi = INT_MIN, clo = INT_MAX, chi = INT_MIN;
+    for (int tx = threadIdx.x; tx < a.tiles_x; tx += 256) {
+        const int tile = ty * a.tiles_x + tx;
+        if (a.tinfo[tile].x != CNT_FAST) continue;
+        const TileDesc td = a.tiles[tile];
+        const int r0 = td.cmin0 - a.rx - e00, c0 = td.cmin1 - a.ry - e01;
+        rlo = min(rlo, r0);
+        rhi = max(rhi, r0 + td.rh - 1);
+        clo = min(clo, c0);
+        chi = max(chi, c0 + td.rw - 1);
+    }
+    rlo = wave_min_i(rlo);
+    rhi = wave_max_i(rhi);
+    clo = wave_min_i(clo);
+    chi = wave_max_i(chi);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = rlo;
+        red[w][1] = rhi;
+        red[w][2] = clo;
+        red[w][3] = chi;
+    }
+    __syncthreads();
+    rlo = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+    rhi = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1]));
+    clo = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+    chi = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
+    if (rlo > rhi) return;
+    clo = max(clo, 0);
+    chi = min(chi, a.Rf - 1);
+    for (int r = max(rlo, 0) + (int)threadIdx.x; r <= min(rhi, a.Rs - 1); r += 256) {
+        atomicMin(&prow[r].x, clo);
+        atomicMax(&prow[r].y, chi);
+    }
+}
+
+// B operand of the interior tiles, precomputed once per search for every reference
+// position P (coordinates relative to frame 0's integer shift: the interior tiles'
+// positions X all have X - e_0 in the grid, since every lookup of theirs is valid),
+// over each plane row's span of interior-tile positions (prow, from k_planes_span):
+// the same bytes the search kernel would generate, in planes [3][Rs Rf][NP] whose 16
+// bytes at (P, 64 kb + 16 g) are lane (c, g)'s operand; and per position the sums
+// sum_n g~_n^2 (exact 64-bit integer, converted once) and sum_n G~_n.  Positions whose
+// lookups leave the grid get zeros (no interior tile reads them).  A wave takes 16
+// positions x 4 frame groups, the layout of the search's B operand.
+constexpr int PL_THREADS = 256;
+constexpr int PL_COLS = 256;   // columns of a plane row per work-group
+__global__ __launch_bounds__(PL_THREADS) void k_pm_planes(const PmArgs a, const int2* __restrict__ prow,
+                                                          uint8_t* __restrict__ planes, double* __restrict__ pcs,
+                                                          double* __restrict__ pgu) {
+    extern __shared__ float4 plsm[];
+    const int NP = a.kblocks * MM_KB, KB = a.kblocks, Rf = a.Rf, Rs = a.Rs;
+    // per frame: weights, the byte offset of the lookup relative to the position's
+    // (4 ((e0 - e_n) . (Rf, 1)), modulo 2^32), the first valid column and whether this
+    // block's row is valid
+    float4* fw = plsm;
+    unsigned* dgo = (unsigned*)(fw + NP);
+    int* clo = (int*)(dgo + NP);
+    int* rok = clo + NP;
+    const int pr = blockIdx.y;
+    const int2 span = prow[pr];
+    const int cb = blockIdx.x * PL_COLS;
+    if (span.x > span.y || cb + PL_COLS <= span.x || cb > span.y) return;
+    const float fs = ldexpf(1.f, *a.fscale);
+    const int e00 = axis_shift(a.dx[0], a.o0).e, e01 = axis_shift(a.dx[1], a.o1).e;
+    for (int n = threadIdx.x; n < NP; n += PL_THREADS) {
+        const bool zero = n >= a.N;
+        const int nn = zero ? 0 : n;
+        unsigned go4;
+        mm_frame_entry(a, nn, zero, fs, fw[n], go4);
+        const int ex = axis_shift(a.dx[2 * nn], a.o0).e, ey = axis_shift(a.dx[2 * nn + 1], a.o1).e;
+        dgo[n] = 4u * (unsigned)((e00 - ex) * Rf + (e01 - ey));
+        clo[n] = ey - e01;
+        const int rr = pr + e00 - ex;
+        rok[n] = rr >= 0 && rr + 1 < Rs;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, g = lane >> 4;
+    const size_t RR = (size_t)Rs * Rf;
+    const size_t stride = RR * NP;
+    const char* __restrict__ refb = (const char*)a.refv;
+    const unsigned rf4 = 4u * (unsigned)Rf;
+    for (int col0 = cb + wave * 16; col0 < cb + PL_COLS; col0 += (PL_THREADS / 64) * 16) {
+        const int pcol = col0 + c;
+        const bool pv = pcol >= span.x && pcol <= span.y && pcol < Rf;
+        const int pc = min(max(pcol, 0), Rf - 1);
+        const size_t P = (size_t)pr * Rf + pc;
+        const unsigned pos4 = 4u * (unsigned)P;
+        long long cs = 0;
+        unsigned long long gs = 0;
+        for (int kb = 0; kb < KB; ++kb) {
+            const int nb = kb * MM_KB + 16 * g;
+            float vals[16];
+            float2 top[16], bot[16];
+            bool in[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                in[t] = rok[nb + t] && (unsigned)(pc - clo[nb + t]) <= (unsigned)(Rf - 2);
+                const unsigned e4 = in[t] ? pos4 + dgo[nb + t] : 0u;
+                top[t] = *(const float2*)(refb + e4);
+                bot[t] = *(const float2*)(refb + (e4 + rf4));
+            }
+            double part = 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float4 wt = fw[nb + t];
+                const float v = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                vals[t] = in[t] && v == v ? v : 0.f;
+            }
+            unsigned B0[4], B1[4], B2[4];
+            unsigned gsum = 0;
+            // (16 squares below 2^44 each: the float64 partial is exact)
+            mm_pack_b(vals, B0, B1, B2, part, gsum);
+            cs += (long long)part;
+            gs += gsum;
+            if (pv) {
+                const size_t off = P * NP + nb;
+                *(uint4*)(planes + off) = make_uint4(B0[0], B0[1], B0[2], B0[3]);
+                *(uint4*)(planes + stride + off) = make_uint4(B1[0], B1[1], B1[2], B1[3]);
+                *(uint4*)(planes + 2 * stride + off) = make_uint4(B2[0], B2[1], B2[2], B2[3]);
+            }
+        }
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        gs += __shfl_xor(gs, 16, 64);
+        gs += __shfl_xor(gs, 32, 64);
+        if (pv && g == 0) {
+            pcs[P] = (double)cs;
+            pgu[P] = (double)gs;
+        }
+    }
+}
+
+template <bool LDSA, bool EDGE, int MH, bool PLANES = false>
 __device__ void pm_mma_item(const PmArgs& a, int slot) {
     extern __shared__ float smem[];
     const int cnt = EDGE ? CNT_EDGE_MM : CNT_FAST;
@@ -1005,14 +1196,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     const float fs = ldexpf(1.f, *a.fscale);
     for (int n = tid; n < NP; n += MM_THREADS) {
         const bool zero = n >= N || (EDGE && sflag[n]);
-        const int nn = zero ? nref : n;
-        const AxisShift s0 = axis_shift(a.dx[2 * nn], a.o0);
-        const AxisShift s1 = axis_shift(a.dx[2 * nn + 1], a.o1);
-        fgo4[n] = 4u * (unsigned)(s0.e * Rf + s1.e);
-        const float t0 = s0.t, t1 = s1.t;
-        fw[n] = zero ? make_float4(0.f, 0.f, 0.f, 0.f)
-                     : make_float4((1.f - t0) * (1.f - t1) * fs, (1.f - t0) * t1 * fs,
-                                   t0 * (1.f - t1) * fs, t0 * t1 * fs);
+        mm_frame_entry(a, zero ? nref : n, zero, fs, fw[n], fgo4[n]);
     }
     if (EDGE) {
         for (int e = tid; e < nslow * 64; e += MM_THREADS) {
@@ -1071,6 +1255,8 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 
     const double kconst = 16384.0 * 257.0 * 65793.0 * (double)(KB * MM_KB);
     const int c = lane & 15, g = lane >> 4;
+    const int pe00 = PLANES ? axis_shift(a.dx[0], a.o0).e : 0, pe01 = PLANES ? axis_shift(a.dx[1], a.o1).e : 0;
+    const size_t pstride = (size_t)a.Rs * Rf * NP;
     const uint4* __restrict__ ipk =
         (LDSA ? (const uint4*)apk : a.ipk + (size_t)tile * KB * (4 * 2 * 64)) + lane;
 
@@ -1106,6 +1292,8 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             // lies in the validated rectangle, so offsets are in [0, 4 Rs Rf))
             const unsigned roff4 = 4u * (unsigned)((T0 + r) * Rf + (T1 + cc));
             const unsigned rf4 = 4u * (unsigned)Rf;
+            // precomputed planes: the position relative to frame 0's integer shift
+            const int Pl = PLANES ? (T0 + r - pe00) * Rf + (T1 + cc - pe01) : 0;
             const char* __restrict__ refb = (const char*)a.refv;
             mm_v4i acc[MH][4];
 #pragma unroll
@@ -1119,95 +1307,104 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 __builtin_amdgcn_wave_barrier();
             }
             for (int kb = 0; kb < KB; ++kb) {
-                // B operand: 16 frames of this lane's position, three biased bytes each;
-                // branch-free so that the 32 loads of the 16 frames are in flight together
-                unsigned B0[4], B1[4], B2[4];
-                unsigned gsum = 0;
-                float2 top[16], bot[16];
-                const int nb = kb * MM_KB + 16 * g;
-                // edge tiles: a frame with invalid lookups in the region (slot sl > 0) reads
-                // the corners of its own lookup, clamped into the grid (out-of-grid corners
-                // are masked below), so that its loads join the batch
-                int slot[16], row[16], col[16];
+                mm_v4i b0, b1, b2;
+                if constexpr (PLANES) {
+                    // precomputed operand bytes of this lane's position and frames
+                    const uint8_t* pb = a.planes + (size_t)Pl * NP + kb * MM_KB + 16 * g;
+                    b0 = mm_as_v4i(*(const uint4*)pb);
+                    b1 = mm_as_v4i(*(const uint4*)(pb + pstride));
+                    b2 = mm_as_v4i(*(const uint4*)(pb + 2 * pstride));
+                } else {
+                    // B operand: 16 frames of this lane's position, three biased bytes each;
+                    // branch-free so that the 32 loads of the 16 frames are in flight together
+                    unsigned B0[4], B1[4], B2[4];
+                    unsigned gsum = 0;
+                    float2 top[16], bot[16];
+                    const int nb = kb * MM_KB + 16 * g;
+                    // edge tiles: a frame with invalid lookups in the region (slot sl > 0) reads
+                    // the corners of its own lookup, clamped into the grid (out-of-grid corners
+                    // are masked below), so that its loads join the batch
+                    int slot[16], row[16], col[16];
 #pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    unsigned e4 = roff4 - fgo4[nb + t];
-                    if (EDGE) {
-                        slot[t] = sflag[nb + t];
-                        const int4 si = sinfo[slot[t] > 0 ? slot[t] - 1 : 0];
-                        row[t] = T0 + r - si.x;
-                        col[t] = T1 + cc - si.y;
-                        const int rc = min(max(row[t], 0), a.Rs - 2), ccl = min(max(col[t], 0), Rf - 2);
-                        if (slot[t] > 0) e4 = 4u * (unsigned)(rc * Rf + ccl);
-                    }
-                    top[t] = *(const float2*)(refb + e4);
-                    bot[t] = *(const float2*)(refb + (e4 + rf4));
-                }
-                float vals[16];
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    const float4 wt = fw[nb + t];
-                    vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
-                    if (EDGE && slot[t] > 0) {
-                        // the masked lookup of the paper's interpolation (renormalised over
-                        // the valid corners), as masked_bilinear computes it
-                        const int4 si = sinfo[slot[t] - 1];
-                        const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
-                        const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
-                        const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
-                        // the clamped corners are the real ones whenever those are in the grid
-                        const float v00 = (r0 && c0) ? top[t].x : qnan();
-                        const float v01 = (r0 && c1) ? top[t].y : qnan();
-                        const float v10 = (r1 && c0) ? bot[t].x : qnan();
-                        const float v11 = (r1 && c1) ? bot[t].y : qnan();
-                        float gm;
-                        if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
-                            gm = bilinear4(v00, v01, v10, v11, fa, fb);
-                        } else {
-                            const float ga = 1.f - fa, gb = 1.f - fb;
-                            const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
-                            float num = 0.f, den = 0.f;
-                            if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
-                            if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
-                            if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
-                            if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
-                            gm = den > 0.f ? num / den : qnan();
+                    for (int t = 0; t < 16; ++t) {
+                        unsigned e4 = roff4 - fgo4[nb + t];
+                        if (EDGE) {
+                            slot[t] = sflag[nb + t];
+                            const int4 si = sinfo[slot[t] > 0 ? slot[t] - 1 : 0];
+                            row[t] = T0 + r - si.x;
+                            col[t] = T1 + cc - si.y;
+                            const int rc = min(max(row[t], 0), a.Rs - 2), ccl = min(max(col[t], 0), Rf - 2);
+                            if (slot[t] > 0) e4 = 4u * (unsigned)(rc * Rf + ccl);
                         }
-                        if (valid(gm)) {
-                            vals[t] = gm * fs;
-                        } else {
-                            vals[t] = 0.f;
-                            const int k = slot[t] - 1;
-                            atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                        top[t] = *(const float2*)(refb + e4);
+                        bot[t] = *(const float2*)(refb + (e4 + rf4));
+                    }
+                    float vals[16];
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) {
+                        const float4 wt = fw[nb + t];
+                        vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
+                        if (EDGE && slot[t] > 0) {
+                            // the masked lookup of the paper's interpolation (renormalised over
+                            // the valid corners), as masked_bilinear computes it
+                            const int4 si = sinfo[slot[t] - 1];
+                            const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
+                            const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
+                            const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
+                            // the clamped corners are the real ones whenever those are in the grid
+                            const float v00 = (r0 && c0) ? top[t].x : qnan();
+                            const float v01 = (r0 && c1) ? top[t].y : qnan();
+                            const float v10 = (r1 && c0) ? bot[t].x : qnan();
+                            const float v11 = (r1 && c1) ? bot[t].y : qnan();
+                            float gm;
+                            if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
+                                gm = bilinear4(v00, v01, v10, v11, fa, fb);
+                            } else {
+                                const float ga = 1.f - fa, gb = 1.f - fb;
+                                const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
+                                float num = 0.f, den = 0.f;
+                                if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
+                                if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
+                                if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
+                                if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
+                                gm = den > 0.f ? num / den : qnan();
+                            }
+                            if (valid(gm)) {
+                                vals[t] = gm * fs;
+                            } else {
+                                vals[t] = 0.f;
+                                const int k = slot[t] - 1;
+                                atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    unsigned u[4];
+                    for (int w = 0; w < 4; ++w) {
+                        unsigned u[4];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int t = 4 * w + b;
-                        const float v = vals[t];
-                        // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
-                        const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
-                        const int gt = (int)gu - (1 << 23);
-                        CS = fma((double)gt, (double)gt, CS);
-                        gsum += gu;
-                        u[b] = gu;
+                        for (int b = 0; b < 4; ++b) {
+                            const int t = 4 * w + b;
+                            const float v = vals[t];
+                            // rint(v) + 2^23 from the bits of v + 1.5 * 2^23 (|v| < 2^22)
+                            const unsigned gu = __float_as_uint(v + 12582912.f) - 0x4AC00000u;
+                            const int gt = (int)gu - (1 << 23);
+                            CS = fma((double)gt, (double)gt, CS);
+                            gsum += gu;
+                            u[b] = gu;
+                        }
+                        const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
+                        const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
+                        const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
+                        const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
+                        B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
+                        B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
+                        B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
                     }
-                    const unsigned t01l = __builtin_amdgcn_perm(u[1], u[0], 0x05010400u);
-                    const unsigned t01h = __builtin_amdgcn_perm(u[1], u[0], 0x07030602u);
-                    const unsigned t23l = __builtin_amdgcn_perm(u[3], u[2], 0x05010400u);
-                    const unsigned t23h = __builtin_amdgcn_perm(u[3], u[2], 0x07030602u);
-                    B0[w] = __builtin_amdgcn_perm(t23l, t01l, 0x05040100u) ^ 0x80808080u;
-                    B1[w] = __builtin_amdgcn_perm(t23l, t01l, 0x07060302u) ^ 0x80808080u;
-                    B2[w] = __builtin_amdgcn_perm(t23h, t01h, 0x05040100u) ^ 0x80808080u;
+                    GU += (double)gsum;
+                    b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
+                    b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
+                    b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
                 }
-                GU += (double)gsum;
-                const mm_v4i b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
-                const mm_v4i b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
-                const mm_v4i b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
                 const uint4* ak = ipk + (size_t)kb * (4 * 2 * 64);
 #pragma unroll
                 for (int m = 0; m < MH; ++m) {
@@ -1222,11 +1419,17 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     acc[m][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b2, acc[m][3], 0, 0, 0);
                 }
             }
-            // column sums of the position over the four lane groups (same sum in all four)
-            GU += __shfl_xor(GU, 16, 64);
-            GU += __shfl_xor(GU, 32, 64);
-            CS += __shfl_xor(CS, 16, 64);
-            CS += __shfl_xor(CS, 32, 64);
+            if constexpr (PLANES) {
+                // the position's column sums over all frames, precomputed
+                GU = a.pgu[Pl];
+                CS = a.pcs[Pl];
+            } else {
+                // column sums of the position over the four lane groups (same sum in all four)
+                GU += __shfl_xor(GU, 16, 64);
+                GU += __shfl_xor(GU, 32, 64);
+                CS += __shfl_xor(CS, 16, 64);
+                CS += __shfl_xor(CS, 32, 64);
+            }
             const double gq = 128.0 * 257.0 * GU - kconst;
             const int rN = r * NY + cc;
             // S = sum_s 256^s acc_s; with at most 3 K-blocks |acc_s| <= 2^21 KB, so the two
@@ -1418,6 +1621,14 @@ PXST_WRAP(k_pm_mma_glb, MM_THREADS, pm_mma_fast_glb)
 PXST_WRAP(k_pm_mma_edge_lds, MM_THREADS, pm_mma_edge_lds)
 PXST_WRAP(k_pm_mma_edge_glb, MM_THREADS, pm_mma_edge_glb)
 PXST_WRAP(k_pm_mma_half, MM_THREADS, pm_mma_fast_half)
+__device__ void pm_mma_planes_lds(const PmArgs& a, int slot) { pm_mma_item<true, false, 4, true>(a, slot); }
+__device__ void pm_mma_planes_glb(const PmArgs& a, int slot) { pm_mma_item<false, false, 4, true>(a, slot); }
+__global__ __launch_bounds__(MM_THREADS) void k_pm_mma_planes_lds(const PmArgs a) {
+    pm_mma_planes_lds(a, (int)blockIdx.x);
+}
+__global__ __launch_bounds__(MM_THREADS) void k_pm_mma_planes_glb(const PmArgs a) {
+    pm_mma_planes_glb(a, (int)blockIdx.x);
+}
 PXST_WRAP(k_pm_mma_edge_half, MM_THREADS, pm_mma_edge_half)
 
 template <int CW, int KR>
@@ -1608,9 +1819,11 @@ int launch_mma(const PmArgs* host_args, int nargs, const PmArgs* dev_jobs, const
         return PXST_EINVAL;
     }
     if (dev_jobs == nullptr) {
+        const bool planes = !edge && !half && host_args[0].planes != nullptr;
         const PmKernel kern = half ? (edge ? k_pm_mma_edge_half : k_pm_mma_half)
                               : edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
-                                     : (stage ? k_pm_mma_lds : k_pm_mma_glb);
+                              : planes ? (stage ? k_pm_mma_planes_lds : k_pm_mma_planes_glb)
+                                       : (stage ? k_pm_mma_lds : k_pm_mma_glb);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, host_args[0]);
     } else {
@@ -1668,9 +1881,30 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
     if (a.mm_on & 1) {
+        // interior tiles' operand planes, when they fit the workspace (whole tiles only)
+        PmArgs ap = a;
+        if (L.planes_on && !(a.mm_on & 16) && g.Rs >= 2 && g.Rf >= 2) {
+            uint8_t* planes = (uint8_t*)(ws + L.planes);
+            double* pcs = (double*)(ws + L.pcs);
+            double* pgu = (double*)(ws + L.pgu);
+            ap.planes = planes;
+            ap.pcs = pcs;
+            ap.pgu = pgu;
+            const size_t sh = (size_t)L.kblocks * MM_KB * (16 + 4 + 4 + 4);
+            int2* prow = (int2*)(ws + L.prow);
+            hipFuncSetAttribute((const void*)k_pm_planes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+            profile_begin("pm_planes", s);
+            hipLaunchKernelGGL(k_planes_span_clear, dim3((g.Rs + 255) / 256), dim3(256), 0, s, prow, g.Rs);
+            hipLaunchKernelGGL(k_planes_span, dim3(a.ntiles / a.tiles_x), dim3(256), 0, s, a, prow);
+            hipLaunchKernelGGL(k_pm_planes, dim3((g.Rf + PL_COLS - 1) / PL_COLS, g.Rs), dim3(PL_THREADS), sh, s, a,
+                               (const int2*)prow, planes, pcs, pgu);
+            profile_end("pm_planes", s, 0, nullptr, 0);
+            rc = check_hip(hipGetLastError(), "operand planes");
+            if (rc) return rc;
+        }
         profile_begin("pm_fast", s);
         profile_begin("pm_fast_int8_ops", s);
-        rc = launch_mma(&a, 1, nullptr, nullptr, a.ntiles, false, s);
+        rc = launch_mma(&ap, 1, nullptr, nullptr, a.ntiles, false, s);
         // int8 operations issued on the matrix cores: 2 per multiply-add, 64 pixels x
         // positions x padded frames x 6 byte pairs
         profile_end("pm_fast_int8_ops", s, 0, a.counters + CNT_MM_POS,
