@@ -182,6 +182,7 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
             L.pcs = take(RR * sizeof(double));
             L.pgu = take(RR * sizeof(double));
             L.prow = take((size_t)g.Rs * 2 * sizeof(int));
+            L.pvb = take(RR * (size_t)L.kblocks * 4 * sizeof(unsigned));
         }
     }
     L.rowmax = take((size_t)g.Rs * sizeof(float));

@@ -78,10 +78,11 @@ struct Layout {
     size_t ipk, pstat;        // frames packed as int8 matrix operands; per-pixel frame sums
     size_t rowmax, fscale;    // per-row max |reference| and the fixed-point exponent
     int kblocks;              // frame K-blocks of the packed frames
-    // interior tiles' B operand planes per reference position and their column sums
-    // (when planes_on: 3 Rs Rf NP bytes within PLANES_MAX)
+    // the search's B operand planes per reference position, their column sums, the
+    // row spans they cover and the lookups' validity bits (when planes_on: 3 Rs Rf NP
+    // bytes within PLANES_MAX)
     bool planes_on;
-    size_t planes, pcs, pgu, prow;
+    size_t planes, pcs, pgu, prow, pvb;
     // translations
     size_t tr_part;
     // error

@@ -56,12 +56,15 @@ struct PmArgs {
     int mm_on;          // bits: interior tiles / edge tiles on the matrix cores, frames
                         // staged in LDS for interior / edge tiles
     int mm_slow_max;    // slow-frame capacity of a matrix-core edge tile
-    // interior tiles' B operand precomputed per reference position (null: generated in
-    // the search kernel): three byte planes [3][Rs Rf][NP] of the positions relative to
-    // frame 0's integer shift, and per position the column sums sum g~^2 and sum G~
+    // B operand precomputed per reference position (null: generated in the search
+    // kernel): three byte planes [3][Rs Rf][NP] of the positions relative to the integer
+    // shift of frame pl_ref (the middle frame), per position the column sums sum g~^2
+    // and sum G~, and per (position, 16 frames) the lookups' validity bits
     const uint8_t* planes;
     const double* pcs;
     const double* pgu;
+    const unsigned* pvb;
+    int pl_ref;
 };
 
 
@@ -894,13 +897,17 @@ __host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_
 // the packed frames are staged in LDS, whether the tiles are searched in two halves of
 // 32 pixels (windows whose error tables of 64 pixels do not fit the LDS), and the edge
 // tiles' slow-frame capacity (the largest that fits the LDS, preferring staged frames).
-// Depends on the job's own window and frame count only.
+// Depends on the job's own window and frame count, and on whether the interior tiles
+// read precomputed operand planes: then a tile whose table of 64 pixels leaves room
+// for only one work-group per CU is searched in halves of 32 pixels with the packed
+// frames staged, so that two fit (each half's region is smaller than the tile's, so
+// the halves issue fewer products in all; they read their operand from L2 twice).
 constexpr size_t MM_LDS_MAX = 160 * 1024;
 struct MmPlan {
     bool fast, edge, fast_stage, edge_stage, fast_half, edge_half;
     int slow_max;
 };
-MmPlan mm_plan(int nx, int ny, int n_frames) {
+MmPlan mm_plan(int nx, int ny, int n_frames, bool planes) {
     MmPlan p{};
     const int nc = nx * ny;
     p.fast = mm_lds_bytes(nc, n_frames, false, false, 0, 4) <= MM_LDS_MAX;
@@ -908,6 +915,10 @@ MmPlan mm_plan(int nx, int ny, int n_frames) {
     if (!p.fast && mm_lds_bytes(nc, n_frames, false, false, 0, 2) <= MM_LDS_MAX) {
         p.fast = true;
         p.fast_half = true;
+    } else if (planes && p.fast && mm_lds_bytes(nc, n_frames, true, false, 0, 4) > MM_LDS_MAX / 2 &&
+               mm_lds_bytes(nc, n_frames, true, false, 0, 2) <= MM_LDS_MAX / 2) {
+        p.fast_half = true;
+        p.fast_stage = true;
     }
     // capacity: the largest multiple of 32 (keeps the LDS arrays 16-byte aligned) that fits
     auto cap = [&](bool stage, int mh) {
@@ -974,8 +985,62 @@ __device__ inline void mm_pack_b(const float (&vals)[16], unsigned (&B0)[4], uns
     }
 }
 
-// Column span [x, y] per plane row of the interior tiles' region positions (relative to
-// frame 0's integer shift); spans start empty (x > y).
+// Corners of the lookup at reference (row, col) from the 2x2 block read at that position
+// clamped into the grid (top-left corner (clamp(row, 0, Rs-2), clamp(col, 0, Rf-2))):
+// a corner outside the grid is NaN; one inside sits in the block at its own row and
+// column minus the block's (0 or 1 -- also where the clamp moved the block).
+__device__ inline void block_corners(int row, int col, float2 top, float2 bot, int Rs, int Rf, float& v00,
+                                     float& v01, float& v10, float& v11) {
+    const int rc = min(max(row, 0), Rs - 2), ccl = min(max(col, 0), Rf - 2);
+    // the block row holding the lookup's first row is 1 only where the clamp moved the
+    // block up (row = Rs - 1); its second row is 0 only where it moved it down (row = -1)
+    const float2 h0 = row > rc ? bot : top, h1 = row < rc ? top : bot;
+    const bool r0 = (unsigned)row < (unsigned)Rs, r1 = (unsigned)(row + 1) < (unsigned)Rs;
+    const bool c0 = (unsigned)col < (unsigned)Rf, c1 = (unsigned)(col + 1) < (unsigned)Rf;
+    const bool x0 = col > ccl, x1 = col < ccl;   // same for the columns
+    v00 = (r0 && c0) ? (x0 ? h0.y : h0.x) : qnan();
+    v01 = (r0 && c1) ? (x1 ? h0.x : h0.y) : qnan();
+    v10 = (r1 && c0) ? (x0 ? h1.y : h1.x) : qnan();
+    v11 = (r1 && c1) ? (x1 ? h1.x : h1.y) : qnan();
+}
+
+// Masked lookup of an edge tile's slow frame (shift si: integer parts, fraction bits)
+// at reference (row, col), from the block read at the clamped position: true when all
+// four corners are valid (the caller keeps its plain interpolation); otherwise gm is
+// Sec. 4's interpolation renormalised over the valid corners (the form masked_bilinear
+// computes), NaN when none is valid.
+__device__ inline bool slow_lookup(const int4 si, int row, int col, float2 top, float2 bot, int Rs, int Rf,
+                                   float& gm) {
+    float v00, v01, v10, v11;
+    block_corners(row, col, top, bot, Rs, Rf, v00, v01, v10, v11);
+    if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) return true;
+    const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
+    const float ga = 1.f - fa, gb = 1.f - fb;
+    const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
+    float num = 0.f, den = 0.f;
+    if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
+    if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
+    if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
+    if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
+    gm = den > 0.f ? num / den : qnan();
+    return false;
+}
+
+// Integer shift of the planes' origin frame.
+__device__ inline int2 planes_origin(const PmArgs& a) {
+    return make_int2(axis_shift(a.dx[2 * a.pl_ref], a.o0).e, axis_shift(a.dx[2 * a.pl_ref + 1], a.o1).e);
+}
+// The tile's region, relative to the planes' origin, lies in the reference grid (so the
+// planes have an entry for each of its positions).  Always true for interior tiles,
+// whose lookups are all valid.
+__device__ inline bool planes_cover(const PmArgs& a, const TileDesc& td, int2 eo) {
+    const int r0 = td.cmin0 - a.rx - eo.x, c0 = td.cmin1 - a.ry - eo.y;
+    return r0 >= 0 && c0 >= 0 && r0 + td.rh <= a.Rs && c0 + td.rw <= a.Rf;
+}
+
+// Column span [x, y] per plane row of the region positions (relative to the planes'
+// origin) of the tiles that read the planes: interior tiles, and edge tiles searched
+// whole whose region the planes cover; spans start empty (x > y).
 __global__ void k_planes_span_clear(int2* __restrict__ prow, int Rs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < Rs) prow[r] = make_int2(INT_MAX, INT_MIN);
@@ -986,13 +1051,16 @@ __global__ void k_planes_span_clear(int2* __restrict__ prow, int Rs) {
 __global__ __launch_bounds__(256) void k_planes_span(const PmArgs a, int2* __restrict__ prow) {
     __shared__ int red[4][4];
     const int ty = blockIdx.x;
-    const int e00 = axis_shift(a.dx[0], a.o0).e, e01 = axis_shift(a.dx[1], a.o1).e;
+    const int2 eo = planes_origin(a);
+    const bool edge_whole = (a.mm_on & 2) && !(a.mm_on & 32);
     int rlo = INT_MAX, rhi = INT_MIN, clo = INT_MAX, chi = INT_MIN;
     for (int tx = threadIdx.x; tx < a.tiles_x; tx += 256) {
         const int tile = ty * a.tiles_x + tx;
-        if (a.tinfo[tile].x != CNT_FAST) continue;
+        const int cls = a.tinfo[tile].x;
+        if (cls != CNT_FAST && !(cls == CNT_EDGE_MM && edge_whole)) continue;
         const TileDesc td = a.tiles[tile];
-        const int r0 = td.cmin0 - a.rx - e00, c0 = td.cmin1 - a.ry - e01;
+        if (cls == CNT_EDGE_MM && !planes_cover(a, td, eo)) continue;
+        const int r0 = td.cmin0 - a.rx - eo.x, c0 = td.cmin1 - a.ry - eo.y;
         rlo = min(rlo, r0);
         rhi = max(rhi, r0 + td.rh - 1);
         clo = min(clo, c0);
@@ -1023,9 +1091,10 @@ __global__ __launch_bounds__(256) void k_planes_span(const PmArgs a, int2* __res
     }
 }
 
-// B operand of the interior tiles, precomputed once per search for every reference
-// position P (coordinates relative to frame 0's integer shift: the interior tiles'
-// positions X all have X - e_0 in the grid, since every lookup of theirs is valid),
+// B operand of the tiles, precomputed once per search for every reference position P
+// (coordinates relative to the integer shift e_c of the planes' origin frame c: the
+// interior tiles' positions X all have X - e_c in the grid, since every lookup of theirs
+// is valid; edge tiles use the planes where they cover them),
 // over each plane row's span of interior-tile positions (prow, from k_planes_span):
 // the same bytes the search kernel would generate, in planes [3][Rs Rf][NP] whose 16
 // bytes at (P, 64 kb + 16 g) are lane (c, g)'s operand; and per position the sums
@@ -1036,32 +1105,32 @@ constexpr int PL_THREADS = 256;
 constexpr int PL_COLS = 256;   // columns of a plane row per work-group
 __global__ __launch_bounds__(PL_THREADS) void k_pm_planes(const PmArgs a, const int2* __restrict__ prow,
                                                           uint8_t* __restrict__ planes, double* __restrict__ pcs,
-                                                          double* __restrict__ pgu) {
+                                                          double* __restrict__ pgu, unsigned* __restrict__ pvb) {
     extern __shared__ float4 plsm[];
     const int NP = a.kblocks * MM_KB, KB = a.kblocks, Rf = a.Rf, Rs = a.Rs;
-    // per frame: weights, the byte offset of the lookup relative to the position's
-    // (4 ((e0 - e_n) . (Rf, 1)), modulo 2^32), the first valid column and whether this
-    // block's row is valid
+    // per frame: weights, the byte offset of this block's lookup row clamped into the
+    // grid, the column offset of the lookup (e_c1 - e_n1) and the row of the lookup
     float4* fw = plsm;
-    unsigned* dgo = (unsigned*)(fw + NP);
-    int* clo = (int*)(dgo + NP);
-    int* rok = clo + NP;
+    unsigned* rbase = (unsigned*)(fw + NP);
+    int* dcol = (int*)(rbase + NP);
+    int* lrow = dcol + NP;
     const int pr = blockIdx.y;
     const int2 span = prow[pr];
     const int cb = blockIdx.x * PL_COLS;
     if (span.x > span.y || cb + PL_COLS <= span.x || cb > span.y) return;
     const float fs = ldexpf(1.f, *a.fscale);
-    const int e00 = axis_shift(a.dx[0], a.o0).e, e01 = axis_shift(a.dx[1], a.o1).e;
+    const int2 eo = planes_origin(a);
+    const int e00 = eo.x, e01 = eo.y;
     for (int n = threadIdx.x; n < NP; n += PL_THREADS) {
         const bool zero = n >= a.N;
         const int nn = zero ? 0 : n;
         unsigned go4;
         mm_frame_entry(a, nn, zero, fs, fw[n], go4);
         const int ex = axis_shift(a.dx[2 * nn], a.o0).e, ey = axis_shift(a.dx[2 * nn + 1], a.o1).e;
-        dgo[n] = 4u * (unsigned)((e00 - ex) * Rf + (e01 - ey));
-        clo[n] = ey - e01;
         const int rr = pr + e00 - ex;
-        rok[n] = rr >= 0 && rr + 1 < Rs;
+        rbase[n] = 4u * (unsigned)(min(max(rr, 0), Rs - 2) * Rf);
+        dcol[n] = e01 - ey;
+        lrow[n] = rr;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, g = lane >> 4;
@@ -1074,27 +1143,42 @@ __global__ __launch_bounds__(PL_THREADS) void k_pm_planes(const PmArgs a, const 
         const bool pv = pcol >= span.x && pcol <= span.y && pcol < Rf;
         const int pc = min(max(pcol, 0), Rf - 1);
         const size_t P = (size_t)pr * Rf + pc;
-        const unsigned pos4 = 4u * (unsigned)P;
         long long cs = 0;
         unsigned long long gs = 0;
         for (int kb = 0; kb < KB; ++kb) {
             const int nb = kb * MM_KB + 16 * g;
             float vals[16];
             float2 top[16], bot[16];
-            bool in[16];
+            int col[16];
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
-                in[t] = rok[nb + t] && (unsigned)(pc - clo[nb + t]) <= (unsigned)(Rf - 2);
-                const unsigned e4 = in[t] ? pos4 + dgo[nb + t] : 0u;
+                // the 2x2 block at the lookup, clamped into the grid
+                col[t] = pc + dcol[nb + t];
+                const unsigned e4 = rbase[nb + t] + 4u * (unsigned)min(max(col[t], 0), Rf - 2);
                 top[t] = *(const float2*)(refb + e4);
                 bot[t] = *(const float2*)(refb + (e4 + rf4));
             }
             double part = 0.0;
+            // per frame: all four corners valid (bits 0-15; the value is the plain
+            // interpolation) and at least one valid (bits 16-31); padding frames count as valid
+            unsigned vbits = 0;
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 const float4 wt = fw[nb + t];
                 const float v = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
-                vals[t] = in[t] && v == v ? v : 0.f;
+                const int rr = lrow[nb + t];
+                const bool in = (unsigned)rr <= (unsigned)(Rs - 2) && (unsigned)col[t] <= (unsigned)(Rf - 2);
+                const bool all = in && v == v;
+                vals[t] = all ? v : 0.f;
+                bool any = all;
+                if (!all) {
+                    float v00, v01, v10, v11;
+                    block_corners(rr, col[t], top[t], bot[t], Rs, Rf, v00, v01, v10, v11);
+                    any = valid(v00) || valid(v01) || valid(v10) || valid(v11);
+                }
+                const bool pad = nb + t >= a.N;
+                vbits |= ((all || pad) ? 1u : 0u) << t;
+                vbits |= ((any || pad) ? 1u : 0u) << (16 + t);
             }
             unsigned B0[4], B1[4], B2[4];
             unsigned gsum = 0;
@@ -1107,6 +1191,7 @@ __global__ __launch_bounds__(PL_THREADS) void k_pm_planes(const PmArgs a, const 
                 *(uint4*)(planes + off) = make_uint4(B0[0], B0[1], B0[2], B0[3]);
                 *(uint4*)(planes + stride + off) = make_uint4(B1[0], B1[1], B1[2], B1[3]);
                 *(uint4*)(planes + 2 * stride + off) = make_uint4(B2[0], B2[1], B2[2], B2[3]);
+                pvb[P * (NP / 16) + kb * 4 + g] = vbits;
             }
         }
         cs += __shfl_xor(cs, 16, 64);
@@ -1127,6 +1212,14 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     if (slot >= a.counters[cnt]) return;
     const int tile = a.lists[(EDGE ? LIST_EDGE_MM : CNT_FAST) * a.ntiles + slot];
     const TileDesc td = a.tiles[tile];
+    if constexpr (EDGE && MH == 4) {
+        // with operand planes, the edge tiles searched whole whose region they cover go
+        // to the planes kernel and the others to the kernel that generates its operand
+        // (edge tiles searched in halves always generate it)
+        if (PLANES ? !planes_cover(a, td, planes_origin(a))
+                   : (a.planes != nullptr && planes_cover(a, td, planes_origin(a))))
+            return;
+    }
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const int RW = td.rw, Q = td.rh * td.rw, NT = (Q + 15) >> 4;
     const int T0 = td.cmin0 - a.rx, T1 = td.cmin1 - a.ry;
@@ -1191,11 +1284,12 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
     }
 
     // frame table: bilinear weights scaled by 2^F (exact: a power of two) and the
-    // reference offset of the frame's shift; padding frames and (edge tiles) frames
-    // with invalid lookups get zero weights and the offset of a frame without any
+    // reference offset of the frame's shift; padding frames get zero weights and the
+    // offset of a real frame (an edge tile's slow frames read their corners at their own
+    // clamped positions, and keep the plain interpolation where all four are valid)
     const float fs = ldexpf(1.f, *a.fscale);
     for (int n = tid; n < NP; n += MM_THREADS) {
-        const bool zero = n >= N || (EDGE && sflag[n]);
+        const bool zero = n >= N;
         mm_frame_entry(a, zero ? nref : n, zero, fs, fw[n], fgo4[n]);
     }
     if (EDGE) {
@@ -1255,7 +1349,8 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 
     const double kconst = 16384.0 * 257.0 * 65793.0 * (double)(KB * MM_KB);
     const int c = lane & 15, g = lane >> 4;
-    const int pe00 = PLANES ? axis_shift(a.dx[0], a.o0).e : 0, pe01 = PLANES ? axis_shift(a.dx[1], a.o1).e : 0;
+    const int2 peo = PLANES ? planes_origin(a) : make_int2(0, 0);
+    const int pe00 = peo.x, pe01 = peo.y;
     const size_t pstride = (size_t)a.Rs * Rf * NP;
     const uint4* __restrict__ ipk =
         (LDSA ? (const uint4*)apk : a.ipk + (size_t)tile * KB * (4 * 2 * 64)) + lane;
@@ -1308,12 +1403,81 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
             }
             for (int kb = 0; kb < KB; ++kb) {
                 mm_v4i b0, b1, b2;
-                if constexpr (PLANES) {
+                if constexpr (PLANES && !EDGE) {
                     // precomputed operand bytes of this lane's position and frames
                     const uint8_t* pb = a.planes + (size_t)Pl * NP + kb * MM_KB + 16 * g;
                     b0 = mm_as_v4i(*(const uint4*)pb);
                     b1 = mm_as_v4i(*(const uint4*)(pb + pstride));
                     b2 = mm_as_v4i(*(const uint4*)(pb + 2 * pstride));
+                } else if constexpr (EDGE && PLANES) {
+                    // edge tile covered by the planes: the planes hold the plain
+                    // interpolation where all four corners are valid (every frame without
+                    // invalid lookups in the region, and most positions of the others) and 0
+                    // where none is; only a lookup with some corners valid, a slow frame near
+                    // the edge of the valid reference, takes the renormalised form here, its
+                    // bytes replaced and the column sums corrected by the difference (exact
+                    // integers).  Invalid lookups are recorded for the epilogue.
+                    const uint8_t* pb = a.planes + (size_t)Pl * NP + kb * MM_KB + 16 * g;
+                    const uint4 q0 = *(const uint4*)pb;
+                    const uint4 q1 = *(const uint4*)(pb + pstride);
+                    const uint4 q2 = *(const uint4*)(pb + 2 * pstride);
+                    const unsigned vb = a.pvb[(size_t)Pl * (NP / 16) + kb * 4 + g];
+                    unsigned B0[4] = {q0.x, q0.y, q0.z, q0.w};
+                    unsigned B1[4] = {q1.x, q1.y, q1.z, q1.w};
+                    unsigned B2[4] = {q2.x, q2.y, q2.z, q2.w};
+                    const int nb = kb * MM_KB + 16 * g;
+                    unsigned none = ~(vb >> 16) & 0xffffu;
+                    unsigned some = (vb >> 16) & ~vb & 0xffffu;
+                    while (none) {
+                        const int t = __ffs(none) - 1;
+                        none &= none - 1u;
+                        const int k = sflag[nb + t] - 1;
+                        if (k >= 0) atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                    }
+                    while (some) {
+                        const int t = __ffs(some) - 1;
+                        some &= some - 1u;
+                        const int k = sflag[nb + t] - 1;
+                        if (k < 0) continue;
+                        const int4 si = sinfo[k];
+                        const int row = T0 + r - si.x, col = T1 + cc - si.y;
+                        const int rc = min(max(row, 0), a.Rs - 2), ccl = min(max(col, 0), Rf - 2);
+                        const unsigned e4 = 4u * (unsigned)(rc * Rf + ccl);
+                        const float2 top = *(const float2*)(refb + e4);
+                        const float2 bot = *(const float2*)(refb + (e4 + rf4));
+                        float gm = 0.f;
+                        slow_lookup(si, row, col, top, bot, a.Rs, Rf, gm);
+                        if (!valid(gm)) {
+                            // (the planes hold 0 here, the value of an invalid lookup)
+                            atomicOr(&imask[c * MW + (k >> 5)], 1u << (k & 31));
+                            continue;
+                        }
+                        const unsigned gn = __float_as_uint(gm * fs + 12582912.f) - 0x4AC00000u;
+                        const int w = t >> 2, sh = 8 * (t & 3);
+                        const unsigned w0 = w == 0 ? B0[0] : w == 1 ? B0[1] : w == 2 ? B0[2] : B0[3];
+                        const unsigned w1 = w == 0 ? B1[0] : w == 1 ? B1[1] : w == 2 ? B1[2] : B1[3];
+                        const unsigned w2 = w == 0 ? B2[0] : w == 1 ? B2[1] : w == 2 ? B2[2] : B2[3];
+                        const unsigned gold =
+                            (((w0 >> sh) & 0xffu) | (((w1 >> sh) & 0xffu) << 8) | (((w2 >> sh) & 0xffu) << 16)) ^
+                            0x808080u;
+                        const double dn = (double)((int)gn - (1 << 23)), dold = (double)((int)gold - (1 << 23));
+                        CS = fma(dn, dn, CS);
+                        CS = fma(-dold, dold, CS);
+                        GU += (double)gn - (double)gold;
+                        const unsigned keep = ~(0xffu << sh);
+                        const unsigned n0 = (w0 & keep) | (((gn ^ 0x80u) & 0xffu) << sh);
+                        const unsigned n1 = (w1 & keep) | ((((gn >> 8) ^ 0x80u) & 0xffu) << sh);
+                        const unsigned n2 = (w2 & keep) | ((((gn >> 16) ^ 0x80u) & 0xffu) << sh);
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) {
+                            B0[x] = x == w ? n0 : B0[x];
+                            B1[x] = x == w ? n1 : B1[x];
+                            B2[x] = x == w ? n2 : B2[x];
+                        }
+                    }
+                    b0 = mm_v4i{(int)B0[0], (int)B0[1], (int)B0[2], (int)B0[3]};
+                    b1 = mm_v4i{(int)B1[0], (int)B1[1], (int)B1[2], (int)B1[3]};
+                    b2 = mm_v4i{(int)B2[0], (int)B2[1], (int)B2[2], (int)B2[3]};
                 } else {
                     // B operand: 16 frames of this lane's position, three biased bytes each;
                     // branch-free so that the 32 loads of the 16 frames are in flight together
@@ -1344,31 +1508,9 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     for (int t = 0; t < 16; ++t) {
                         const float4 wt = fw[nb + t];
                         vals[t] = fmaf(wt.w, bot[t].y, fmaf(wt.z, bot[t].x, fmaf(wt.y, top[t].y, wt.x * top[t].x)));
-                        if (EDGE && slot[t] > 0) {
-                            // the masked lookup of the paper's interpolation (renormalised over
-                            // the valid corners), as masked_bilinear computes it
-                            const int4 si = sinfo[slot[t] - 1];
-                            const float fa = __int_as_float(si.z), fb = __int_as_float(si.w);
-                            const bool r0 = row[t] >= 0 && row[t] < a.Rs, r1 = row[t] + 1 >= 0 && row[t] + 1 < a.Rs;
-                            const bool c0 = col[t] >= 0 && col[t] < Rf, c1 = col[t] + 1 >= 0 && col[t] + 1 < Rf;
-                            // the clamped corners are the real ones whenever those are in the grid
-                            const float v00 = (r0 && c0) ? top[t].x : qnan();
-                            const float v01 = (r0 && c1) ? top[t].y : qnan();
-                            const float v10 = (r1 && c0) ? bot[t].x : qnan();
-                            const float v11 = (r1 && c1) ? bot[t].y : qnan();
-                            float gm;
-                            if (valid(v00) && valid(v01) && valid(v10) && valid(v11)) {
-                                gm = bilinear4(v00, v01, v10, v11, fa, fb);
-                            } else {
-                                const float ga = 1.f - fa, gb = 1.f - fb;
-                                const float w00 = ga * gb, w01 = ga * fb, w10 = fa * gb, w11 = fa * fb;
-                                float num = 0.f, den = 0.f;
-                                if (valid(v00)) { num = fmaf(w00, v00, num); den += w00; }
-                                if (valid(v01)) { num = fmaf(w01, v01, num); den += w01; }
-                                if (valid(v10)) { num = fmaf(w10, v10, num); den += w10; }
-                                if (valid(v11)) { num = fmaf(w11, v11, num); den += w11; }
-                                gm = den > 0.f ? num / den : qnan();
-                            }
+                        float gm;
+                        if (EDGE && slot[t] > 0 &&
+                            !slow_lookup(sinfo[slot[t] - 1], row[t], col[t], top[t], bot[t], a.Rs, Rf, gm)) {
                             if (valid(gm)) {
                                 vals[t] = gm * fs;
                             } else {
@@ -1419,7 +1561,7 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                     acc[m][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b2, acc[m][3], 0, 0, 0);
                 }
             }
-            if constexpr (PLANES) {
+            if constexpr (PLANES && !EDGE) {
                 // the position's column sums over all frames, precomputed
                 GU = a.pgu[Pl];
                 CS = a.pcs[Pl];
@@ -1429,6 +1571,11 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                 GU += __shfl_xor(GU, 32, 64);
                 CS += __shfl_xor(CS, 16, 64);
                 CS += __shfl_xor(CS, 32, 64);
+                if constexpr (EDGE && PLANES) {
+                    // (the lanes' sums are the slow frames' corrections)
+                    GU += a.pgu[Pl];
+                    CS += a.pcs[Pl];
+                }
             }
             const double gq = 128.0 * 257.0 * GU - kconst;
             const int rN = r * NY + cc;
@@ -1608,6 +1755,24 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
         }                                                                                     \
     }
 
+// Work item of block b out of n items.  Work-groups go to the eight XCDs in turn
+// (block b to XCD b mod 8) and each XCD has its own L2, so consecutive items of the
+// work list -- neighbouring tiles, whose regions overlap -- would each be read into a
+// different L2.  Instead each XCD takes one contiguous run of the list: XCD x holds
+// the items [x q + min(x, r), ...) with q = n / 8, r = n mod 8 (a bijection of [0, n)).
+__device__ inline int xcd_item(int b, int n) {
+    if (b >= n) return b;
+    const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + i;
+}
+
+// single-job launch of a matrix-core search over the list counted by CNT, items in
+// contiguous runs per XCD
+#define PXST_WRAP_XCD(NAME, BODY, CNT)                                                        \
+    __global__ __launch_bounds__(MM_THREADS) void NAME(const PmArgs a) {                      \
+        BODY(a, xcd_item((int)blockIdx.x, a.counters[CNT]));                                 \
+    }
+
 PXST_WRAP(k_classify, 64, classify_item)
 PXST_WRAP(k_pm_generic, 256, pm_generic_item)
 __device__ void pm_mma_fast_lds(const PmArgs& a, int slot) { pm_mma_item<true, false, 4>(a, slot); }
@@ -1623,12 +1788,16 @@ PXST_WRAP(k_pm_mma_edge_glb, MM_THREADS, pm_mma_edge_glb)
 PXST_WRAP(k_pm_mma_half, MM_THREADS, pm_mma_fast_half)
 __device__ void pm_mma_planes_lds(const PmArgs& a, int slot) { pm_mma_item<true, false, 4, true>(a, slot); }
 __device__ void pm_mma_planes_glb(const PmArgs& a, int slot) { pm_mma_item<false, false, 4, true>(a, slot); }
-__global__ __launch_bounds__(MM_THREADS) void k_pm_mma_planes_lds(const PmArgs a) {
-    pm_mma_planes_lds(a, (int)blockIdx.x);
-}
-__global__ __launch_bounds__(MM_THREADS) void k_pm_mma_planes_glb(const PmArgs a) {
-    pm_mma_planes_glb(a, (int)blockIdx.x);
-}
+__device__ void pm_mma_half_planes_lds(const PmArgs& a, int slot) { pm_mma_item<true, false, 2, true>(a, slot); }
+__device__ void pm_mma_half_planes_glb(const PmArgs& a, int slot) { pm_mma_item<false, false, 2, true>(a, slot); }
+PXST_WRAP_XCD(k_pm_mma_planes_lds, pm_mma_planes_lds, CNT_FAST)
+PXST_WRAP_XCD(k_pm_mma_planes_glb, pm_mma_planes_glb, CNT_FAST)
+PXST_WRAP_XCD(k_pm_mma_half_planes_lds, pm_mma_half_planes_lds, CNT_FAST)
+PXST_WRAP_XCD(k_pm_mma_half_planes_glb, pm_mma_half_planes_glb, CNT_FAST)
+__device__ void pm_mma_edge_planes_lds(const PmArgs& a, int slot) { pm_mma_item<true, true, 4, true>(a, slot); }
+__device__ void pm_mma_edge_planes_glb(const PmArgs& a, int slot) { pm_mma_item<false, true, 4, true>(a, slot); }
+PXST_WRAP_XCD(k_pm_mma_edge_planes_lds, pm_mma_edge_planes_lds, CNT_EDGE_MM)
+PXST_WRAP_XCD(k_pm_mma_edge_planes_glb, pm_mma_edge_planes_glb, CNT_EDGE_MM)
 PXST_WRAP(k_pm_mma_edge_half, MM_THREADS, pm_mma_edge_half)
 
 template <int CW, int KR>
@@ -1745,7 +1914,7 @@ size_t lds_bytes(const Launch& l, int n_frames) {
 
 PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
                     const float* dx, const float* u_in, const pxst_window& win, float* u_out,
-                    float* err_min, int32_t* argmin, char* ws, const Layout& L) {
+                    float* err_min, int32_t* argmin, char* ws, const Layout& L, bool planes) {
     PmArgs a{};
     a.frames = sc.frames;
     a.white = sc.white;
@@ -1785,7 +1954,8 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
     a.pstat = (const double*)(ws + L.pstat);
     a.fscale = (const int*)(ws + L.fscale);
     a.kblocks = L.kblocks;
-    const MmPlan mp = mm_plan(a.NX, a.NY, g.N);
+    a.pl_ref = g.N / 2;
+    const MmPlan mp = mm_plan(a.NX, a.NY, g.N, planes);
     a.mm_on = (mp.fast ? 1 : 0) | (mp.edge ? 2 : 0) | (mp.fast_stage ? 4 : 0) | (mp.edge_stage ? 8 : 0) |
               (mp.fast_half ? 16 : 0) | (mp.edge_half ? 32 : 0);
     a.mm_slow_max = mp.slow_max;
@@ -1801,7 +1971,8 @@ PmArgs make_pm_args(const Geom& g, const pxst_scan& sc, const float* refv, const
 int launch_mma(const PmArgs* host_args, int nargs, const PmArgs* dev_jobs, const int* off, int grid,
                bool edge, hipStream_t s) {
     const bool half = (host_args[0].mm_on & (edge ? 32 : 16)) != 0;
-    bool stage = !half;
+    // (the plan stages the frames of interior-tile halves only where they fit)
+    bool stage = !(half && edge);
     for (int j = 0; j < nargs; ++j) {
         stage = stage && (host_args[j].mm_on & (edge ? 8 : 4)) != 0;
         if (((host_args[j].mm_on & (edge ? 32 : 16)) != 0) != half) {
@@ -1819,13 +1990,22 @@ int launch_mma(const PmArgs* host_args, int nargs, const PmArgs* dev_jobs, const
         return PXST_EINVAL;
     }
     if (dev_jobs == nullptr) {
-        const bool planes = !edge && !half && host_args[0].planes != nullptr;
-        const PmKernel kern = half ? (edge ? k_pm_mma_edge_half : k_pm_mma_half)
-                              : edge ? (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb)
+        const bool planes = host_args[0].planes != nullptr;
+        const PmKernel kern = half ? (edge ? k_pm_mma_edge_half
+                                      : planes ? (stage ? k_pm_mma_half_planes_lds : k_pm_mma_half_planes_glb)
+                                               : k_pm_mma_half)
+                              : edge ? (planes ? (stage ? k_pm_mma_edge_planes_lds : k_pm_mma_edge_planes_glb)
+                                               : (stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb))
                               : planes ? (stage ? k_pm_mma_planes_lds : k_pm_mma_planes_glb)
                                        : (stage ? k_pm_mma_lds : k_pm_mma_glb);
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(MM_THREADS), sh, s, host_args[0]);
+        if (edge && !half && planes) {
+            // the edge tiles the planes do not cover
+            const PmKernel rest = stage ? k_pm_mma_edge_lds : k_pm_mma_edge_glb;
+            hipFuncSetAttribute((const void*)rest, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+            hipLaunchKernelGGL(rest, dim3(grid), dim3(MM_THREADS), sh, s, host_args[0]);
+        }
     } else {
         const PmBatchKernel kern = half ? (edge ? k_pm_mma_edge_half_batch : k_pm_mma_half_batch)
                                    : edge ? (stage ? k_pm_mma_edge_lds_batch : k_pm_mma_edge_glb_batch)
@@ -1872,7 +2052,9 @@ PmPlan pm_plan(int NX, int NY) {
 int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
                      const float* dx, const float* u_in, const pxst_window& win, float* u_out,
                      float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
-    const PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L);
+    // interior tiles read precomputed operand planes when the workspace holds them
+    const bool use_planes = L.planes_on && g.Rs >= 2 && g.Rf >= 2;
+    const PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L, use_planes);
     const PmPlan pl = pm_plan(a.NX, a.NY);
     hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(COMPACT_THREADS), 0, s, a);
@@ -1880,16 +2062,19 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     if (rc) return rc;
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
+    // with the operand planes (interior tiles, and edge tiles searched whole)
+    PmArgs ap = a;
     if (a.mm_on & 1) {
-        // interior tiles' operand planes, when they fit the workspace (whole tiles only)
-        PmArgs ap = a;
-        if (L.planes_on && !(a.mm_on & 16) && g.Rs >= 2 && g.Rf >= 2) {
+        // the operand planes, when they fit the workspace
+        if (use_planes) {
             uint8_t* planes = (uint8_t*)(ws + L.planes);
             double* pcs = (double*)(ws + L.pcs);
             double* pgu = (double*)(ws + L.pgu);
+            unsigned* pvb = (unsigned*)(ws + L.pvb);
             ap.planes = planes;
             ap.pcs = pcs;
             ap.pgu = pgu;
+            ap.pvb = pvb;
             const size_t sh = (size_t)L.kblocks * MM_KB * (16 + 4 + 4 + 4);
             int2* prow = (int2*)(ws + L.prow);
             hipFuncSetAttribute((const void*)k_pm_planes, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -1897,7 +2082,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
             hipLaunchKernelGGL(k_planes_span_clear, dim3((g.Rs + 255) / 256), dim3(256), 0, s, prow, g.Rs);
             hipLaunchKernelGGL(k_planes_span, dim3(a.ntiles / a.tiles_x), dim3(256), 0, s, a, prow);
             hipLaunchKernelGGL(k_pm_planes, dim3((g.Rf + PL_COLS - 1) / PL_COLS, g.Rs), dim3(PL_THREADS), sh, s, a,
-                               (const int2*)prow, planes, pcs, pgu);
+                               (const int2*)prow, planes, pcs, pgu, pvb);
             profile_end("pm_planes", s, 0, nullptr, 0);
             rc = check_hip(hipGetLastError(), "operand planes");
             if (rc) return rc;
@@ -1922,7 +2107,7 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     }
     if (a.mm_on & 2) {
         profile_begin("pm_edge_mma", s);
-        rc = launch_mma(&a, 1, nullptr, nullptr, a.ntiles, true, s);
+        rc = launch_mma(&ap, 1, nullptr, nullptr, a.ntiles, true, s);
         profile_end("pm_edge_mma", s, 0, a.counters + CNT_GOOD_EDGE_MM, evals_per_good_px);
         if (rc) return rc;
     }
@@ -1963,7 +2148,7 @@ int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStre
     for (int j = 0; j < n; ++j) {
         const PmJobDesc& d = jobs[j];
         base[j] = make_pm_args(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
-                               nullptr, d.ws, *d.L);
+                               nullptr, d.ws, *d.L, false);
     }
     // classification of all jobs in one launch
     {

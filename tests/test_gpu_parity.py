@@ -7,6 +7,8 @@ from the generator or the oracle, never from the GPU path.
 """
 import sys
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -228,6 +230,29 @@ def test_pixel_map_large_window_tile_halves(r, n_frames, mask):
         pxst.profile_enable(False)
     # both matrix-core launches ran, and interior tiles were searched on them
     assert n_fast == 1 and ops > 0 and n_edge == 1
+
+
+def test_pixel_map_reference_valid_to_its_edge():
+    """A reference grid cropped inside its valid area (every pixel of its first and last
+    rows and columns valid), so that lookups reach row -1 and the last row and column
+    and beyond: an edge tile's slow frame takes each corner inside the grid from its own
+    row and column, also where the 2x2 block read was moved into the grid, and counts
+    the corners outside as invalid, as the oracle's masked interpolation does (Sec. 4)."""
+    s = make_scan(CONFIGS["tiny"])
+    ref, w = oracle_state(s)
+    rows = np.nonzero((w > 0).any(axis=1))[0]
+    cols = np.nonzero((w > 0).any(axis=0))[0]
+    r0, r1, c0, c1 = rows[0] + 6, rows[-1] - 6, cols[0] + 6, cols[-1] - 6
+    ref_c = np.ascontiguousarray(ref[r0:r1 + 1, c0:c1 + 1])
+    w_c = np.ascontiguousarray(w[r0:r1 + 1, c0:c1 + 1])
+    for edge in (w_c[0], w_c[-1], w_c[:, 0], w_c[:, -1]):
+        assert np.all(edge > 0)
+    s2 = dataclasses.replace(s, origin=(s.origin[0] + int(r0), s.origin[1] + int(c0)), ref_shape=ref_c.shape)
+    # lookups at the first and last rows of the grid exist
+    p0 = np.floor(s.u0[0][None] - s.dx0[:, 0, None, None] - s2.origin[0]).astype(int)
+    assert (p0 + s.window[0] >= ref_c.shape[0] - 1).any() and (p0 - s.window[0] <= -1).any()
+    for refine in (False, True):
+        check_pixel_map(s2, ref_c, w_c, s.dx0, s.u0, s.window, refine, label=f"reference cropped, refine={refine}")
 
 
 def test_pixel_map_in_place_and_all_masked():
