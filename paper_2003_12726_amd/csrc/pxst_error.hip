@@ -89,7 +89,11 @@ __device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
 
 // One thread per pixel; frames in groups of ERR_FB whose loads are all issued before
 // the group is evaluated.  Per-frame sums of the wave go to LDS, then one partial per
-// block and frame to the workspace.
+// block and frame to the workspace.  PAIRS (a grid of at least 2x2): the four corners
+// come from two 8-byte loads of the 2x2 block at the lookup clamped into the grid, each
+// corner inside the grid at its own row and column of the block; otherwise four loads
+// at the corners clamped one by one.
+template <bool PAIRS>
 __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
     extern __shared__ double wsum_sh[];   // [N][waves]
     constexpr int WAVES = ERR_THREADS / 64;
@@ -101,6 +105,7 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
     const bool use = inb && a.mask[pc] != 0 && a.s2[pc] > 0.f;
     const float Wp = a.white[pc];
     const float s2 = a.s2[pc];
+    const float inv_s2 = use ? 1.f / s2 : 0.f;
     const float u0 = a.u[pc], u1 = a.u[HW + pc];
     const float f0 = floorf(u0), f1 = floorf(u1);
     const float fu0 = u0 - f0, fu1 = u1 - f1;
@@ -122,12 +127,29 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
             // corner flags: bit 0 row r, bit 1 row r + 1, bit 2 column c, bit 3 column c + 1
             ok[t] = ((unsigned)r < (unsigned)a.Rs ? 1u : 0u) | ((unsigned)(r + 1) < (unsigned)a.Rs ? 2u : 0u) |
                     ((unsigned)c < (unsigned)a.Rf ? 4u : 0u) | ((unsigned)(c + 1) < (unsigned)a.Rf ? 8u : 0u);
-            const int ra = min(max(r, 0), a.Rs - 1), rb = min(max(r + 1, 0), a.Rs - 1);
-            const int ca = min(max(c, 0), a.Rf - 1), cb = min(max(c + 1, 0), a.Rf - 1);
-            v[t][0] = a.refv[(size_t)ra * a.Rf + ca];
-            v[t][1] = a.refv[(size_t)ra * a.Rf + cb];
-            v[t][2] = a.refv[(size_t)rb * a.Rf + ca];
-            v[t][3] = a.refv[(size_t)rb * a.Rf + cb];
+            if constexpr (PAIRS) {
+                const int rc = min(max(r, 0), a.Rs - 2), ccl = min(max(c, 0), a.Rf - 2);
+                const float* bp = a.refv + ((unsigned)rc * (unsigned)a.Rf + (unsigned)ccl);
+                const float2 top = *(const float2*)bp;
+                const float2 bot = *(const float2*)(bp + a.Rf);
+                // the block row of the lookup's first row is 1 only where the clamp moved
+                // the block up (r = Rs - 1), that of its second row 0 only where it moved
+                // it down (r = -1); the same for the columns (corners outside the grid
+                // are masked by the flags)
+                const float2 h0 = r > rc ? bot : top, h1 = r < rc ? top : bot;
+                const bool x0 = c > ccl, x1 = c < ccl;
+                v[t][0] = x0 ? h0.y : h0.x;
+                v[t][1] = x1 ? h0.x : h0.y;
+                v[t][2] = x0 ? h1.y : h1.x;
+                v[t][3] = x1 ? h1.x : h1.y;
+            } else {
+                const int ra = min(max(r, 0), a.Rs - 1), rb = min(max(r + 1, 0), a.Rs - 1);
+                const int ca = min(max(c, 0), a.Rf - 1), cb = min(max(c + 1, 0), a.Rf - 1);
+                v[t][0] = a.refv[(size_t)ra * a.Rf + ca];
+                v[t][1] = a.refv[(size_t)ra * a.Rf + cb];
+                v[t][2] = a.refv[(size_t)rb * a.Rf + ca];
+                v[t][3] = a.refv[(size_t)rb * a.Rf + cb];
+            }
             I[t] = (float)a.frames[(size_t)n * HW + pc];
         }
         double e[ERR_FB];
@@ -149,7 +171,7 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
             e[t] = 0.0;
             if (use && n0 + t < a.N && valid(g)) {
                 const float rr = fmaf(-Wp, g, I[t]);
-                const float eps = rr * rr / s2;
+                const float eps = (rr * rr) * inv_s2;
                 kahan_add(pS, pC, eps);
                 e[t] = (double)eps;
             }
@@ -229,7 +251,10 @@ int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const fl
         return PXST_EUNSUPPORTED;
     }
     profile_begin("err_pixels", s);
-    hipLaunchKernelGGL(k_err_pixels, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
+    if (g.Rs >= 2 && g.Rf >= 2)
+        hipLaunchKernelGGL(k_err_pixels<true>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
+    else
+        hipLaunchKernelGGL(k_err_pixels<false>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
     profile_end("err_pixels", s, (long long)g.HW() * g.N, nullptr, 0);
     hipLaunchKernelGGL(k_err_frames, dim3(g.N), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_err_total, dim3(1), dim3(64), 0, s, a);
