@@ -134,7 +134,8 @@ def roofline(mm, avg_ms, launches, evals_per_launch, fp32_equiv_tflops, traffic)
     if mm_n:
         ops = mm_ops / mm_n
         achieved = ops / (mm_ms / mm_n * 1e-3) / 1e12
-        return {"kernel": "pixel-map search, interior tiles (k_pm_mma: int8 matrix cores)",
+        return {"kernel": "pixel-map search, interior tiles (k_pm_mma_*: int8 matrix cores; "
+                           "k_pm_mma_half_planes_lds on the realistic scan)",
                 "bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_INT8_MFMA_TOPS, "int8_ops_per_launch": ops,
                 **common, **equiv}
