@@ -37,10 +37,16 @@ FLOP_PER_EVAL = 4   # r = I - W g (1 FMA) and E += r^2 (1 FMA)
 
 
 def pm_source_hash() -> str:
+    """Hash of the pixel-map search's code (comments and blank space left out, so that
+    an edited comment keeps the counters taken on the same code)."""
+    import re
     h = hashlib.sha256()
     for f in ("pxst_pixel_map.hip", "pxst_device.hpp", "pxst_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2003_12726_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2003_12726_amd", "csrc", f), encoding="utf-8") as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

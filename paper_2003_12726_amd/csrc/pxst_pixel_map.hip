@@ -1094,13 +1094,15 @@ __global__ __launch_bounds__(256) void k_planes_span(const PmArgs a, int2* __res
 // B operand of the tiles, precomputed once per search for every reference position P
 // (coordinates relative to the integer shift e_c of the planes' origin frame c: the
 // interior tiles' positions X all have X - e_c in the grid, since every lookup of theirs
-// is valid; edge tiles use the planes where they cover them),
-// over each plane row's span of interior-tile positions (prow, from k_planes_span):
-// the same bytes the search kernel would generate, in planes [3][Rs Rf][NP] whose 16
-// bytes at (P, 64 kb + 16 g) are lane (c, g)'s operand; and per position the sums
-// sum_n g~_n^2 (exact 64-bit integer, converted once) and sum_n G~_n.  Positions whose
-// lookups leave the grid get zeros (no interior tile reads them).  A wave takes 16
-// positions x 4 frame groups, the layout of the search's B operand.
+// is valid; edge tiles use the planes where they cover them), over each plane row's
+// span of positions of the tiles that read them (prow, from k_planes_span): the bytes
+// the search kernel would generate for a lookup with all four corners valid, in planes
+// [3][Rs Rf][NP] whose 16 bytes at (P, 64 kb + 16 g) are lane (c, g)'s operand, and 0
+// for any other lookup; per position the sums sum_n g~_n^2 (exact 64-bit integer,
+// converted once) and sum_n G~_n; and per (position, 16 frames) the validity bits
+// (bits 0-15: all four corners valid, bits 16-31: at least one valid; padding frames
+// count as valid).  A wave takes 16 positions x 4 frame groups, the layout of the
+// search's B operand.
 constexpr int PL_THREADS = 256;
 constexpr int PL_COLS = 256;   // columns of a plane row per work-group
 __global__ __launch_bounds__(PL_THREADS) void k_pm_planes(const PmArgs a, const int2* __restrict__ prow,
