@@ -162,7 +162,16 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
         if (chunks > (size_t)g.N) chunks = (size_t)g.N;
         if (chunks < 1) chunks = 1;
         L.ref_chunks = (int)chunks;
-        L.rpart = take(chunks > 1 ? chunks * RRs * sizeof(RefPart) : 1);
+        // frame chunks of the tile splat (its partial sums share the buffer)
+        const size_t stiles = (size_t)((g.Rs + RS_TR - 1) / RS_TR) * (size_t)((g.Rf + RS_TC - 1) / RS_TC);
+        size_t sch = (SPLAT_GROUPS + stiles - 1) / (stiles > 0 ? stiles : 1);
+        if (sch > REF_PART_MAX / RRs) sch = REF_PART_MAX / RRs;
+        if (sch > (size_t)g.N) sch = (size_t)g.N;
+        if (sch < 1) sch = 1;
+        L.splat_chunks = (int)sch;
+        const size_t pch = chunks > sch ? chunks : sch;
+        static_assert(sizeof(RefPart) == sizeof(longlong2), "one partial buffer for both updates");
+        L.rpart = take(pch > 1 ? pch * RRs * sizeof(RefPart) : 1);
     }
     L.scan_tmp_bytes = scan_temp_bound(ncells + 3);
     L.scan_tmp = take(L.scan_tmp_bytes);

@@ -60,6 +60,13 @@ constexpr int GRID_THREADS = 256;
 // Reference gather: partial results of at most this many (pixel, frame-chunk) pairs.
 constexpr size_t REF_PART_MAX = (size_t)8 << 20;
 
+// Reference tiles of the splat (rows x columns of reference pixels per work-group), and
+// the work-groups its frame chunks aim at: 3.5 times the 2048 resident at once (8 per
+// CU) -- about half of a reference's tiles receive points, and finer chunks cost more
+// partial sums to add.
+constexpr int RS_TR = 16, RS_TC = 56;
+constexpr size_t SPLAT_GROUPS = 7168;
+
 struct RefPart {
     float s, c;     // compensated float32 numerator of the chunk
     double den;     // float64 weight sum of the chunk
@@ -72,6 +79,7 @@ struct Layout {
     // reference update
     size_t ginfo, gpart, keys, ccount, vals2, cstart, pdata, bsort, fsort, rpart, scan_tmp;
     int ref_chunks;   // frame chunks of the reference gather
+    int splat_chunks; // frame chunks of the reference tile splat
     size_t scan_tmp_bytes;
     // pixel map
     size_t tiles, lists, counters, tinfo;

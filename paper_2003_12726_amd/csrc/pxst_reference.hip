@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 // term).  The sums are exact, so the LDS atomic additions give the same result in any
 // order (bitwise reproducible).  Frame chunks (grid z) write exact partial sums that a
 // second pass adds; the quotient is formed in FP64.
-constexpr int RS_TR = 16, RS_TC = 56, RS_THREADS = 256;
+constexpr int RS_THREADS = 256;
 
 struct SplatArgs {
     const uint16_t* fsort;
@@ -945,7 +945,7 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     a.Rf = g.Rf;
     a.GH = grid_h(g);
     a.GW = grid_w(g);
-    a.nchunks = L.ref_chunks;
+    a.nchunks = L.splat_chunks;
     a.part = (longlong2*)(ws + L.rpart);
     a.ref = ref;
     a.wsum = wsum;

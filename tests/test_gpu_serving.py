@@ -28,7 +28,10 @@ def _lib():
 def requests():
     shapes = [((37, 53), 7, (3, 2), 0.0, False), ((48, 40), 9, (2, 2), 0.0, True),
               ((33, 45), 5, (5, 5), 0.0, False), ((21, 19), 4, (1, 3), 0.02, False),
-              ((40, 64), 6, (3, 3), 0.05, True)]
+              ((40, 64), 6, (3, 3), 0.05, True),
+              # 441 candidates: alone, the interior tiles are searched in halves against
+              # the operand planes; batched, whole with the operand generated in the kernel
+              ((48, 64), 9, (10, 10), 0.03, False)]
     out = []
     for k, (det, n, win, arr, upd) in enumerate(shapes):
         s = random_small_scan(det=det, n_frames=n, window=win, seed=300 + k)
