@@ -344,7 +344,8 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
 /* Kernel timing for benchmarks: when enabled, the library brackets each launch of
  * the named kernel family with HIP events on the launch stream and accumulates
  * their elapsed times (reading them synchronises on the recorded events).
- * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "pm_frac" (a whole
+ * Families: "pm_fast", "pm_edge", "pm_edge_mma", "pm_generic", "pm_planes" (the
+ * operand planes the matrix-core searches read; no work units), "pm_frac" (a whole
  * fractional-step search), "pm_split" (both split-half searches), "defocus_sweep",
  * "ref_gather",
  * "tr_partial", "err_pixels", "pm_fast_int8_ops" (the interior-tile search on the
