@@ -95,8 +95,16 @@ __device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
 // at the corners clamped one by one.
 template <bool PAIRS>
 __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
-    extern __shared__ double wsum_sh[];   // [N][waves]
+    extern __shared__ double wsum_sh[];   // [N][waves], then the frame table [N]
     constexpr int WAVES = ERR_THREADS / 64;
+    // per frame: the fractions of its shift and the integer parts (bits of ints)
+    float4* ftab = (float4*)(wsum_sh + (size_t)a.N * WAVES);
+    for (int n = threadIdx.x; n < a.N; n += ERR_THREADS) {
+        const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+        const float sd0 = floorf(d0), sd1 = floorf(d1);
+        ftab[n] = make_float4(d0 - sd0, d1 - sd1, __int_as_float((int)sd0), __int_as_float((int)sd1));
+    }
+    __syncthreads();
     const size_t HW = (size_t)a.H * a.W;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const size_t pix = (size_t)blockIdx.x * ERR_THREADS + threadIdx.x;
@@ -112,36 +120,30 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
     const int i0 = (int)f0 - a.o0, i1 = (int)f1 - a.o1;
     float pS = 0.f, pC = 0.f;
     for (int n0 = 0; n0 < a.N; n0 += ERR_FB) {
+        // PAIRS: v holds the 2x2 block read at the lookup clamped into the grid; else the
+        // four corners clamped one by one
         float v[ERR_FB][4], I[ERR_FB], fa[ERR_FB], fb[ERR_FB];
-        unsigned ok[ERR_FB];
+        int rr[ERR_FB], cq[ERR_FB];
 #pragma unroll
         for (int t = 0; t < ERR_FB; ++t) {
             const int n = min(n0 + t, a.N - 1);
-            const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
-            const float sd0 = floorf(d0), sd1 = floorf(d1);
-            const float t0 = fu0 - (d0 - sd0), t1 = fu1 - (d1 - sd1);
-            const int r = i0 - (int)sd0 - (t0 < 0.f ? 1 : 0);
-            const int c = i1 - (int)sd1 - (t1 < 0.f ? 1 : 0);
+            const float4 ft = ftab[n];
+            const float t0 = fu0 - ft.x, t1 = fu1 - ft.y;
+            const int r = i0 - __float_as_int(ft.z) - (t0 < 0.f ? 1 : 0);
+            const int c = i1 - __float_as_int(ft.w) - (t1 < 0.f ? 1 : 0);
+            rr[t] = r;
+            cq[t] = c;
             fa[t] = t0 < 0.f ? t0 + 1.f : t0;
             fb[t] = t1 < 0.f ? t1 + 1.f : t1;
-            // corner flags: bit 0 row r, bit 1 row r + 1, bit 2 column c, bit 3 column c + 1
-            ok[t] = ((unsigned)r < (unsigned)a.Rs ? 1u : 0u) | ((unsigned)(r + 1) < (unsigned)a.Rs ? 2u : 0u) |
-                    ((unsigned)c < (unsigned)a.Rf ? 4u : 0u) | ((unsigned)(c + 1) < (unsigned)a.Rf ? 8u : 0u);
             if constexpr (PAIRS) {
                 const int rc = min(max(r, 0), a.Rs - 2), ccl = min(max(c, 0), a.Rf - 2);
                 const float* bp = a.refv + ((unsigned)rc * (unsigned)a.Rf + (unsigned)ccl);
                 const float2 top = *(const float2*)bp;
                 const float2 bot = *(const float2*)(bp + a.Rf);
-                // the block row of the lookup's first row is 1 only where the clamp moved
-                // the block up (r = Rs - 1), that of its second row 0 only where it moved
-                // it down (r = -1); the same for the columns (corners outside the grid
-                // are masked by the flags)
-                const float2 h0 = r > rc ? bot : top, h1 = r < rc ? top : bot;
-                const bool x0 = c > ccl, x1 = c < ccl;
-                v[t][0] = x0 ? h0.y : h0.x;
-                v[t][1] = x1 ? h0.x : h0.y;
-                v[t][2] = x0 ? h1.y : h1.x;
-                v[t][3] = x1 ? h1.x : h1.y;
+                v[t][0] = top.x;
+                v[t][1] = top.y;
+                v[t][2] = bot.x;
+                v[t][3] = bot.y;
             } else {
                 const int ra = min(max(r, 0), a.Rs - 1), rb = min(max(r + 1, 0), a.Rs - 1);
                 const int ca = min(max(c, 0), a.Rf - 1), cb = min(max(c + 1, 0), a.Rf - 1);
@@ -155,18 +157,37 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
         double e[ERR_FB];
 #pragma unroll
         for (int t = 0; t < ERR_FB; ++t) {
+            const int r = rr[t], c = cq[t];
+            // all four corners inside the grid: the values read are the corners
+            const bool in = (unsigned)r <= (unsigned)(a.Rs - 2) && (unsigned)c <= (unsigned)(a.Rf - 2);
             float g;
-            if (__builtin_expect(ok[t] == 15u && valid(v[t][0]) && valid(v[t][1]) && valid(v[t][2]) &&
-                                     valid(v[t][3]), 1)) {
+            if (__builtin_expect(in && valid(v[t][0]) && valid(v[t][1]) && valid(v[t][2]) && valid(v[t][3]), 1)) {
                 const float h0 = fmaf(fb[t], v[t][1] - v[t][0], v[t][0]);
                 const float h1 = fmaf(fb[t], v[t][3] - v[t][2], v[t][2]);
                 g = fmaf(fa[t], h1 - h0, h0);
             } else {
-                const unsigned k = ok[t];
+                // corner flags: bit 0 row r, bit 1 row r + 1, bit 2 column c, bit 3 column c + 1
+                const unsigned k = ((unsigned)r < (unsigned)a.Rs ? 1u : 0u) |
+                                   ((unsigned)(r + 1) < (unsigned)a.Rs ? 2u : 0u) |
+                                   ((unsigned)c < (unsigned)a.Rf ? 4u : 0u) |
+                                   ((unsigned)(c + 1) < (unsigned)a.Rf ? 8u : 0u);
+                float v00 = v[t][0], v01 = v[t][1], v10 = v[t][2], v11 = v[t][3];
+                if constexpr (PAIRS) {
+                    // the block row of the lookup's first row is 1 only where the clamp
+                    // moved the block up (r = Rs - 1), that of its second row 0 only where
+                    // it moved it down (r = -1); the same for the columns
+                    const int rc = min(max(r, 0), a.Rs - 2), ccl = min(max(c, 0), a.Rf - 2);
+                    const float2 top = make_float2(v[t][0], v[t][1]), bot = make_float2(v[t][2], v[t][3]);
+                    const float2 h0 = r > rc ? bot : top, h1 = r < rc ? top : bot;
+                    const bool x0 = c > ccl, x1 = c < ccl;
+                    v00 = x0 ? h0.y : h0.x;
+                    v01 = x1 ? h0.x : h0.y;
+                    v10 = x0 ? h1.y : h1.x;
+                    v11 = x1 ? h1.x : h1.y;
+                }
                 const float q = qnan();
-                g = masked_bilinear4((k & 5u) == 5u ? v[t][0] : q, (k & 9u) == 9u ? v[t][1] : q,
-                                     (k & 6u) == 6u ? v[t][2] : q, (k & 10u) == 10u ? v[t][3] : q, fa[t],
-                                     fb[t]);
+                g = masked_bilinear4((k & 5u) == 5u ? v00 : q, (k & 9u) == 9u ? v01 : q, (k & 6u) == 6u ? v10 : q,
+                                     (k & 10u) == 10u ? v11 : q, fa[t], fb[t]);
             }
             e[t] = 0.0;
             if (use && n0 + t < a.N && valid(g)) {
@@ -245,16 +266,20 @@ int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const fl
     a.frame_err = (double*)(ws + L.err_pix);
     a.frame_out = frame_err;
     a.total = total;
-    const size_t sh = (size_t)g.N * (ERR_THREADS / 64) * sizeof(double);
-    if (sh > 60 * 1024) {
-        set_error("error evaluation supports at most %d frames", (int)(60 * 1024 / 32));
+    const size_t sh = (size_t)g.N * (ERR_THREADS / 64) * sizeof(double) + (size_t)g.N * sizeof(float4);
+    if (sh > 150 * 1024) {
+        set_error("error evaluation supports at most %d frames", (int)(150 * 1024 / 48));
         return PXST_EUNSUPPORTED;
     }
     profile_begin("err_pixels", s);
-    if (g.Rs >= 2 && g.Rf >= 2)
+    // (up to 1920 frames: 92 KB, above the default limit of dynamic LDS)
+    if (g.Rs >= 2 && g.Rf >= 2) {
+        hipFuncSetAttribute((const void*)k_err_pixels<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(k_err_pixels<true>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
-    else
+    } else {
+        hipFuncSetAttribute((const void*)k_err_pixels<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         hipLaunchKernelGGL(k_err_pixels<false>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
+    }
     profile_end("err_pixels", s, (long long)g.HW() * g.N, nullptr, 0);
     hipLaunchKernelGGL(k_err_frames, dim3(g.N), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_err_total, dim3(1), dim3(64), 0, s, a);
