@@ -903,6 +903,8 @@ __host__ __device__ inline size_t mm_lds_bytes(int nc, int n_frames, bool stage_
 // frames staged, so that two fit (each half's region is smaller than the tile's, so
 // the halves issue fewer products in all; they read their operand from L2 twice).
 constexpr size_t MM_LDS_MAX = 160 * 1024;
+// jobs of at least this many 8x8 tiles are searched alone inside a batch
+constexpr long long PM_SOLO_TILES = 1024;
 struct MmPlan {
     bool fast, edge, fast_stage, edge_stage, fast_half, edge_half;
     int slow_max;
@@ -2142,7 +2144,27 @@ int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& 
 // persistent classification over every tile of every job; then, per group of jobs
 // sharing a window, one persistent launch of each kernel class.  `table` is device
 // memory with room for 3 * n PmArgs and the item offsets.
-int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStream_t s) {
+int launch_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar, hipStream_t s) {
+    if (n_in <= 0) return PXST_OK;
+    // A job of at least PM_SOLO_TILES tiles whose workspace holds the operand planes fills
+    // the device by itself: it is searched as it would be alone (planes, tile halves,
+    // per-XCD work runs), each such job in its own launches; the smaller jobs share the
+    // batched launches, where launch overhead is what they save.
+    std::vector<PmJobDesc> small;
+    small.reserve(n_in);
+    for (int j = 0; j < n_in; ++j) {
+        const PmJobDesc& d = jobs_in[j];
+        const long long tiles = (long long)((d.g.H + TILE - 1) / TILE) * ((d.g.W + TILE - 1) / TILE);
+        if (d.L->planes_on && d.g.Rs >= 2 && d.g.Rf >= 2 && tiles >= PM_SOLO_TILES) {
+            const int rc = launch_pixel_map(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
+                                            nullptr, d.ws, *d.L, s);
+            if (rc) return rc;
+        } else {
+            small.push_back(d);
+        }
+    }
+    const PmJobDesc* jobs = small.data();
+    const int n = (int)small.size();
     if (n <= 0) return PXST_OK;
     const int persistent_groups = PERSISTENT_GROUPS;
     // argument table: [fast args n][edge args n][plain args n]; offsets per launch
