@@ -435,6 +435,27 @@ def test_error_parity(case):
     np.testing.assert_allclose(re, o["ref"], rtol=ERR_TOL_REL, atol=1e-6 * o["ref"].max())
 
 
+def test_maximum_frame_count():
+    """The largest frame count the library takes (1920): the reference update, the
+    pixel-map search on the matrix cores with 30 frame blocks (the contraction's byte
+    classes then combine in float64) and the error evaluation at its largest LDS use,
+    each against the oracle on a small detector."""
+    s = random_small_scan(det=(16, 24), n_frames=1920, window=(2, 2), seed=61, n_grid=(40, 48), step=1.0)
+    say(f"[max frames] det={s.det} N={s.n_frames} ref={s.ref_shape}")
+    rg, wg = gpu_reference(s, s.u0, s.dx0)
+    ro, wo = oracle_state(s)
+    np.testing.assert_array_equal(wg > 0, wo > 0)
+    err, _ = ref_rel_error(rg, ro, wo)
+    assert err < REF_TOL_REL, err
+    check_pixel_map(s, ro, wo, s.dx0, s.u0, (2, 2), True, label="1920 frames")
+    ref32 = ro.astype(np.float32).astype(np.float64)
+    pe, fe, tot, re = gpu_error(s, ref32, wo, s.u0, s.dx0)
+    o = oracle.calc_error(s.frames, s.white, s.mask, ref32, wo, s.u0, s.dx0, s.origin, ref_error=True)
+    assert abs(tot - o["total"]) <= ERR_TOL_REL * o["total"]
+    np.testing.assert_allclose(fe, o["frame"], rtol=ERR_TOL_REL, atol=1e-9 * o["frame"].max())
+    np.testing.assert_allclose(pe, o["pixel"], rtol=ERR_TOL_REL, atol=1e-6 * o["pixel"].max())
+
+
 # ------------------------------------------------------------------------ solve
 
 def gpu_solve(s, n_iter, window, refine, update_dx=False, tr=(2, 2)):
