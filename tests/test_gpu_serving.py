@@ -31,7 +31,9 @@ def requests():
               ((40, 64), 6, (3, 3), 0.05, True),
               # 441 candidates: alone, the interior tiles are searched in halves against
               # the operand planes; batched, whole with the operand generated in the kernel
-              ((48, 64), 9, (10, 10), 0.03, False)]
+              ((48, 64), 9, (10, 10), 0.03, False),
+              # 729 candidates: halves in both, against the planes alone, generated batched
+              ((40, 48), 8, (13, 13), 0.04, False)]
     out = []
     for k, (det, n, win, arr, upd) in enumerate(shapes):
         s = random_small_scan(det=det, n_frames=n, window=win, seed=300 + k)
