@@ -38,7 +38,17 @@ struct Span {
     long long work;
     int* pinned;        // device counter copied here asynchronously (or null)
     long long scale;
+    int snap;           // counter snapshot pinned points into (or -1: its own copy)
 };
+// Pinned copies of a block of device counters, shared by the spans that read them and
+// reused once every such span has been read.
+constexpr int SNAP_INTS = 64;
+struct Snap {
+    int* host = nullptr;
+    int refs = 0;
+    bool busy = false;
+};
+std::vector<Snap> g_snaps;
 struct Family {
     std::vector<Span> spans;
     std::vector<hipEvent_t> pool;
@@ -74,6 +84,47 @@ int* take_pinned(Family& f) {
 
 bool profiling() { return g_prof_on; }
 
+int profile_snapshot(const int* dev_counters, int n, hipStream_t s) {
+    if (!g_prof_on || n <= 0 || n > SNAP_INTS) return -1;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int id = -1;
+    for (size_t i = 0; i < g_snaps.size(); ++i)
+        if (!g_snaps[i].busy) {
+            id = (int)i;
+            break;
+        }
+    if (id < 0) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, SNAP_INTS * sizeof(int), hipHostMallocDefault) != hipSuccess) return -1;
+        g_snaps.push_back(Snap{(int*)p, 0, false});
+        id = (int)g_snaps.size() - 1;
+    }
+    Snap& sn = g_snaps[id];
+    if (hipMemcpyAsync(sn.host, dev_counters, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return -1;
+    sn.busy = true;
+    sn.refs = 0;
+    return id;
+}
+
+void profile_end_snap(const char* family, hipStream_t s, int snap, int index, const int* dev_count,
+                      long long scale) {
+    if (!g_prof_on) return;
+    if (snap < 0) {
+        profile_end(family, s, 0, dev_count, scale);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    Family& f = g_prof[family];
+    if (!f.open) return;
+    hipEvent_t b = take_event(f);
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_snaps[snap].refs += 1;
+    f.spans.push_back(Span{f.open, b, 0, g_snaps[snap].host + index, scale, snap});
+    f.open = nullptr;
+}
+
 void profile_begin(const char* family, hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -98,7 +149,7 @@ void profile_end(const char* family, hipStream_t s, long long work, const int* d
         pin = take_pinned(f);
         if (pin) hipMemcpyAsync(pin, dev_count, sizeof(int), hipMemcpyDeviceToHost, s);
     }
-    f.spans.push_back(Span{f.open, b, work, pin, scale});
+    f.spans.push_back(Span{f.open, b, work, pin, scale, -1});
     f.open = nullptr;
 }
 
@@ -640,7 +691,12 @@ int pxst_profile_read(const char* family, double* total_ms, int64_t* launches, i
         }
         f.pool.push_back(sp.a);
         f.pool.push_back(sp.b);
-        if (sp.pinned) f.pinned_pool.push_back(sp.pinned);
+        if (sp.snap >= 0) {
+            Snap& sn = g_snaps[sp.snap];
+            if (--sn.refs <= 0) sn.busy = false;
+        } else if (sp.pinned) {
+            f.pinned_pool.push_back(sp.pinned);
+        }
     }
     f.spans.clear();
     return PXST_OK;

@@ -147,6 +147,12 @@ void profile_begin(const char* family, hipStream_t s);
 void profile_end(const char* family, hipStream_t s, long long work, const int* dev_count,
                  long long scale);
 bool profiling();
+// One asynchronous copy of n device counters for the spans of one call (id, or -1 when
+// profiling is off or the copy could not be made); profile_end_snap then takes its work
+// count from entry index of that copy (or, for id -1, copies dev_count itself).
+int profile_snapshot(const int* dev_counters, int n, hipStream_t s);
+void profile_end_snap(const char* family, hipStream_t s, int snap, int index, const int* dev_count,
+                      long long scale);
 
 // ------------------------------------------------------------------- batched launches
 // Argument tables of a batched launch live in the caller's batch workspace; they are

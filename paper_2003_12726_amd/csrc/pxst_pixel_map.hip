@@ -2064,6 +2064,8 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(COMPACT_THREADS), 0, s, a);
     int rc = check_hip(hipGetLastError(), "pixel-map classification");
     if (rc) return rc;
+    // (profiling: the launches' work counts, final once the lists are built, in one copy)
+    const int snap = profile_snapshot(a.counters, CNT_N, s);
 
     const long long evals_per_good_px = (long long)a.NX * a.NY * g.N;
     // with the operand planes (interior tiles, and edge tiles searched whole)
@@ -2096,23 +2098,23 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
         rc = launch_mma(&ap, 1, nullptr, nullptr, a.ntiles, false, s);
         // int8 operations issued on the matrix cores: 2 per multiply-add, 64 pixels x
         // positions x padded frames x 6 byte pairs
-        profile_end("pm_fast_int8_ops", s, 0, a.counters + CNT_MM_POS,
+        profile_end_snap("pm_fast_int8_ops", s, snap, CNT_MM_POS, a.counters + CNT_MM_POS,
                     2LL * 64 * 6 * (long long)mm_frames_padded(g.N));
-        profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
+        profile_end_snap("pm_fast", s, snap, CNT_GOOD_FAST, a.counters + CNT_GOOD_FAST, evals_per_good_px);
         if (rc) return rc;
     } else {
         const size_t sh = lds_bytes(pl.lf, g.N);
         hipFuncSetAttribute((const void*)pl.fs.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_fast", s);
         hipLaunchKernelGGL(pl.fs.fn, dim3(a.ntiles), dim3(pl.lf.waves * 64), sh, s, pl.fast_args(a));
-        profile_end("pm_fast", s, 0, a.counters + CNT_GOOD_FAST, evals_per_good_px);
+        profile_end_snap("pm_fast", s, snap, CNT_GOOD_FAST, a.counters + CNT_GOOD_FAST, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (interior tiles)");
         if (rc) return rc;
     }
     if (a.mm_on & 2) {
         profile_begin("pm_edge_mma", s);
         rc = launch_mma(&ap, 1, nullptr, nullptr, a.ntiles, true, s);
-        profile_end("pm_edge_mma", s, 0, a.counters + CNT_GOOD_EDGE_MM, evals_per_good_px);
+        profile_end_snap("pm_edge_mma", s, snap, CNT_GOOD_EDGE_MM, a.counters + CNT_GOOD_EDGE_MM, evals_per_good_px);
         if (rc) return rc;
     }
     {
@@ -2120,13 +2122,13 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
         hipFuncSetAttribute((const void*)pl.es.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         profile_begin("pm_edge", s);
         hipLaunchKernelGGL(pl.es.fn, dim3(a.ntiles), dim3(pl.le.waves * 64), sh, s, pl.edge_args(a));
-        profile_end("pm_edge", s, 0, a.counters + CNT_GOOD_EDGE, evals_per_good_px);
+        profile_end_snap("pm_edge", s, snap, CNT_GOOD_EDGE, a.counters + CNT_GOOD_EDGE, evals_per_good_px);
         rc = check_hip(hipGetLastError(), "pixel-map search (edge tiles)");
         if (rc) return rc;
     }
     profile_begin("pm_generic", s);
     hipLaunchKernelGGL(k_pm_generic, dim3(a.ntiles), dim3(256), 0, s, a);
-    profile_end("pm_generic", s, 0, a.counters + CNT_GOOD_GENERIC, evals_per_good_px);
+    profile_end_snap("pm_generic", s, snap, CNT_GOOD_GENERIC, a.counters + CNT_GOOD_GENERIC, evals_per_good_px);
     return check_hip(hipGetLastError(), "pixel-map search (scattered tiles)");
 }
 
