@@ -156,28 +156,40 @@ class Server:
                 raise ValueError(f"job {r.job_id} needs {job_bytes(r)} bytes, over the budget")
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
-        while pend or waiting or resident:
+        def admit(held: int) -> List[tuple]:
+            """Arrived jobs admitted in arrival order while slots and memory allow (held:
+            jobs already resident); their uploads are queued on the stream."""
+            nonlocal used
             t = now()
             while pend and pend[0].arrival / time_scale <= t:
                 r = pend.popleft()
                 waiting.append((r, r.arrival / time_scale))
-            # admission in arrival order while slots and memory allow
-            while waiting and len(resident) < self.max_slots:
+            new = []
+            while waiting and held + len(new) < self.max_slots:
                 r, arr = waiting[0]
                 nb = job_bytes(r)
                 if used + nb > self.budget:
                     break
                 waiting.popleft()
                 res = _Resident(r, self.dev, self.stream)
-                resident.append((res, arr, now(), nb))
+                new.append((res, arr, now(), nb))
                 used += nb
+            return new
+
+        while pend or waiting or resident:
             if not resident:
-                if pend:
-                    time.sleep(max(0.0, pend[0].arrival / time_scale - now()))
-                continue
+                resident = admit(0)
+                if not resident:
+                    if pend:
+                        time.sleep(max(0.0, pend[0].arrival / time_scale - now()))
+                    continue
             self.max_resident = max(self.max_resident, len(resident))
             jobs = [r[0].cjob() for r in resident]
             batch_iterate(jobs, self._batch_ws(len(jobs)))
+            # while the tick runs, admit what has arrived: the host-side staging of their
+            # frames overlaps the device's work, their uploads follow the tick on the
+            # stream, and they join from the next tick
+            joining = admit(len(resident))
             torch.cuda.synchronize(self.dev)
             self.ticks += 1
             fin = now()
@@ -193,7 +205,7 @@ class Server:
                     used -= nb
                 else:
                     keep.append((res, arr, adm, nb))
-            resident = keep
+            resident = keep + joining
         return out
 
 
