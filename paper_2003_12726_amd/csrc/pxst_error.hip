@@ -23,6 +23,8 @@ __global__ void k_sigma2(const uint16_t* __restrict__ frames, const float* __res
     }
     const float Wp = white[pix];
     float S = 0.f, P = 0.f;
+    // (unrolled so that the loads of several frames are in flight; same order of sums)
+#pragma unroll 8
     for (int n = 0; n < N; ++n) {
         const float v = (float)frames[(size_t)n * HW + pix] - Wp;
         P = fmaf(v, v, P);

@@ -831,20 +831,27 @@ __global__ __launch_bounds__(256) void k_pm_pack(const uint16_t* __restrict__ fr
     ipk[base + 64] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
 }
 
-// Per-pixel frame sums of a tile (FP64, exact for the integer sums).
-__global__ __launch_bounds__(64) void k_pm_pixstats(const uint16_t* __restrict__ frames,
-                                                    const float* __restrict__ white,
-                                                    const uint8_t* __restrict__ mask, int N, int H,
-                                                    int W, int tiles_x, double* __restrict__ pstat) {
-    const int tile = blockIdx.x, p = threadIdx.x;
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int i = ty * TILE + (p >> 3), j = tx * TILE + (p & 7);
+// Per-pixel frame sums (FP64, exact for the integer sums), stored per tile [tile][64
+// pixels][4].  One thread per pixel of the detector padded to whole tiles, in row-major
+// order, so that a wave's loads of a frame are contiguous; padding pixels get zeros.
+__global__ __launch_bounds__(256) void k_pm_pixstats(const uint16_t* __restrict__ frames,
+                                                     const float* __restrict__ white,
+                                                     const uint8_t* __restrict__ mask, int N, int H,
+                                                     int W, int tiles_x, double* __restrict__ pstat) {
+    const int PW = tiles_x * TILE;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tiles_y = (H + TILE - 1) / TILE;
+    if (idx >= (size_t)tiles_y * TILE * PW) return;
+    const int i = (int)(idx / PW), j = (int)(idx - (size_t)i * PW);
+    const int tile = (i / TILE) * tiles_x + j / TILE, p = (i % TILE) * TILE + j % TILE;
     const bool good = i < H && j < W && mask[(size_t)i * W + j] != 0;
     const size_t HW = (size_t)H * W;
     double A = 0.0, S = 0.0, V = 0.0;
     if (good) {
         const size_t pix = (size_t)i * W + j;
         const double Wp = (double)white[pix];
+        // (unrolled so that the loads of several frames are in flight; same order of sums)
+#pragma unroll 8
         for (int n = 0; n < N; ++n) {
             const double I = (double)frames[(size_t)n * HW + pix];
             A = fma(I, I, A);
@@ -2137,8 +2144,8 @@ int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& 
     const int ntiles = tiles_x * ((g.H + TILE - 1) / TILE);
     hipLaunchKernelGGL(k_pm_pack, dim3((unsigned)(ntiles * L.kblocks)), dim3(256), 0, s, sc.frames,
                        sc.mask, g.N, g.H, g.W, tiles_x, L.kblocks, (uint4*)(ws + L.ipk));
-    hipLaunchKernelGGL(k_pm_pixstats, dim3((unsigned)ntiles), dim3(64), 0, s, sc.frames, sc.white,
-                       sc.mask, g.N, g.H, g.W, tiles_x, (double*)(ws + L.pstat));
+    hipLaunchKernelGGL(k_pm_pixstats, dim3((unsigned)(((size_t)ntiles * 64 + 255) / 256)), dim3(256), 0, s,
+                       sc.frames, sc.white, sc.mask, g.N, g.H, g.W, tiles_x, (double*)(ws + L.pstat));
     return check_hip(hipGetLastError(), "pixel-map setup");
 }
 
