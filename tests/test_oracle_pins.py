@@ -84,6 +84,23 @@ def test_splat_single_contribution_gives_ratio():
     np.testing.assert_allclose(w.sum(), 350.0 ** 2, rtol=1e-14)
 
 
+def test_splat_drops_out_of_grid_corners():
+    """Sec. 2.2.1 with the reading for corners outside the reference grid: a point half
+    a pixel above the first row adds only to its two in-grid corners (each then holds
+    I/W, with weight W^2 times its bilinear share); nothing lands anywhere else, also
+    not on a pixel that a second point at an integer position fills on its own."""
+    frames = np.array([[[900, 500]]], dtype=np.uint16)
+    white = np.array([[300.0, 200.0]], np.float32)
+    mask = np.ones((1, 2), np.uint8)
+    u = np.array([[[-0.5, 0.0]], [[2.25, 0.0]]], np.float32)
+    ref, w = oracle.update_reference(frames, white, mask, u, np.zeros((1, 2), np.float32), (0, 0), (4, 5))
+    assert np.argwhere(w > 0).tolist() == [[0, 0], [0, 2], [0, 3]]
+    np.testing.assert_allclose(ref[0, 2:4], 3.0, rtol=1e-14)
+    np.testing.assert_allclose(w[0, 2:4], 300.0 ** 2 * 0.5 * np.array([0.75, 0.25]), rtol=1e-14)
+    assert ref[0, 0] == 2.5 and w[0, 0] == 200.0 ** 2
+    assert np.count_nonzero(ref) == 3
+
+
 def test_identity_map_gives_weighted_mean():
     """Integer identity map and integer translations: I_ref[p] = sum W I / sum W^2 (Sec. 2.2.1).
 
@@ -139,6 +156,10 @@ def test_round_half_up_and_float32_edges():
     x32 = np.nextafter(np.float32(0.5), np.float32(0))
     assert np.float32(np.floor(x32 + np.float32(0.5))) == 1.0
     assert oracle.round_half_up(np.float64(x32)) == 0.0
+    # the same in float64: the double just below 1/2 plus 1/2 rounds to 1 in float64
+    x64 = np.nextafter(0.5, 0.0)
+    assert np.floor(x64 + 0.5) == 1.0
+    assert oracle.round_half_up(x64) == 0.0 and oracle.round_half_up(-x64) == 0.0
 
 
 def test_quadratic_refine_exact_on_quadrics():
@@ -157,6 +178,8 @@ def test_quadratic_refine_exact_on_quadrics():
     # a maximum and a saddle are rejected
     assert oracle.quadratic_refine(-(X ** 2 + Y ** 2)) == (0.0, 0.0)
     assert oracle.quadratic_refine(X ** 2 - Y ** 2) == (0.0, 0.0)
+    # also when the maximum's stationary point lies off the centre
+    assert oracle.quadratic_refine(-((X - 0.2) ** 2 + 2.0 * (Y + 0.1) ** 2)) == (0.0, 0.0)
     # vertex outside the cell is clamped
     ox, oy = oracle.quadratic_refine((X - 0.9) ** 2 + (Y + 2.0) ** 2)
     assert ox == 0.5 and oy == -0.5
@@ -288,6 +311,136 @@ def test_masked_pixels_keep_their_map():
     assert np.all(np.isinf(e[bad])) and np.all(k[bad] == -1)
 
 
+def _rendered_scan(offsets_u=None, offsets_dx=None, seed=11):
+    """Noiseless float frames of a smooth speckle reference, rendered with scipy's
+    order-1 spline at fractional true positions (a routine neither side uses)."""
+    rng = np.random.default_rng(seed)
+    H, W, N = 14, 16, 16
+    F = ndimage.gaussian_filter(rng.standard_normal((H + 24, W + 24)), 2.0, mode="wrap")
+    F = 1.0 + 0.2 * F / F.std()
+    white = np.full((H, W), 1000.0)
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    u_id = np.stack([ii, jj]).astype(np.float64)
+    a, b = np.meshgrid(np.arange(4) - 1.5, np.arange(4) - 1.5, indexing="ij")
+    dx_grid = np.round(np.stack([3 * a.ravel(), 3 * b.ravel()], 1))
+    u_true = u_id if offsets_u is None else u_id + offsets_u
+    dx_true = dx_grid if offsets_dx is None else dx_grid + offsets_dx
+    org = (-12, -12)
+    frames = np.stack([white * ndimage.map_coordinates(
+        F, [u_true[0] - dx_true[n, 0] - org[0], u_true[1] - dx_true[n, 1] - org[1]], order=1)
+        for n in range(N)])
+    return F, white, np.ones((H, W), np.uint8), u_id, dx_grid, u_true, dx_true, org
+
+
+def test_pixel_map_refinement_moves_towards_truth():
+    """Sec. 2.2.2, paraboloid refinement: with the truth 0.3 px (slow axis) and 0.2 px
+    (fast axis) off the integer grid, in signs alternating between pixels, the integer
+    search lands on the nearest grid point and the refinement must move each axis
+    towards the truth (a wrong sign or swapped axes moves it away)."""
+    H, W = 14, 16
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    sgn = np.where((ii + jj) % 2 == 0, 1.0, -1.0)
+    F, white, mask, u_id, dx, u_true, _, org = _rendered_scan(np.stack([0.3 * sgn, -0.2 * sgn]))
+    frames = np.stack([white * ndimage.map_coordinates(
+        F, [u_true[0] - dx[n, 0] - org[0], u_true[1] - dx[n, 1] - org[1]], order=1) for n in range(dx.shape[0])])
+    u_int, _, _ = oracle.update_pixel_map(frames, white, mask, F, np.ones_like(F), dx, u_id, org, (2, 2),
+                                          refine=False)
+    np.testing.assert_array_equal(u_int, u_id)            # nearest grid point
+    u_ref, _, _ = oracle.update_pixel_map(frames, white, mask, F, np.ones_like(F), dx, u_id, org, (2, 2),
+                                          refine=True)
+    d = np.abs(u_ref - u_true)
+    for ax, t in ((0, 0.3), (1, 0.2)):
+        assert d[ax].mean() < 0.4 * t, (ax, d[ax].mean())
+        assert np.mean(d[ax] < t) > 0.9, (ax, np.mean(d[ax] < t))
+
+
+def test_translation_refinement_moves_towards_truth():
+    """Sec. 2.2.3: frames rendered with translations 0.3 px / 0.2 px off the integer
+    start, in signs that differ between frames and axes; the integer search keeps the
+    start and the refined translation of every frame is closer to the truth on each
+    axis separately."""
+    N = 16
+    off = np.stack([np.where(np.arange(N) % 2 == 0, 0.3, -0.3), np.where(np.arange(N) % 3 == 0, -0.2, 0.2)], 1)
+    F, white, mask, u_id, dx, _, dx_true, org = _rendered_scan(offsets_dx=off)
+    frames = np.stack([white * ndimage.map_coordinates(
+        F, [u_id[0] - dx_true[n, 0] - org[0], u_id[1] - dx_true[n, 1] - org[1]], order=1) for n in range(N)])
+    d_int, _, _ = oracle.update_translations(frames, white, mask, F, np.ones_like(F), u_id, dx, org, (1, 1),
+                                             refine=False)
+    np.testing.assert_array_equal(d_int, dx)
+    d_ref, _, _ = oracle.update_translations(frames, white, mask, F, np.ones_like(F), u_id, dx, org, (1, 1),
+                                             refine=True)
+    assert np.all(np.abs(d_ref - dx_true) < 0.5 * np.abs(off)), np.abs(d_ref - dx_true)
+
+
+def _constant_band_case():
+    """Reference of constant value c with an invalid band; frames kappa c W everywhere.
+    Every valid lookup gives g = c, so each term is r = c W (kappa - 1) against
+    v = W (kappa c - 1) and any ratio of sums over one set of terms is
+    c^2 (kappa - 1)^2 / (kappa c - 1)^2, whichever terms the band removes."""
+    c, kappa = 1.3, 1.1
+    H, W, N = 9, 11, 3
+    rng = np.random.default_rng(19)
+    white = rng.uniform(200, 900, (H, W))
+    frames = np.broadcast_to(kappa * c * white, (N, H, W)).copy()
+    ref = np.full((H + 10, W + 10), c)
+    w = np.ones_like(ref)
+    w[:, 8:11] = 0
+    ref[:, 8:11] = 0
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    u = np.stack([ii, jj]).astype(np.float64) + 0.25
+    dx = np.array([[0.0, 0.0], [1.0, -1.0], [-1.0, 2.0]])
+    return frames, white, np.ones((H, W), np.uint8), ref, w, u, dx, (-5, -5), c * c * (kappa - 1) ** 2 / (kappa * c - 1) ** 2
+
+
+def test_translation_error_is_ratio_over_valid_pixels():
+    """Sec. 2.2.3 (the ratio of Sec. 2.2.2 with the sums over pixels): both sums run
+    over the same set of pixels with a valid lookup, so the closed-form ratio holds for
+    every shift although the band removes a different set of pixels for each."""
+    frames, white, mask, ref, w, u, dx, org, E0 = _constant_band_case()
+    _, _, _, E = oracle.update_translations(frames, white, mask, ref, w, u, dx, org, (2, 2), refine=False,
+                                            return_errors=True)
+    np.testing.assert_allclose(E, E0, rtol=1e-12)
+    # the band does remove lookups: a lookup column inside it exists for some shift
+    cols = np.floor(u[1] - dx[0, 1] - org[1]).astype(int)
+    assert any(((cols - s >= 7) & (cols - s <= 10)).any() for s in range(-2, 3))
+
+
+def test_pixel_map_error_is_ratio_over_valid_frames():
+    """Sec. 2.2.2: err and var are summed over the frames whose lookup is valid (the
+    reading of var's candidate index), so the closed-form ratio holds for every
+    candidate with at least one valid frame."""
+    frames, white, mask, ref, w, u, dx, org, E0 = _constant_band_case()
+    _, e, k, E = oracle.update_pixel_map(frames, white, mask, ref, w, dx, u, org, (2, 2), refine=False,
+                                         return_errors=True)
+    fin = np.isfinite(E)
+    assert fin.mean() > 0.5
+    np.testing.assert_allclose(E[fin], E0, rtol=1e-12)
+
+
+def test_zero_variance_perfect_fit_is_zero_error():
+    """Reading of Sec. 2.2.2 for var = 0: frames equal to the white-field against a
+    reference of ones fit perfectly with no variance; the error is 0 (a perfect fit),
+    not undefined, so every candidate ties at 0 and the first is taken; the same in
+    the translation search."""
+    H, W, N = 5, 6, 3
+    white = np.full((H, W), 250.0, np.float32)
+    frames = np.full((N, H, W), 250, np.uint16)
+    mask = np.ones((H, W), np.uint8)
+    ref = np.ones((H + 12, W + 12))
+    ii, jj = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    u = np.stack([ii, jj]).astype(np.float32)
+    dx = np.zeros((N, 2), np.float32)
+    u1, e, k = oracle.update_pixel_map(frames, white, mask, ref, np.ones_like(ref), dx, u, (-6, -6), (2, 1),
+                                       refine=False)
+    assert np.all(e == 0) and np.all(k == 0)
+    np.testing.assert_array_equal(u1[0], ii - 2.0)
+    np.testing.assert_array_equal(u1[1], jj - 1.0)
+    d1, e, k = oracle.update_translations(frames, white, mask, ref, np.ones_like(ref), u, dx, (-6, -6), (1, 1),
+                                          refine=False)
+    assert np.all(e == 0) and np.all(k == 0)
+    np.testing.assert_array_equal(d1, np.full((N, 2), -1.0))
+
+
 # ----------------------------------------------------------------------- Sec. 2.2.4
 
 def test_error_equals_frames_times_search_minimum():
@@ -316,17 +469,62 @@ def test_sigma2_is_state_independent_and_zero_at_whitefield():
     assert np.all(b == 0) and np.all(a[s.mask > 0] > 0)
 
 
-def test_reference_plane_error_is_weighted_mean():
-    """Sec. 2.2.4: a constant per-pixel error maps to that constant on the reference plane."""
+def test_reference_plane_error_single_and_two_contributions():
+    """Sec. 2.2.4, error mapped to the reference plane "the same way the reference is
+    formed": a reference pixel reached by a single (frame, pixel) term holds that term's
+    error whatever its bilinear weight; one reached by two terms at integer positions
+    holds their plain mean (the reading: weights omega M, not omega M W).
+
+    1x2 detector, pixels A and B with different white-field values, two frames shifted
+    by one pixel along the fast axis: node 1 receives (A, frame 0) and (B, frame 1),
+    node 2 only (B, frame 0), node 0 only (A, frame 1)."""
+    rng = np.random.default_rng(17)
+    frames = rng.integers(200, 900, (2, 1, 2)).astype(np.uint16)
+    white = np.array([[300.0, 700.0]], np.float32)
+    mask = np.ones((1, 2), np.uint8)
+    u = np.array([[[0.0, 0.0]], [[0.0, 1.0]]], np.float32)
+    dx = np.array([[0.0, 0.0], [0.0, 1.0]], np.float32)
+    ref = rng.uniform(0.5, 1.5, (2, 4))
+    r = oracle.calc_error(frames, white, mask, ref, np.ones_like(ref), u, dx, (0, -1), ref_error=True)
+    e_B0, e_A1 = r["ref"][0, 2], r["ref"][0, 0]
+    e_A0 = r["pixel"][0, 0] - e_A1
+    e_B1 = r["pixel"][0, 1] - e_B0
+    assert e_A0 > 0 and e_B1 > 0 and abs(e_A0 - e_B1) > 0.1 * max(e_A0, e_B1)
+    np.testing.assert_allclose(r["frame"], [e_A0 + e_B0, e_A1 + e_B1], rtol=1e-12)
+    np.testing.assert_allclose(r["ref"][0, 1], 0.5 * (e_A0 + e_B1), rtol=1e-12)
+    assert np.all(r["ref"][1] == 0) and r["ref"][0, 3] == 0
+    # a single term at a fractional position: every touched pixel holds its error
+    f1 = np.array([[[640]]], np.uint16)
+    w1 = np.array([[400.0]], np.float32)
+    u1 = np.array([[[0.3]], [[1.6]]], np.float32)
+    r1 = oracle.calc_error(f1, w1, np.ones((1, 1), np.uint8), ref, np.ones_like(ref), u1,
+                           np.zeros((1, 2), np.float32), (0, 0), ref_error=True)
+    touched = r1["ref"] != 0
+    assert touched.sum() == 4
+    np.testing.assert_allclose(r1["ref"][touched], r1["total"], rtol=1e-12)
+
+
+def test_error_excludes_invalid_lookups():
+    """Sec. 2.2.4 with the masked interpolation of Sec. 4: a lookup with no valid corner
+    contributes nothing.  On an exact scan at its integer truth every valid lookup fits
+    exactly, so with a band of the reference made invalid the total stays 0; counting
+    the band's lookups (as if their value were 0) would add I^2 / sigma^2 > 0."""
     s = exact_scan()
     ref, w = _exact_state(s)
+    w = w.copy()
+    band = slice(ref.shape[1] // 2 - 2, ref.shape[1] // 2 + 2)
+    w[:, band] = 0
+    ref = np.where(w > 0, ref, 0.0)
+    hits = 0
+    for n in range(s.n_frames):
+        cols = np.rint(s.u_true[1] - s.dx_true[n, 1] - s.origin[1]).astype(int)
+        hits += int(((cols >= band.start) & (cols < band.stop)).sum())
+    assert hits > 0
+    e0 = oracle.calc_error(s.frames, s.white, s.mask, ref, w, s.u_true, s.dx_true, s.origin)
     u_off = s.u_true.copy()
-    u_off[0] += 0.5
-    r = oracle.calc_error(s.frames, s.white, s.mask, ref, w, u_off, s.dx_true, s.origin,
-                          ref_error=True)
-    assert r["ref"].shape == tuple(s.ref_shape)
-    assert np.all(r["ref"] >= 0)
-    assert r["ref"].max() <= r["pixel"].max() + 1e-9
+    u_off[1] += 1.0
+    e1 = oracle.calc_error(s.frames, s.white, s.mask, ref, w, u_off, s.dx_true, s.origin)
+    assert e1["total"] > 0 and e0["total"] <= 1e-12 * e1["total"]
 
 
 # ------------------------------------------------------------------------- Sec. 2.2
