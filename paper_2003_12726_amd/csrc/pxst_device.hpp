@@ -100,6 +100,16 @@ __device__ inline float normalised_error(float err, float var, int nv) {
     return err == 0.f ? 0.f : INFINITY;
 }
 
+// The same for a pixel whose white-field value is 0: every residual I - W g is then
+// the count I itself, so over any set of valid frames the error equals the variance
+// and E is exactly 1 (0 when every such count is 0).  Kernels that sum the error and
+// the variance in different orders use this form, so that all candidates of such a
+// pixel tie exactly and the first one wins, as the exact quotient has it.
+__device__ inline float zero_white_error(float err, int nv) {
+    if (nv <= 0) return INFINITY;
+    return err > 0.f ? 1.f : 0.f;
+}
+
 // Paraboloid refinement on a 3x3 stencil E[x+1][y+1] (least-squares fit of
 // q0 + q1 x + q2 y + q3 x^2 + q4 x y + q5 y^2 over x, y in {-1, 0, 1}); the vertex
 // is accepted only for a minimum and clamped to +-0.5.

@@ -649,7 +649,8 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
                 float E = INFINITY;
                 if (good && kx0 + r < NX) {
                     const bool any = nfast > 0 || !signbit(vK[r][m]);
-                    E = normalised_error(eS[r][m] + eP[r][m], vcommon + vK[r][m], any ? 1 : 0);
+                    E = Wp == 0.f ? zero_white_error(eS[r][m] + eP[r][m], any ? 1 : 0)
+                                  : normalised_error(eS[r][m] + eP[r][m], vcommon + vK[r][m], any ? 1 : 0);
                     if (E < bestE) {
                         bestE = E;
                         bestK = (kx0 + r) * CW + m;
@@ -1676,7 +1677,8 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
                             double err = ef[e] - ai[e];
                             err = err > 0.0 ? err : 0.0;
                             const float var = (float)(pp[p].vf - (double)vi[e]);
-                            ebuf[pp[p].eo + rN] = normalised_error((float)err, var, nv);
+                            ebuf[pp[p].eo + rN] = Wl[e] == 0.f ? zero_white_error((float)err, nv)
+                                                               : normalised_error((float)err, var, nv);
                         }
                     }
                 }

@@ -45,6 +45,8 @@ class ScanSpec:
     dx_start: str = "true"               # "true" | "nominal"
     n_frames: Optional[int] = None       # first n frames of the grid
     seed: int = 0
+    bright_frac: float = 0.0             # fraction of reference pixels made bright
+    bright_gain: float = 1.0             # their brightness relative to the speckle
 
 
 @dataclasses.dataclass
@@ -219,6 +221,11 @@ def make_scan(spec: ScanSpec, variant: str = "poisson", mask: str = "ones") -> S
     origin, ref_shape = _place_reference(spec, coords, margin)
 
     ref_true = _speckle(rng, ref_shape, spec.ref_sigma, spec.ref_contrast)
+    if spec.bright_frac > 0:
+        # isolated bright pixels (a high dynamic range), from a generator of their own so
+        # that the other draws of the scan stay those of the plain speckle
+        hot = np.random.Generator(np.random.PCG64(spec.seed + 7919)).random(ref_shape) < spec.bright_frac
+        ref_true = np.where(hot, ref_true * spec.bright_gain, ref_true)
     white = _white(spec, H, W)
     if exact:
         white = np.maximum(np.round(white), 1.0)

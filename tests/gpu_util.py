@@ -12,15 +12,20 @@ ERR_TOL_REL = 1e-5        # error figures
 U32 = 2.0 ** -24          # float32 unit roundoff
 
 
-def emin_bound(E, nv, var, imax, kappa=8.0):
+def emin_bound(E, nv, var, imax, kappa=8.0, wq=0.0):
     """Admissible |E_gpu - E_oracle| of a normalised error E = sum r^2 / var.
 
     Each float32 residual r = I - W g carries an error |e| <= kappa u (|I| + |W g|)
     <= 3 kappa u I_max (a few roundings in the lookup and the product), so
     |dE| <= 2 sqrt(E S) + S with S = nv (3 kappa u I_max)^2 / var, plus 1e-5 E for the
     summation.  For a near-perfect fit (tiny E) this is far above 1e-5 E.
+
+    ``wq``: W times the fixed-point step q = 2^-F of the reference lookups on the matrix
+    cores (F = 21 - e, max |I_ref| < 2^e), added to each residual's error: a lookup
+    there is rounded to a multiple of q, after a float32 interpolation whose error is a
+    fraction of q.  It matters only for references of a high dynamic range.
     """
-    S = nv * (3.0 * kappa * U32 * imax) ** 2 / np.maximum(var, 1e-300)
+    S = nv * (3.0 * kappa * U32 * imax + wq) ** 2 / np.maximum(var, 1e-300)
     return 1e-5 * E + 2.0 * np.sqrt(E * S) + S
 
 
@@ -73,3 +78,13 @@ def compare_argmin(k_gpu, k_orc, E_orc_grid, good_index):
         else:
             bad.append(p)
     return ok, len(bad), bad
+
+
+def fixed_point_step(ref, w):
+    """Step 2^-F of the matrix-core search's fixed-point reference: F = 21 - e with e the
+    exponent for which the largest |I_ref| of a valid pixel is below 2^e."""
+    v = np.abs(np.asarray(ref, dtype=np.float64)[np.asarray(w) > 0])
+    if v.size == 0 or v.max() <= 0:
+        return 0.0
+    e = int(np.frexp(v.max())[1])
+    return 2.0 ** -(21 - e)
