@@ -271,6 +271,25 @@ int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, cons
                float* ref_err, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Figures of merit without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes what pxst_error computes for pixel_err, frame_err and total,
+ * with the same kernels, bit for bit; the reference-plane error is not offered.
+ * Scratch (the reference with its validity, sigma^2 and the partial sums:
+ * 4 Rs Rf + 4 H W + 8 N ceil(H W / 256) + 8 N bytes, each section rounded up to 256)
+ * comes from a fixed device array of PXST_NOALLOC_SCRATCH_BYTES (32 MiB) inside the
+ * library, one copy per GPU it runs on, held until the process ends.  Geometries
+ * that need more return PXST_EUNSUPPORTED before any GPU work.  The call allocates
+ * nothing and needs no clearing between calls.  All calls on one GPU share its array:
+ * calls that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Arguments, layout and the other errors as pxst_error.
+ */
+#define PXST_NOALLOC_SCRATCH_BYTES (32u << 20)
+int pxst_error_noalloc(const pxst_scan* scan, const float* ref, const double* wsum, const float* u,
+                       const float* dx, float* pixel_err, double* frame_err, double* total,
+                       hipStream_t stream);
+
+/*
  * Pixel-map regularisation -- Sec. 2.2.2, closing paragraphs: optionally a Gaussian
  * filter of the map ("sigma"), then optionally the irrotational constraint
  * ("integrate": the map is replaced by the gradient of its least-squares potential).

@@ -58,7 +58,8 @@ class CJob(ctypes.Structure):
 
 SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_reference_ex",
            "pxst_update_pixel_map", "pxst_update_pixel_map_fractional", "pxst_split_half_pixel_map",
-           "pxst_defocus_sweep", "pxst_update_translations", "pxst_error", "pxst_solve", "pxst_batch_workspace_bytes",
+           "pxst_defocus_sweep", "pxst_update_translations", "pxst_error", "pxst_error_noalloc", "pxst_solve",
+           "pxst_batch_workspace_bytes",
            "pxst_batch_iterate", "pxst_regularise_pixel_map", "pxst_profile_enable",
            "pxst_profile_read", "pxst_last_error", "pxst_abi_version")
 
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        vp, vp, sz, vp]
     lib.pxst_update_translations.argtypes = [P(CScan), vp, vp, vp, vp, Window, vp, vp, vp, vp, sz, vp]
     lib.pxst_error.argtypes = [P(CScan), vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pxst_error_noalloc.argtypes = [P(CScan), vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pxst_solve.argtypes = [P(CScan), P(SolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
     lib.pxst_batch_workspace_bytes.argtypes = [i32]
     lib.pxst_batch_workspace_bytes.restype = sz
@@ -264,6 +266,14 @@ def error(scan: Scan, ref, wsum, u, dx, total, pixel_err=None, frame_err=None, r
     _check(lib.pxst_error(ctypes.byref(scan.c()), _ptr(ref), _ptr(wsum), _ptr(u), _ptr(dx),
                           _ptr(pixel_err), _ptr(frame_err), _ptr(total), _ptr(ref_err), p, n,
                           _stream(stream)))
+
+
+def error_noalloc(scan: Scan, ref, wsum, u, dx, total, pixel_err=None, frame_err=None, stream=None):
+    """Figures of merit (Sec. 2.2.4) with the library's fixed scratch array instead of a
+    workspace: no device memory is allocated."""
+    lib = load_library()
+    _check(lib.pxst_error_noalloc(ctypes.byref(scan.c()), _ptr(ref), _ptr(wsum), _ptr(u), _ptr(dx),
+                                  _ptr(pixel_err), _ptr(frame_err), _ptr(total), _stream(stream)))
 
 
 def solve(scan: Scan, opts: SolveOpts, u, dx, ref, wsum, err_hist=None, ws=None, stream=None):

@@ -367,6 +367,64 @@ static int check_ws(const void* ws, size_t bytes, size_t need) {
     return PXST_OK;
 }
 
+// ------------------------------------------------------- allocation-free error pass
+// Scratch of pxst_error_noalloc: a fixed device array, one copy per GPU that the library
+// runs on, held until the process ends.  In host code `scratch` names only a stand-in:
+// its device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[PXST_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_dev;   // device ordinal -> address of its copy
+
+// Address of the current device's copy of `scratch` (looked up on its first use there,
+// with that device current).
+static int scratch_address(char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(e));
+        return PXST_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it == g_scratch_dev.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(e));
+            return PXST_EHIP;
+        }
+        it = g_scratch_dev.emplace(dev, (char*)p).first;
+    }
+    *out = it->second;
+    return PXST_OK;
+}
+
+// The error pass's sections of the scratch array, each 256-byte aligned: the reference
+// with invalid pixels as NaN, sigma^2, the per-(frame, block) partial sums and the
+// per-frame sums.  Every section is written in full before it is read, so nothing is
+// cleared between calls.
+struct NoallocLayout {
+    size_t refv, s2, err_part, err_pix, total;
+};
+
+static NoallocLayout noalloc_layout(const Geom& g) {
+    NoallocLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L.refv = take((size_t)g.Rs * g.Rf * sizeof(float));
+    L.s2 = take(g.HW() * sizeof(float));
+    const size_t nblk = (g.HW() + ERR_THREADS - 1) / ERR_THREADS;
+    L.err_part = take((size_t)g.N * nblk * sizeof(double));
+    L.err_pix = take((size_t)g.N * sizeof(double) + sizeof(double));
+    L.total = off;
+    return L;
+}
+
 }  // namespace pxst
 
 using namespace pxst;
@@ -595,6 +653,35 @@ int pxst_error(const pxst_scan* scan, const float* ref, const double* wsum, cons
         return rc;
     if (ref_err) return launch_reference_error(g, *scan, u, dx, refv, ref_err, w, L, stream);
     return PXST_OK;
+}
+
+int pxst_error_noalloc(const pxst_scan* scan, const float* ref, const double* wsum, const float* u,
+                       const float* dx, float* pixel_err, double* frame_err, double* total,
+                       hipStream_t stream) {
+    int rc;
+    if ((rc = check_scan(scan))) return rc;
+    if ((rc = check_ptr(ref, 4, "ref")) || (rc = check_ptr(wsum, 8, "wsum")) ||
+        (rc = check_ptr(u, 4, "u")) || (rc = check_ptr(dx, 4, "dx")) ||
+        (rc = check_ptr(total, 8, "total")) || (rc = check_ptr(pixel_err, 4, "pixel_err", false)) ||
+        (rc = check_ptr(frame_err, 8, "frame_err", false)))
+        return rc;
+    const Geom g = geom_of(scan->geom);
+    const NoallocLayout NL = noalloc_layout(g);
+    if (NL.total > (size_t)PXST_NOALLOC_SCRATCH_BYTES) {
+        set_error("the error pass of this geometry needs %zu bytes of scratch; the fixed array holds %zu",
+                  NL.total, (size_t)PXST_NOALLOC_SCRATCH_BYTES);
+        return PXST_EUNSUPPORTED;
+    }
+    char* w = nullptr;
+    if ((rc = scratch_address(&w))) return rc;
+    Layout L{};
+    L.err_part = NL.err_part;
+    L.err_pix = NL.err_pix;
+    float* refv = (float*)(w + NL.refv);
+    float* s2 = (float*)(w + NL.s2);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
+    if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
+    return launch_error(g, *scan, refv, s2, u, dx, pixel_err, frame_err, total, w, L, stream);
 }
 
 int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u_out, float sigma,

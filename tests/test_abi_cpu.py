@@ -151,3 +151,14 @@ def test_regularise_argument_checks(lib):
     # solve options carry the same checks
     o = pxst.make_opts(1, (2, 2), sigma=-2.0)
     assert lib.pxst_workspace_bytes(ctypes.byref(g), ctypes.byref(o)) == 0
+
+
+def test_noalloc_error_rejects_geometry_beyond_its_scratch(lib):
+    """The allocation-free error pass refuses, before any GPU work, a geometry whose
+    scratch (reference, sigma^2, partial sums) exceeds the library's fixed array."""
+    P = 0x4000
+    big = _scan(geom=pxst.make_geom(400, (2048, 2048), (2200, 2200), (-50, -50)))
+    assert lib.pxst_error_noalloc(ctypes.byref(big), P, P, P, P, None, None, P, None) == pxst.PXST_EUNSUPPORTED
+    assert "scratch" in pxst.last_error()
+    sc = _scan()
+    assert lib.pxst_error_noalloc(ctypes.byref(sc), P, P, P, P, None, None, None, None) == pxst.PXST_EINVAL
