@@ -122,33 +122,30 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
     print(json.dumps(d["realistic"], indent=1))
 
 
-def roofline(mm, avg_ms, launches, evals_per_launch, fp32_equiv_tflops, traffic):
-    """Roofline of the dominant kernel, the interior-tile pixel-map search.  On the matrix
-    cores its work is the int8 contraction it issues (2 ops per multiply-add); the
-    classic form (4 float32 flop per candidate evaluation on the vector ALUs) is given
-    beside it for comparison."""
-    common = {
-        "traffic": traffic["bytes_per_launch"] if traffic else None,
-        "avg_launch_ms": avg_ms,
-        "launches": launches,
-        "evals_per_launch": evals_per_launch,
-    }
-    equiv = {"fp32_vector_equivalent_tflops": fp32_equiv_tflops,
-             "fp32_vector_equivalent_frac_nonpacked": (fp32_equiv_tflops / PEAK_FP32_NONPACKED_TFLOPS)
-             if fp32_equiv_tflops else None}
+def roofline(mm, avg_ms, launches, evals_per_launch, achieved_tflops, traffic):
+    """Roofline of the dominant kernel, the interior-tile pixel-map search, on the basis of
+    the method's own arithmetic: 4 flop per candidate evaluation (r = I - W g and E += r^2,
+    two FMAs) times the evaluations one launch covers, over the launch's average duration,
+    against the float32 vector peak (157.3 TFLOP/s).  The kernel reaches that work through
+    an exact int8 contraction on the matrix cores; what it issues there (2 ops per int8
+    multiply-add, six byte pairs per frame, padded regions and frames) is reported beside it
+    against the dense int8 peak."""
+    out = {"kernel": "pixel-map search, interior tiles (k_pm_mma_half_planes_lds on the realistic scan: "
+                     "int8 matrix cores)",
+           "bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_PACKED_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved_tflops / PEAK_FP32_PACKED_TFLOPS if achieved_tflops else None,
+           "traffic": traffic["bytes_per_launch"] if traffic else None,
+           "basis": "4 flop per candidate evaluation (pixels x candidates x frames of the launch's tiles) "
+                    "/ average launch time (HIP events on the launch stream) / float32 vector peak",
+           "flop_per_eval": FLOP_PER_EVAL, "evals_per_launch": evals_per_launch,
+           "avg_launch_ms": avg_ms, "launches": launches}
     mm_ms, mm_n, mm_ops = mm
     if mm_n:
         ops = mm_ops / mm_n
-        achieved = ops / (mm_ms / mm_n * 1e-3) / 1e12
-        return {"kernel": "pixel-map search, interior tiles (k_pm_mma_*: int8 matrix cores; "
-                           "k_pm_mma_half_planes_lds on the realistic scan)",
-                "bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_MFMA_TOPS, "unit": "TOP/s",
-                "frac": achieved / PEAK_INT8_MFMA_TOPS, "int8_ops_per_launch": ops,
-                **common, **equiv}
-    return {"kernel": "pixel-map search, interior tiles (k_pm_fast: vector ALU)", "bound": "alu",
-            "achieved": fp32_equiv_tflops, "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
-            "frac": equiv["fp32_vector_equivalent_frac_nonpacked"], "flop_per_eval": FLOP_PER_EVAL,
-            **common}
+        tops = ops / (mm_ms / mm_n * 1e-3) / 1e12
+        out["int8_mfma"] = {"achieved_tops": tops, "peak_tops": PEAK_INT8_MFMA_TOPS,
+                            "frac": tops / PEAK_INT8_MFMA_TOPS, "int8_ops_per_launch": ops}
+    return out
 
 
 # --------------------------------------------------------------------- oracle leg
@@ -183,6 +180,8 @@ def cpu_baseline(scan, n_workers: int, px_per_worker: int):
     t = time.perf_counter()
     with ctx.Pool(n_workers) as pool:
         per = pool.map(_oracle_worker, jobs)
+        pool.close()
+        pool.join()    # every worker has exited before the GPU is touched
     wall = time.perf_counter() - t
     return {
         "value": evals / wall,
@@ -215,6 +214,8 @@ def served_requests(n_jobs: int, workers: int):
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         rows = pool.map(_gen_job, [(k, specs[k], arrivals[k]) for k in range(n_jobs)], chunksize=1)
+        pool.close()
+        pool.join()
     return rows
 
 
@@ -441,6 +442,86 @@ def defocus_bench(scan, dev):
             "best_scale": [float(x) for x in scales[int(best.cpu().numpy()[0])]]}
 
 
+def precision_study(scan, dev, reps: int = 4):
+    """The precision study on the realistic scan: for each reference-update arithmetic of
+    the library (exact -- terms on a power-of-two grid summed exactly in 64-bit integers,
+    the default and the stand-in for an FP64 update; fp32 -- float32 numerator with
+    compensated sums; bf16 -- the exact update stored in bfloat16), one reference update,
+    one pixel-map update and one translation update (+-2 px) from the start state
+    (u0, dx0), compared with the FP64 oracle's results of the same steps stored in
+    tests/golden/precision_realistic.npz (written by the oracle alone), and the full
+    solve's time with that arithmetic."""
+    import numpy as np
+    import torch
+    import paper_2003_12726_amd as pxst
+    g = np.load(os.path.join(ROOT, "tests", "golden", "precision_realistic.npz"))
+    H, W = scan.det
+    f16 = scan.frames.view(np.int16)
+    sc = pxst.Scan(torch.from_numpy(f16).to(dev), torch.from_numpy(scan.white).to(dev),
+                   torch.from_numpy(scan.mask).to(dev), scan.ref_shape, scan.origin)
+    base = pxst.make_opts(scan.iters, scan.window, scan.refine, scan.update_dx, scan.tr_window)
+    ws = pxst.alloc_workspace(sc.geom, base, device=dev)
+    u0 = torch.from_numpy(scan.u0).to(dev)
+    dx0 = torch.from_numpy(scan.dx0).to(dev)
+    rows, cols = g["rows"], g["cols"]
+    frames = [int(x) for x in g["frames"]]
+
+    def stats(x):
+        x = np.abs(np.asarray(x, dtype=np.float64).ravel())
+        return {"max": float(x.max()), "p99": float(np.percentile(x, 99))} if x.size else None
+
+    out = {"workload": "realistic scan, one step of each kind from (u0, dx0): the reference at 8192 "
+                       "well-covered pixels, the map at 400 sampled pixels, translations of 6 frames; "
+                       "the full solve per arithmetic", "modes": {}}
+    for mode in ("exact", "fp32", "bf16"):
+        ref = torch.empty(scan.ref_shape, dtype=torch.float32, device=dev)
+        w = torch.empty(scan.ref_shape, dtype=torch.float64, device=dev)
+        pxst.update_reference(sc, u0, dx0, ref, w, ws, mode=mode)
+        u1 = torch.empty_like(u0)
+        kg = torch.empty((H, W), dtype=torch.int32, device=dev)
+        pxst.update_pixel_map(sc, ref, w, dx0, u0, pxst.make_window(scan.window[0], scan.window[1], scan.refine),
+                              u1, None, kg, ws)
+        dx1 = torch.empty_like(dx0)
+        pxst.update_translations(sc, ref, w, u0, dx0, pxst.make_window(2, 2, True), dx1, None, None, ws)
+        torch.cuda.synchronize()
+        rg = ref.cpu().numpy().ravel()[g["ref_index"]].astype(np.float64)
+        rel = np.abs(rg - g["ref_value"]) / np.maximum(np.abs(g["ref_value"]), 1e-30)
+        ug = u1.cpu().numpy()[:, rows, cols]
+        kgs = kg.cpu().numpy()[rows, cols]
+        ko = g["argmin"]
+        fin = (ko >= 0) & (kgs >= 0)
+        same = fin & (kgs == ko)
+        ties = 0
+        for p in np.nonzero(fin & ~same)[0]:
+            hit = np.nonzero(g["top_index"][p] == kgs[p])[0]
+            eo = g["top_error"][p, 0]
+            if hit.size and abs(g["top_error"][p, hit[0]] - eo) <= 1e-6 * abs(eo):
+                ties += 1
+        du = np.abs(ug[:, same] - g["u"][:, same]).max(axis=0)
+        ddx = np.abs(dx1.cpu().numpy()[frames] - g["dx"]).max(axis=1)
+        o = pxst.make_opts(scan.iters, scan.window, scan.refine, scan.update_dx, scan.tr_window, ref_mode=mode)
+        hist = torch.zeros(max(scan.iters, 1), dtype=torch.float64, device=dev)
+        times = []
+        for rep in range(reps + 1):
+            u = u0.clone()
+            dx = dx0.clone()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            pxst.solve(sc, o, u, dx, ref, w, hist, ws)
+            b.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        out["modes"][mode] = {
+            "ref_rel": stats(rel), "ref_max_abs_over_scale": float(np.abs(rg - g["ref_value"]).max() / g["ref_scale"]),
+            "u_px": stats(du), "argmin_equal": int(same.sum()), "argmin_ties": int(ties),
+            "argmin_other": int((fin & ~same).sum() - ties), "pixels": int(fin.sum()),
+            "dx_px": stats(ddx), "solve_ms": ms,
+            "pm_evals_per_s": scan.pm_evals() * scan.iters / (ms * 1e-3)}
+    return out
+
+
 def pct(xs, q):
     if not xs:
         return None
@@ -457,6 +538,8 @@ def main():
     ap.add_argument("--no-divergent", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the regularisation, fractional, split-half and defocus sections")
+    ap.add_argument("--divergent-only", action="store_true",
+                    help="profiling aid: time only the divergent scan's solve and print its line")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--served-jobs", type=int, default=64)
     ap.add_argument("--served-speedup", type=float, default=50.0)
@@ -478,6 +561,18 @@ def main():
     import torch
     import paper_2003_12726_amd as pxst
     from synth.scans import cached_scan
+
+    if args.divergent_only:
+        pxst.load_library()
+        dev = torch.device("cuda:0")
+        d = cached_scan("divergent")
+        dj = Job(d, dev)
+        dwall, _ = time_steps(dj, args.steps, args.warmup)
+        print(json.dumps({"workload": "divergent: 512x512, 400 frames, window +-15 x +-3 px, 8 iterations, "
+                                      "translation update +-2 px on",
+                          "ms_per_solve": 1000.0 * dwall / args.steps,
+                          "pm_evals_per_s": dj.pm_evals() / (dwall / args.steps)}), flush=True)
+        return
 
     scan = cached_scan("realistic")
     # the oracle leg forks worker processes: run it before this process loads the HIP
@@ -533,7 +628,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (uint16 frames; f64 weight and error sums)",
+        "dtype": "int8 MFMA: uint16 counts x 22-bit fixed-point reference, FP64 combine; FP32 elsewhere",
         "data": "synthetic (seeded scan shaped like the realistic workload)",
         "config": {
             "workload": "realistic: 256x1024 uint16 detector, 121 frames (11x11 grid, 8 px step), "
@@ -567,6 +662,7 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_extras:
+        out["precision_study"] = precision_study(scan, dev)
         out["regularisation"] = regularisation_bench(scan, dev)
         out["fractional_search"] = fractional_bench(scan, dev)
         out["split_half"] = split_half_bench(scan, dev)
