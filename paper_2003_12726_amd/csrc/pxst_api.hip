@@ -247,8 +247,9 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     }
     L.rowmax = take((size_t)g.Rs * sizeof(float));
     L.fscale = take(sizeof(int));
-    const size_t nblk_tr = (HW + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK;
+    const size_t nblk_tr = (size_t)((g.H + TR_TILE - 1) / TR_TILE) * ((g.W + TR_TILE - 1) / TR_TILE);
     L.tr_part = take((size_t)g.N * nblk_tr * (tr_ct > 0 ? tr_ct : 1) * 3 * sizeof(float));
+    L.tr_bbox = take(nblk_tr * 4 * sizeof(int));
     const size_t per_err = (size_t)ERR_THREADS;
     const size_t nblk_err = (HW + per_err - 1) / per_err;
     L.err_part = take((size_t)g.N * nblk_err * sizeof(double));

@@ -181,6 +181,35 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Sum over the 64 lanes of a wave with data-parallel-primitive moves instead of LDS
+// permutes: xor 1 and xor 2 inside quads, then the mirrors of half-rows and rows (each
+// lane then holds its 16-lane row's sum), then the four row sums read from lanes 0, 16,
+// 32 and 48 and added in that order.  The result is uniform across the wave.  Every lane
+// must be active.
+template <int CTRL>
+__device__ inline float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float wave_total(float v) {
+    v += dpp_f32<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f32<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f32<0x141>(v);   // row_half_mirror
+    v += dpp_f32<0x140>(v);   // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return ((r0 + r1) + r2) + r3;
+}
+__device__ inline int wave_total(int v) {
+    v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false);
+    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, false);
+    return ((__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+            __builtin_amdgcn_readlane(v, 32)) + __builtin_amdgcn_readlane(v, 48);
+}
+
 __device__ inline int wave_min_i(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));

@@ -31,7 +31,8 @@ constexpr int MM_KB = 64;
 // Packed frames of one tile and K-block: 4 row groups x 2 bytes x 64 lanes x 16 bytes.
 constexpr size_t MM_PACK_BYTES = 4 * 2 * 64 * 16;
 // Translation partial sums: detector pixels per work-group.
-constexpr int TR_PIX_PER_BLOCK = 4096;
+constexpr int TR_TILE = 64;          // translation search: 64 x 64 detector pixels per work-group
+constexpr int TR_LDS_FLOATS = 8192;  // its staged reference region (32 KB)
 constexpr int TR_THREADS = 256;
 constexpr int TR_CT_MAX = (2 * PXST_MAX_TR_RADIUS + 1) * (2 * PXST_MAX_TR_RADIUS + 1);
 // Error evaluation: pixels per work-group.
@@ -92,7 +93,7 @@ struct Layout {
     bool planes_on;
     size_t planes, pcs, pgu, prow, pvb;
     // translations
-    size_t tr_part;
+    size_t tr_part, tr_bbox;
     // error
     size_t err_part, err_pix;
     // pixel-map regularisation: filter weights and pass buffer; DCT matrices and two

@@ -2,12 +2,20 @@
 // detector for integer shifts of that frame's translation, first minimum and
 // paraboloid refinement.
 //
-// Pass 1 (grid: pixel blocks x frames): a thread walks 16 pixels of one frame; for
-// each it loads the (2Tx+2) x (2Ty+2) reference neighbourhood of u - dx_n - origin
-// once and forms all shifted lookups from it (the bilinear fractions do not depend on
-// the integer shift): when the neighbourhood is fully valid, by interpolating its rows
-// along the fast axis once and the results along the slow axis per shift.  Per-shift sums are reduced over the work-group and written as
-// per-block partials.  Pass 2 (one wave per frame) adds the partials with compensated
+// Pass 0 (one work-group per 64 x 64 detector tile): the bounding box of the integer
+// parts of the map over the tile's good pixels (it does not depend on the frame).
+// Pass 1 (grid: tiles x frames): the work-group stages in LDS the reference region that
+// the tile's lookups of this frame can reach, for every shift (the box moved by the
+// frame's integer shift, widened by the window and one cell); each thread takes 16
+// pixels of the tile (one column, every fourth row), reads each pixel's
+// (2Tx+2) x (2Ty+2) neighbourhood from LDS and forms all shifted lookups from it (the
+// bilinear fractions do not depend on the integer shift): the neighbourhood's rows are
+// interpolated along the fast axis once and the results along the slow axis per shift;
+// a neighbourhood with an invalid value (NaN: invalid reference pixel or outside the
+// grid, which the sum of the row interpolations reveals) takes the masked form per
+// shift instead.  A tile whose region exceeds the LDS reads the neighbourhoods from the
+// reference directly.  Per-shift sums are reduced over the work-group and written as
+// per-tile partials.  Pass 2 (one wave per frame) adds the partials with compensated
 // float32 sums in a fixed order, normalises, takes the first minimum and refines.
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
@@ -26,129 +34,312 @@ struct TrArgs {
     float* dx_out;
     float* err_out;
     int* arg_out;
-    float* part;      // [N][nblk][Ct][3]
+    float* part;      // [N][nblk][Ct][3]: error, variance, a positive value when any lookup was valid
+    int4* bbox;       // [nblk]: min / max of floor(u0), min / max of floor(u1) over good pixels
     int N, H, W, Rs, Rf, o0, o1;
-    int nblk, refine;
+    int nblk, tiles_x, refine;
 };
 
-template <int TX, int TY>
-__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
-    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
-    constexpr int CR = 2 * TY + 2;   // neighbourhood columns
-    constexpr int RR = 2 * TX + 2;   // neighbourhood rows
-    const int blk = blockIdx.x, n = blockIdx.y;
+// Pass 0: integer bounding box of the map over each tile's good pixels (min > max when
+// the tile has none; |u| beyond 2^24 marks the box as unusable).
+__global__ __launch_bounds__(256) void k_tr_bbox(TrArgs a) {
+    const int tile = blockIdx.x;
+    const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const size_t HW = (size_t)a.H * a.W;
-    const float d0 = a.dx_in[2 * n], d1 = a.dx_in[2 * n + 1];
-    const float s0 = floorf(d0), s1 = floorf(d1);
-    const float fd0 = d0 - s0, fd1 = d1 - s1;
-    const uint16_t* fr = a.frames + (size_t)n * HW;
-
-    // per shift: squared residuals; the variance and count of the pixels with a valid
-    // lookup are common to all shifts for pixels whose whole neighbourhood is valid
-    // (vC, cC) and kept per shift for the others (var, cnt)
-    float err[CT], var[CT];
-    int cnt[CT];
-#pragma unroll
-    for (int s = 0; s < CT; ++s) {
-        err[s] = 0.f;
-        var[s] = 0.f;
-        cnt[s] = 0;
-    }
-    float vC = 0.f;
-    int cC = 0;
-    const size_t p_begin = (size_t)blk * TR_PIX_PER_BLOCK;
-    for (int m = 0; m < TR_PIX_PER_BLOCK / TR_THREADS; ++m) {
-        const size_t pix = p_begin + (size_t)m * TR_THREADS + threadIdx.x;
-        if (pix >= HW || a.mask[pix] == 0) continue;
+    int mn0 = INT_MAX, mx0 = INT_MIN, mn1 = INT_MAX, mx1 = INT_MIN;
+    for (int e = threadIdx.x; e < TR_TILE * TR_TILE; e += 256) {
+        const int i = ty * TR_TILE + e / TR_TILE, j = tx * TR_TILE + e % TR_TILE;
+        if (i >= a.H || j >= a.W) continue;
+        const size_t pix = (size_t)i * a.W + j;
+        if (a.mask[pix] == 0) continue;
         const float u0 = a.u[pix], u1 = a.u[HW + pix];
-        const float f0 = floorf(u0), f1 = floorf(u1);
-        const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
-        const int a0 = (int)f0 - (int)s0 - a.o0 - (t0 < 0.f ? 1 : 0);
-        const int b0 = (int)f1 - (int)s1 - a.o1 - (t1 < 0.f ? 1 : 0);
-        const float fa = t0 < 0.f ? t0 + 1.f : t0, fb = t1 < 0.f ? t1 + 1.f : t1;
-        const float Wp = a.white[pix];
-        const float I = (float)fr[pix];
-        const float v = I - Wp, v2 = v * v;
-        // neighbourhood rows a0 - TX .. a0 + TX + 1, columns b0 - TY .. b0 + TY + 1;
-        // shift (sx, sy) looks up corner rows a0 - sx, a0 - sx + 1 and columns
-        // b0 - sy, b0 - sy + 1
-        float nb[RR][CR];
-        bool all = a0 - TX >= 0 && a0 + TX + 1 < a.Rs && b0 - TY >= 0 && b0 + TY + 1 < a.Rf;
+        const bool ok = fabsf(u0) < 16777216.f && fabsf(u1) < 16777216.f;
+        const int f0 = ok ? (int)floorf(u0) : INT_MIN / 4, f1 = ok ? (int)floorf(u1) : INT_MIN / 4;
+        mn0 = min(mn0, f0);
+        mx0 = max(mx0, ok ? f0 : INT_MAX / 4);
+        mn1 = min(mn1, f1);
+        mx1 = max(mx1, ok ? f1 : INT_MAX / 4);
+    }
+    mn0 = wave_min_i(mn0);
+    mx0 = wave_max_i(mx0);
+    mn1 = wave_min_i(mn1);
+    mx1 = wave_max_i(mx1);
+    __shared__ int4 red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = make_int4(mn0, mx0, mn1, mx1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 b = red[0];
+        for (int w = 1; w < 4; ++w) {
+            b.x = min(b.x, red[w].x);
+            b.y = max(b.y, red[w].y);
+            b.z = min(b.z, red[w].z);
+            b.w = max(b.w, red[w].w);
+        }
+        a.bbox[tile] = b;
+    }
+}
+
+// One pixel's contribution to every shift's sums.  The neighbourhood holds rows
+// a0 - TX .. a0 + TX + 1 and columns b0 - TY .. b0 + TY + 1; shift (sx, sy) looks up
+// corner rows a0 - sx, a0 - sx + 1 and columns b0 - sy, b0 - sy + 1, i.e. neighbourhood
+// rows and columns ix = TX - sx + {0, 1}, iy = TY - sy + {0, 1}.
+//
+// tr_fast: every lookup valid; h[r][c] is row r interpolated along the fast axis between
+// columns c and c + 1 (the fractions do not depend on the shift), so a shift costs an
+// interpolation along the slow axis and two FMAs.
+template <int TX, int TY>
+__device__ __forceinline__ void tr_fast(const float (&h)[2 * TX + 2][2 * TY + 1], float fa, float I, float Wp,
+                                        bool good, float (&err)[(2 * TX + 1) * (2 * TY + 1)], float& vC,
+                                        int& cC) {
+    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1;
+    const float v = I - Wp;
+    const float nW = -Wp;
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const int rr = a0 - TX + r;
+    for (int ix = 0; ix < NXs; ++ix) {
 #pragma unroll
-            for (int c = 0; c < CR; ++c) {
-                const int cc = b0 - TY + c;
-                nb[r][c] = (rr >= 0 && rr < a.Rs && cc >= 0 && cc < a.Rf) ? a.refv[(size_t)rr * a.Rf + cc]
-                                                                         : qnan();
-                all = all && valid(nb[r][c]);
+        for (int iy = 0; iy < NYs; ++iy) {
+            const float g = fmaf(fa, h[ix + 1][iy] - h[ix][iy], h[ix][iy]);
+            const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
+            const float rr = fmaf(nW, g, I);
+            err[s] = fmaf(rr, rr, err[s]);
+        }
+    }
+    vC = fmaf(v, v, vC);
+    cC += good ? 1 : 0;
+}
+
+// tr_masked: some neighbourhood value is invalid (NaN): the masked bilinear form of
+// Sec. 4 per shift; a shift whose lookup has no valid corner drops the pixel.
+template <int TX, int TY>
+__device__ __forceinline__ void tr_masked(const float (&nb)[2 * TX + 2][2 * TY + 2], float fa, float fb,
+                                          float I, float Wp, bool good,
+                                          float (&err)[(2 * TX + 1) * (2 * TY + 1)],
+                                          float (&var)[(2 * TX + 1) * (2 * TY + 1)], unsigned& anyv) {
+    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1;
+    const float v = I - Wp, v2 = v * v;
+#pragma unroll
+    for (int ix = 0; ix < NXs; ++ix) {
+#pragma unroll
+        for (int iy = 0; iy < NYs; ++iy) {
+            const float v00 = nb[ix][iy], v01 = nb[ix][iy + 1], v10 = nb[ix + 1][iy],
+                        v11 = nb[ix + 1][iy + 1];
+            const float ga = 1.f - fa, gb = 1.f - fb;
+            float num = 0.f, den = 0.f;
+            if (valid(v00)) { num = fmaf(ga * gb, v00, num); den += ga * gb; }
+            if (valid(v01)) { num = fmaf(ga * fb, v01, num); den += ga * fb; }
+            if (valid(v10)) { num = fmaf(fa * gb, v10, num); den += fa * gb; }
+            if (valid(v11)) { num = fmaf(fa * fb, v11, num); den += fa * fb; }
+            const float g = den > 0.f ? num / den : qnan();
+            const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
+            if (good && valid(g)) {
+                const float rr = fmaf(-Wp, g, I);
+                err[s] = fmaf(rr, rr, err[s]);
+                var[s] += v2;
+                anyv |= 1u << s;
             }
         }
-        if (all) {
-            // every lookup valid: interpolate along fs, then along ss (the fractions are
-            // the same for every shift)
-            float h[RR][CR - 1];
+    }
+}
+
+// a NaN anywhere in the neighbourhood reaches the sum of its row interpolations
+template <int TX, int TY>
+__device__ __forceinline__ bool rows_valid(const float (&h)[2 * TX + 2][2 * TY + 1]) {
+    float chk = 0.f;
+#pragma unroll
+    for (int r = 0; r < 2 * TX + 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2 * TY + 1; ++c) chk += h[r][c];
+    return valid(chk);
+}
+
+// Per-frame constants of the pixel loop.
+struct TrFrame {
+    const uint16_t* fr;
+    float fd0, fd1;
+    int is0, is1;
+    const float* reg;   // staged region: rows from R0, columns from C0, pitch RW
+    int R0, C0, RW;
+};
+
+// The 16 pixels of a thread (column j of its tile, rows wave, wave + 4, ...): each
+// pixel's neighbourhood from the staged region (STAGED) or from the reference, then its
+// contribution to every shift.  CHECK: the neighbourhoods may hold invalid values.  The
+// next pixel's inputs are loaded while the current one is evaluated, and a pixel that
+// is masked or outside the detector runs the same instructions with zero count and
+// white-field, at the box corner (so that its reads stay inside the staged region), and
+// adds nothing.
+template <int TX, int TY, bool STAGED, bool CHECK>
+__device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int i_first, int j, int4 bb,
+                                          float (&err)[(2 * TX + 1) * (2 * TY + 1)],
+                                          float (&var)[(2 * TX + 1) * (2 * TY + 1)], unsigned& anyv,
+                                          float& vC, int& cC) {
+    constexpr int CR = 2 * TY + 2, RR = 2 * TX + 2;
+    constexpr int NM = TR_TILE / (TR_THREADS / 64);
+    const size_t HW = (size_t)a.H * a.W;
+    auto fetch = [&](int m, bool& good, float& u0, float& u1, float& Wp, float& I) {
+        const int i = i_first + (TR_THREADS / 64) * m;
+        const bool in = m < NM && i < a.H && j < a.W;
+        const size_t pix = in ? (size_t)i * a.W + j : 0;
+        const unsigned mk = a.mask[pix];
+        good = in & (mk != 0u);
+        u0 = a.u[pix];
+        u1 = a.u[HW + pix];
+        Wp = a.white[pix];
+        I = (float)f.fr[pix];
+    };
+    bool g_n;
+    float u0_n, u1_n, W_n, I_n;
+    fetch(0, g_n, u0_n, u1_n, W_n, I_n);
+    for (int m = 0; m < NM; ++m) {
+        const bool good = g_n;
+        const float u0 = good ? u0_n : (float)bb.x, u1 = good ? u1_n : (float)bb.z;
+        const float Wp = good ? W_n : 0.f, I = good ? I_n : 0.f;
+        fetch(m + 1, g_n, u0_n, u1_n, W_n, I_n);
+        const float f0 = floorf(u0), f1 = floorf(u1);
+        const float t0 = (u0 - f0) - f.fd0, t1 = (u1 - f1) - f.fd1;
+        const int a0 = (int)f0 - f.is0 - a.o0 - (t0 < 0.f ? 1 : 0);
+        const int b0 = (int)f1 - f.is1 - a.o1 - (t1 < 0.f ? 1 : 0);
+        const float fa = t0 < 0.f ? t0 + 1.f : t0, fb = t1 < 0.f ? t1 + 1.f : t1;
+        float nb[RR][CR];
+        if (STAGED) {
+            const float* q = f.reg + (a0 - TX - f.R0) * f.RW + (b0 - TY - f.C0);
 #pragma unroll
             for (int r = 0; r < RR; ++r)
 #pragma unroll
-                for (int c = 0; c < CR - 1; ++c) h[r][c] = fmaf(fb, nb[r][c + 1] - nb[r][c], nb[r][c]);
-            const float nW = -Wp;
-#pragma unroll
-            for (int ix = 0; ix < NXs; ++ix) {
-#pragma unroll
-                for (int iy = 0; iy < NYs; ++iy) {
-                    const float g = fmaf(fa, h[ix + 1][iy] - h[ix][iy], h[ix][iy]);
-                    const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
-                    const float rr = fmaf(nW, g, I);
-                    err[s] = fmaf(rr, rr, err[s]);
-                }
-            }
-            vC += v2;
-            cC += 1;
+                for (int c = 0; c < CR; ++c) nb[r][c] = q[r * f.RW + c];
         } else {
 #pragma unroll
-            for (int ix = 0; ix < NXs; ++ix) {
+            for (int r = 0; r < RR; ++r) {
+                const int rr = a0 - TX + r;
 #pragma unroll
-                for (int iy = 0; iy < NYs; ++iy) {
-                    const float v00 = nb[ix][iy], v01 = nb[ix][iy + 1], v10 = nb[ix + 1][iy],
-                                v11 = nb[ix + 1][iy + 1];
-                    const float ga = 1.f - fa, gb = 1.f - fb;
-                    float num = 0.f, den = 0.f;
-                    if (valid(v00)) { num = fmaf(ga * gb, v00, num); den += ga * gb; }
-                    if (valid(v01)) { num = fmaf(ga * fb, v01, num); den += ga * fb; }
-                    if (valid(v10)) { num = fmaf(fa * gb, v10, num); den += fa * gb; }
-                    if (valid(v11)) { num = fmaf(fa * fb, v11, num); den += fa * fb; }
-                    const float g = den > 0.f ? num / den : qnan();
-                    // shift (sx, sy) = (TX - ix, TY - iy); candidate index (sx + TX) NYs + (sy + TY)
-                    const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
-                    if (valid(g)) {
-                        const float rr = fmaf(-Wp, g, I);
-                        err[s] = fmaf(rr, rr, err[s]);
-                        var[s] += v2;
-                        cnt[s] += 1;
+                for (int c = 0; c < CR; ++c) {
+                    const int cc = b0 - TY + c;
+                    nb[r][c] = (rr >= 0 && rr < a.Rs && cc >= 0 && cc < a.Rf)
+                                   ? a.refv[(size_t)rr * a.Rf + cc] : qnan();
+                }
+            }
+        }
+        float h[RR][CR - 1];
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int c = 0; c < CR - 1; ++c) h[r][c] = fmaf(fb, nb[r][c + 1] - nb[r][c], nb[r][c]);
+        if (!CHECK || rows_valid<TX, TY>(h))
+            tr_fast<TX, TY>(h, fa, I, Wp, good, err, vC, cC);
+        else
+            tr_masked<TX, TY>(nb, fa, fb, I, Wp, good, err, var, anyv);
+    }
+}
+
+// Pass 1.  STAGED: the tiles whose region fits the LDS; the others (and tiles without a
+// good pixel) in the launch without staging.  Every tile is written by exactly one.
+template <int TX, int TY, bool STAGED>
+__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
+    constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
+    __shared__ float reg[STAGED ? TR_LDS_FLOATS : 1];
+    const int tile = blockIdx.x, n = blockIdx.y;
+    const int tyi = tile / a.tiles_x, txi = tile - tyi * a.tiles_x;
+    const int4 bb = a.bbox[tile];
+    const bool any_px = bb.x <= bb.y;
+    const long long rh = (long long)bb.y - bb.x + 2 * TX + 3, rw = (long long)bb.w - bb.z + 2 * TY + 3;
+    const bool fits = any_px && rh * rw <= TR_LDS_FLOATS;
+    if (fits != STAGED) return;
+    const size_t HW = (size_t)a.H * a.W;
+    const float d0 = a.dx_in[2 * n], d1 = a.dx_in[2 * n + 1];
+    const float s0 = floorf(d0), s1 = floorf(d1);
+    TrFrame f;
+    f.fr = a.frames + (size_t)n * HW;
+    f.fd0 = d0 - s0;
+    f.fd1 = d1 - s1;
+    f.is0 = (int)s0;
+    f.is1 = (int)s1;
+    f.reg = reg;
+    f.RW = STAGED ? (int)rw : 0;
+    // the region of this frame's lookups: rows R0 .. R0 + rh - 1, columns C0 .. C0 + rw - 1
+    f.R0 = bb.x - f.is0 - a.o0 - 1 - TX;
+    f.C0 = bb.z - f.is1 - a.o1 - 1 - TY;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // staged region entirely valid (no invalid reference pixel, inside the grid): every
+    // neighbourhood read from it is valid and skips the test
+    bool region_ok = false;
+    if (STAGED) {
+        // wave w stages rows w, w + 4, ...: lanes take columns lane, lane + 64, ...; eight
+        // rows' loads in flight at a time
+        const int RH = (int)rh, RW = f.RW;
+        bool bad = false;
+        for (int r0 = wave; r0 < RH; r0 += 8 * (TR_THREADS / 64)) {
+            for (int c = lane; c < RW; c += 64) {
+                const int gc = f.C0 + c;
+                const bool cin = gc >= 0 && gc < a.Rf;
+                float vals[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int r = r0 + k * (TR_THREADS / 64), gr = f.R0 + r;
+                    vals[k] = (r < RH && cin && gr >= 0 && gr < a.Rs) ? a.refv[(size_t)gr * a.Rf + gc] : qnan();
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int r = r0 + k * (TR_THREADS / 64);
+                    if (r < RH) {
+                        reg[r * RW + c] = vals[k];
+                        bad = bad || !valid(vals[k]);
                     }
                 }
             }
         }
+        region_ok = !__syncthreads_or(bad ? 1 : 0);
     }
+
+    // per shift: squared residuals; the variance of the pixels with a valid lookup is
+    // common to all shifts for pixels whose whole neighbourhood is valid (vC, cC) and
+    // kept per shift for the others (var, with a bit per shift set by any valid lookup)
+    float err[CT], var[CT];
 #pragma unroll
     for (int s = 0; s < CT; ++s) {
-        var[s] += vC;
-        cnt[s] += cC;
+        err[s] = 0.f;
+        var[s] = 0.f;
     }
-    // work-group reduction of every per-shift sum
+    unsigned anyv = 0u;
+    float vC = 0.f;
+    int cC = 0;
+    const int j = txi * TR_TILE + lane, i_first = tyi * TR_TILE + wave;
+    if (any_px) {
+        if (STAGED && region_ok)
+            tr_pixels<TX, TY, STAGED, false>(a, f, i_first, j, bb, err, var, anyv, vC, cC);
+        else
+            tr_pixels<TX, TY, STAGED, true>(a, f, i_first, j, bb, err, var, anyv, vC, cC);
+    }
+
+    // work-group reduction of every per-shift sum; when no pixel of the work-group took
+    // the masked form, the variance and count are the common ones for every shift
+    // (a pixel's masked-form variance is non-zero only with its bit set)
     __shared__ float red[TR_THREADS / 64][CT * 3];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool masked = __syncthreads_or(anyv != 0u ? 1 : 0);
+    if (masked) {
 #pragma unroll
-    for (int s = 0; s < CT; ++s) {
-        const float e = wave_sum<float>(err[s]);
-        const float vv = wave_sum<float>(var[s]);
-        const int c = wave_sum<int>(cnt[s]);
-        if (lane == 0) {
-            red[wave][3 * s] = e;
-            red[wave][3 * s + 1] = vv;
-            red[wave][3 * s + 2] = (float)c;
+        for (int s = 0; s < CT; ++s) {
+            const float e = wave_total(err[s]);
+            const float vv = wave_total(var[s] + vC);
+            const int c = wave_total(cC + (int)((anyv >> s) & 1u));
+            if (lane == 0) {
+                red[wave][3 * s] = e;
+                red[wave][3 * s + 1] = vv;
+                red[wave][3 * s + 2] = (float)c;
+            }
+        }
+    } else {
+        const float vv = wave_total(vC);
+        const int c = wave_total(cC);
+#pragma unroll
+        for (int s = 0; s < CT; ++s) {
+            const float e = wave_total(err[s]);
+            if (lane == 0) {
+                red[wave][3 * s] = e;
+                red[wave][3 * s + 1] = vv;
+                red[wave][3 * s + 2] = (float)c;
+            }
         }
     }
     __syncthreads();
@@ -156,7 +347,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
         float acc = 0.f;
 #pragma unroll
         for (int w = 0; w < TR_THREADS / 64; ++w) acc += red[w][q];
-        a.part[((size_t)n * a.nblk + blk) * (CT * 3) + q] = acc;
+        a.part[((size_t)n * a.nblk + tile) * (CT * 3) + q] = acc;
     }
 }
 
@@ -218,22 +409,23 @@ __global__ __launch_bounds__(64) void k_tr_final(TrArgs a) {
 typedef void (*TrKernel)(TrArgs);
 
 template <int TX, int TY>
-void pick(TrKernel& p, TrKernel& f) {
-    p = k_tr_partial<TX, TY>;
+void pick(TrKernel& ps, TrKernel& pg, TrKernel& f) {
+    ps = k_tr_partial<TX, TY, true>;
+    pg = k_tr_partial<TX, TY, false>;
     f = k_tr_final<TX, TY>;
 }
 
-bool pick_tr(int tx, int ty, TrKernel& p, TrKernel& f) {
+bool pick_tr(int tx, int ty, TrKernel& ps, TrKernel& pg, TrKernel& f) {
     switch (tx * 3 + ty) {
-        case 0: pick<0, 0>(p, f); return true;
-        case 1: pick<0, 1>(p, f); return true;
-        case 2: pick<0, 2>(p, f); return true;
-        case 3: pick<1, 0>(p, f); return true;
-        case 4: pick<1, 1>(p, f); return true;
-        case 5: pick<1, 2>(p, f); return true;
-        case 6: pick<2, 0>(p, f); return true;
-        case 7: pick<2, 1>(p, f); return true;
-        case 8: pick<2, 2>(p, f); return true;
+        case 0: pick<0, 0>(ps, pg, f); return true;
+        case 1: pick<0, 1>(ps, pg, f); return true;
+        case 2: pick<0, 2>(ps, pg, f); return true;
+        case 3: pick<1, 0>(ps, pg, f); return true;
+        case 4: pick<1, 1>(ps, pg, f); return true;
+        case 5: pick<1, 2>(ps, pg, f); return true;
+        case 6: pick<2, 0>(ps, pg, f); return true;
+        case 7: pick<2, 1>(ps, pg, f); return true;
+        case 8: pick<2, 2>(ps, pg, f); return true;
     }
     return false;
 }
@@ -243,8 +435,8 @@ bool pick_tr(int tx, int ty, TrKernel& p, TrKernel& f) {
 int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
                         const float* dx_in, const pxst_window& win, float* dx_out, float* err_min,
                         int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
-    TrKernel kp = nullptr, kf = nullptr;
-    if (!pick_tr(win.r_ss, win.r_fs, kp, kf)) {
+    TrKernel kp = nullptr, kg = nullptr, kf = nullptr;
+    if (!pick_tr(win.r_ss, win.r_fs, kp, kg, kf)) {
         set_error("translation window radii must be in 0..%d", PXST_MAX_TR_RADIUS);
         return PXST_EUNSUPPORTED;
     }
@@ -266,10 +458,14 @@ int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, c
     a.Rf = g.Rf;
     a.o0 = g.o0;
     a.o1 = g.o1;
-    a.nblk = (int)((g.HW() + TR_PIX_PER_BLOCK - 1) / TR_PIX_PER_BLOCK);
+    a.tiles_x = (g.W + TR_TILE - 1) / TR_TILE;
+    a.nblk = a.tiles_x * ((g.H + TR_TILE - 1) / TR_TILE);
+    a.bbox = (int4*)(ws + L.tr_bbox);
     a.refine = win.refine != 0;
+    hipLaunchKernelGGL(k_tr_bbox, dim3(a.nblk), dim3(256), 0, s, a);
     profile_begin("tr_partial", s);
     hipLaunchKernelGGL(kp, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
+    hipLaunchKernelGGL(kg, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
     profile_end("tr_partial", s,
                 (long long)g.HW() * g.N * (2 * win.r_ss + 1) * (2 * win.r_fs + 1), nullptr, 0);
     hipLaunchKernelGGL(kf, dim3(g.N), dim3(64), 0, s, a);
