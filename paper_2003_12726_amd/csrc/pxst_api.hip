@@ -13,7 +13,6 @@
 
 namespace pxst {
 
-size_t scan_temp_bound(size_t n);
 
 // ---------------------------------------------------------------------------- errors
 static thread_local char g_err[512] = "";
@@ -199,11 +198,13 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     L.keys = take(HW * 4);
     L.vals2 = take(HW * 4);
     const size_t ncells = (size_t)grid_h(g) * (size_t)grid_w(g);
-    L.ccount = take((ncells + 3) * 4);
-    L.cstart = take((ncells + 3) * 4);
+    L.ccount = take((ncells + 2) * 4);
+    L.cstart = take((size_t)grid_h(g) * (grid_w(g) + 1) * 4);
+    L.rtot = take((size_t)grid_h(g) * 4);
+    L.rstart = take(((size_t)grid_h(g) + 1) * 4);
+    L.kstart = take(4 * 4);
     L.pdata = take(HW * 16);
     L.bsort = take(HW * 8);
-    L.fsort = take((size_t)g.N * HW * sizeof(uint16_t));
     {
         // frame chunks of the reference gather: enough (pixel, chunk) work items to fill
         // the device, bounded by the partial-result buffer
@@ -224,8 +225,6 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
         static_assert(sizeof(RefPart) == sizeof(longlong2), "one partial buffer for both updates");
         L.rpart = take(pch > 1 ? pch * RRs * sizeof(RefPart) : 1);
     }
-    L.scan_tmp_bytes = scan_temp_bound(ncells + 3);
-    L.scan_tmp = take(L.scan_tmp_bytes);
     const size_t ntiles = (size_t)((g.H + TILE - 1) / TILE) * ((g.W + TILE - 1) / TILE);
     L.tiles = take(ntiles * sizeof(TileDesc));
     L.lists = take(4 * ntiles * sizeof(int));

@@ -78,10 +78,9 @@ struct Layout {
     // common
     size_t refv, sat, sat_tmp, s2;
     // reference update
-    size_t ginfo, gpart, keys, ccount, vals2, cstart, pdata, bsort, fsort, rpart, scan_tmp;
+    size_t ginfo, gpart, keys, ccount, vals2, cstart, rtot, rstart, kstart, pdata, bsort, rpart;
     int ref_chunks;   // frame chunks of the reference gather
     int splat_chunks; // frame chunks of the reference tile splat
-    size_t scan_tmp_bytes;
     // pixel map
     size_t tiles, lists, counters, tinfo;
     size_t ipk, pstat;        // frames packed as int8 matrix operands; per-pixel frame sums

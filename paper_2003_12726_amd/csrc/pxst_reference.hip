@@ -2,10 +2,9 @@
 // reference-plane error (Sec. 2.2.4).
 //
 // Both start from an inverted map: the good pixels are binned by floor(u) - origin
-// into a cell grid (a stable radix sort of cell keys gives each cell its pixels in
-// index order, so a row of cells is a contiguous run of sorted entries), and the
-// frames are copied into sorted-entry order so that an entry's frame value is read at
-// the entry's own index.
+// into a cell grid by a counting sort that leaves every cell's pixels in pixel order,
+// so a row of cells is a contiguous run of entries; an entry carries its pixel index,
+// through which the frames are read in their own order.
 //
 // Reference update: a work-group owns a tile of reference pixels and, frame by frame,
 // walks the rows of cells whose points can put a bilinear corner on the tile, adding
@@ -17,8 +16,6 @@
 // cells around p + floor(dx_n) (only those can put a corner on p), with compensated
 // float32 sums over frames and float64 weight sums; frame chunks (grid z) are combined
 // in chunk order, so every sum has a fixed order.
-#include <rocprim/device/device_scan.hpp>
-
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
 
@@ -148,14 +145,34 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __
 
 // The inverted map is a counting sort of the pixels by cell key (cell index in the
 // grid; ncells: good pixel outside the grid; ncells + 1: bad pixel) that leaves the
-// pixels of every key in pixel order, as a stable sort would:
-//   counts per key -> exclusive scan = cstart (first entry of every key) -> pixels of
-//   grid cells placed with atomic slot counters -> every cell's few entries sorted by
-//   pixel index; good pixels outside the grid placed in pixel order by one work-group.
-// Bad pixels are counted but not placed (no pass reads them).
-__global__ void k_fill_u32(unsigned* __restrict__ p, size_t n, unsigned v) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// pixels of every key in pixel order, as a stable sort would.  Only the cells of the
+// good pixels' bounding box (clipped to the grid) are touched:
+//   counts cleared -> counts per key (integer atomics) -> per row of cells an exclusive
+//   scan of its counts (cstart, one more entry for the row's end) and the row's total ->
+//   one work-group scans the row totals (rstart) and sets the starts of the two other
+//   keys (kstart) -> pixels of grid cells placed with atomic slot counters (which returns
+//   every count to 0) -> per cell its few entries sorted by pixel index and the entries'
+//   data written; good pixels outside the grid placed in pixel order by one work-group.
+// The first entry of cell (r, c) is rstart[r] + cstart[r (GW + 1) + c].  Bad pixels are
+// counted but not placed (no pass reads them).
+__device__ inline void grid_region(const GridInfo& gi, int GH, int GW, int& r0, int& r1, int& c0, int& c1) {
+    r0 = max(gi.bmin0 - gi.g0, 0);
+    r1 = min(gi.bmax0 - gi.g0, GH - 1);
+    c0 = max(gi.bmin1 - gi.g1, 0);
+    c1 = min(gi.bmax1 - gi.g1, GW - 1);
+}
+
+// One work-group per row of cells: clears the counts of the region's cells (and the two
+// other keys' counts).
+__global__ __launch_bounds__(256) void k_count_clear(const GridInfo* __restrict__ gi_, int GH, int GW,
+                                                     unsigned* __restrict__ cnt) {
+    const GridInfo gi = *gi_;
+    int r0, r1, c0, c1;
+    grid_region(gi, GH, GW, r0, r1, c0, c1);
+    const int r = blockIdx.x;
+    if (r == 0 && threadIdx.x < 2) cnt[(size_t)GH * GW + threadIdx.x] = 0u;
+    if (r < r0 || r > r1) return;
+    for (int c = c0 + (int)threadIdx.x; c <= c1; c += 256) cnt[(size_t)r * GW + c] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask,
@@ -184,90 +201,186 @@ __global__ __launch_bounds__(256) void k_keys(const float* __restrict__ u, const
     }
 }
 
+// Inclusive scan over the 64 lanes of a wave (row_shr steps inside rows of 16, then the
+// row ends broadcast to the rows above them).
+__device__ inline unsigned wave_incl_scan(unsigned v) {
+    const unsigned lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned t = __shfl_up(v, d, 64);
+        if (lane >= (unsigned)d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of a work-group's 256 values (one per thread); total returned.
+__device__ inline unsigned block_excl_scan(unsigned v, unsigned* tmp4, unsigned& total) {
+    const unsigned lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned inc = wave_incl_scan(v);
+    if (lane == 63) tmp4[wave] = inc;
+    __syncthreads();
+    unsigned before = 0;
+    total = 0;
+#pragma unroll
+    for (unsigned w = 0; w < 4; ++w) {
+        before += w < wave ? tmp4[w] : 0u;
+        total += tmp4[w];
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+// One work-group per row of cells: in-row exclusive scan of the region's counts, with
+// the row's end after its last cell, and the row's total (0 outside the region).
+__global__ __launch_bounds__(256) void k_scan_rows(const GridInfo* __restrict__ gi_, int GH, int GW,
+                                                   const unsigned* __restrict__ cnt, unsigned* __restrict__ cstart,
+                                                   unsigned* __restrict__ rtot) {
+    __shared__ unsigned tmp4[4];
+    const GridInfo gi = *gi_;
+    int r0, r1, c0, c1;
+    grid_region(gi, GH, GW, r0, r1, c0, c1);
+    const int r = blockIdx.x;
+    if (r < r0 || r > r1) {
+        if (threadIdx.x == 0) rtot[r] = 0u;
+        return;
+    }
+    const unsigned* cr = cnt + (size_t)r * GW;
+    unsigned* sr = cstart + (size_t)r * (GW + 1);
+    unsigned run = 0;
+    for (int cb = c0; cb <= c1; cb += 256) {
+        const int c = cb + (int)threadIdx.x;
+        const unsigned v = c <= c1 ? cr[c] : 0u;
+        unsigned tot;
+        const unsigned ex = block_excl_scan(v, tmp4, tot);
+        if (c <= c1) sr[c] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        sr[c1 + 1] = run;
+        rtot[r] = run;
+    }
+}
+
+// One work-group: exclusive scan of the row totals into rstart[0 .. GH] and the starts
+// of the other keys: kstart[0] = first entry outside the grid, kstart[1] = number of
+// good pixels, kstart[2] = end.
+__global__ __launch_bounds__(256) void k_scan_top(int GH, const unsigned* __restrict__ rtot,
+                                                  const unsigned* __restrict__ cnt, unsigned ncells,
+                                                  unsigned* __restrict__ rstart, unsigned* __restrict__ kstart) {
+    __shared__ unsigned tmp4[4];
+    unsigned run = 0;
+    for (int rb = 0; rb < GH; rb += 256) {
+        const int r = rb + (int)threadIdx.x;
+        const unsigned v = r < GH ? rtot[r] : 0u;
+        unsigned tot;
+        const unsigned ex = block_excl_scan(v, tmp4, tot);
+        if (r < GH) rstart[r] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        rstart[GH] = run;
+        const unsigned nov = cnt[ncells + KEY_OVERFLOW_OFF], nbad = cnt[ncells + KEY_INVALID_OFF];
+        kstart[0] = run;
+        kstart[1] = run + nov;
+        kstart[2] = run + nov + nbad;
+    }
+}
+
+__device__ inline unsigned cell_first(const unsigned* __restrict__ cstart, const unsigned* __restrict__ rstart,
+                                      int GW, int r, int c) {
+    return rstart[r] + cstart[(size_t)r * (GW + 1) + c];
+}
+
 // Places the pixels of grid cells: slot = remaining count - 1 (the order inside a cell
-// is fixed afterwards).
-__global__ void k_cell_scatter(const unsigned* __restrict__ keys, int HW, unsigned ncells,
-                               const unsigned* __restrict__ cstart, unsigned* __restrict__ cnt,
-                               unsigned* __restrict__ vals) {
+// is fixed afterwards); the counts end at 0.
+__global__ void k_cell_scatter(const unsigned* __restrict__ keys, int HW, int GW, unsigned ncells,
+                               const unsigned* __restrict__ cstart, const unsigned* __restrict__ rstart,
+                               unsigned* __restrict__ cnt, unsigned* __restrict__ vals) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= HW) return;
     const unsigned key = keys[k];
     if (key < ncells) {
-        const unsigned r = atomicSub(&cnt[key], 1u) - 1u;
-        vals[cstart[key] + r] = (unsigned)k;
+        const unsigned r = key / (unsigned)GW, c = key - r * (unsigned)GW;
+        const unsigned slot = atomicSub(&cnt[key], 1u) - 1u;
+        vals[cell_first(cstart, rstart, GW, (int)r, (int)c) + slot] = (unsigned)k;
     }
 }
 
-// Good pixels outside the grid, in pixel order (one work-group; nothing to do for a
-// sensible map).
-constexpr int OV_THREADS = 1024;
-__global__ __launch_bounds__(OV_THREADS) void k_overflow_order(const unsigned* __restrict__ keys, int HW,
-                                                               unsigned ncells,
-                                                               const unsigned* __restrict__ cstart,
-                                                               unsigned* __restrict__ vals) {
-    constexpr int WAVES = OV_THREADS / 64;
-    __shared__ unsigned wc[WAVES];
-    const unsigned ob = cstart[ncells + KEY_OVERFLOW_OFF], oe = cstart[ncells + KEY_OVERFLOW_OFF + 1];
+// Entry data: fractions of u, white-field and the cell in grid coordinates packed as
+// (row << 16) | column (all 1s outside the grid; both fit 16 bits since detector and
+// reference sides are at most 16384), plus the cell coordinates themselves.
+__device__ inline void entry_data(const float* __restrict__ u, const float* __restrict__ white, unsigned k,
+                                  int HW, int o0, int o1, const GridInfo& gi, int GH, int GW, float4& pd, int2& bs) {
+    const float u0 = u[k], u1 = u[HW + k];
+    const float f0 = floorf(u0), f1 = floorf(u1);
+    const int b0 = cell_coord(u0, o0), b1 = cell_coord(u1, o1);
+    const int r = b0 - gi.g0, c = b1 - gi.g1;
+    const unsigned pack = (r >= 0 && r < GH && c >= 0 && c < GW) ? ((unsigned)r << 16) | (unsigned)c : ~0u;
+    pd = make_float4(u0 - f0, u1 - f1, white[k], __uint_as_float(pack));
+    bs = make_int2(b0, b1);
+}
+
+// One work-group per row of cells (GH of them) and one more for the good pixels outside
+// the grid.  A row's work-group takes its region cells: sorts each cell's entries by
+// pixel index (a cell holds one or two pixels when u maps about one pixel per reference
+// pixel) and writes their data.  The last work-group places the pixels outside the grid
+// in pixel order and writes theirs (nothing to do for a sensible map).
+__global__ __launch_bounds__(256) void k_cell_finish(const float* __restrict__ u, const float* __restrict__ white,
+                                                     const unsigned* __restrict__ keys, int HW, int o0, int o1,
+                                                     const GridInfo* __restrict__ gi_, int GH, int GW,
+                                                     const unsigned* __restrict__ cstart,
+                                                     const unsigned* __restrict__ rstart,
+                                                     const unsigned* __restrict__ kstart,
+                                                     unsigned* __restrict__ vals, float4* __restrict__ pdata,
+                                                     int2* __restrict__ bsort) {
+    __shared__ unsigned wc[4];
+    const GridInfo gi = *gi_;
+    const int r = blockIdx.x;
+    if (r < GH) {
+        int r0, r1, c0, c1;
+        grid_region(gi, GH, GW, r0, r1, c0, c1);
+        if (r < r0 || r > r1) return;
+        for (int c = c0 + (int)threadIdx.x; c <= c1; c += 256) {
+            const unsigned b = cell_first(cstart, rstart, GW, r, c);
+            const unsigned n = cell_first(cstart, rstart, GW, r, c + 1) - b;
+            unsigned* v = vals + b;
+            for (unsigned i = 1; i < n; ++i) {   // insertion sort of a few entries
+                const unsigned x = v[i];
+                unsigned j = i;
+                while (j > 0 && v[j - 1] > x) {
+                    v[j] = v[j - 1];
+                    --j;
+                }
+                v[j] = x;
+            }
+            for (unsigned i = 0; i < n; ++i) entry_data(u, white, v[i], HW, o0, o1, gi, GH, GW, pdata[b + i], bsort[b + i]);
+        }
+        return;
+    }
+    const unsigned ob = kstart[0], oe = kstart[1];
     if (oe == ob) return;
+    const unsigned ncells = (unsigned)GH * (unsigned)GW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned base = ob;
-    for (int k0 = 0; k0 < HW; k0 += OV_THREADS) {
+    for (int k0 = 0; k0 < HW; k0 += 256) {
         const int k = k0 + threadIdx.x;
         const bool f = k < HW && keys[k] == ncells + KEY_OVERFLOW_OFF;
         const unsigned long long m = __ballot(f);
         if (lane == 0) wc[wave] = (unsigned)__popcll(m);
         __syncthreads();
         unsigned before = 0, total = 0;
-        for (int w = 0; w < WAVES; ++w) {
+        for (int w = 0; w < 4; ++w) {
             before += w < wave ? wc[w] : 0u;
             total += wc[w];
         }
-        if (f) vals[base + before + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (unsigned)k;
+        if (f) {
+            const unsigned e = base + before + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            vals[e] = (unsigned)k;
+            entry_data(u, white, (unsigned)k, HW, o0, o1, gi, GH, GW, pdata[e], bsort[e]);
+        }
         base += total;
         __syncthreads();
     }
-}
-
-// Sorts every grid cell's entries by pixel index (shell sort; a cell holds one or two
-// pixels when u maps about one pixel per reference pixel).
-__global__ void k_cell_order(const unsigned* __restrict__ cstart, unsigned ncells, unsigned* __restrict__ vals) {
-    const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    const unsigned b = cstart[c], n = cstart[c + 1] - b;
-    if (n < 2) return;
-    unsigned* v = vals + b;
-    unsigned gap = 1;
-    while (gap * 3 + 1 < n) gap = gap * 3 + 1;
-    for (; gap > 0; gap /= 3) {
-        for (unsigned i = gap; i < n; ++i) {
-            const unsigned x = v[i];
-            unsigned j = i;
-            while (j >= gap && v[j - gap] > x) {
-                v[j] = v[j - gap];
-                j -= gap;
-            }
-            v[j] = x;
-        }
-    }
-}
-
-// Per sorted entry: fractions of u, white-field and the cell in grid coordinates packed
-// as (row << 16) | column (all 1s outside the grid; both fit 16 bits since detector and
-// reference sides are at most 16384), plus the cell coordinates themselves.
-__global__ void k_pixel_data(const float* __restrict__ u, const float* __restrict__ white,
-                             const unsigned* __restrict__ vals, int HW, const unsigned* __restrict__ n_good,
-                             int o0, int o1, const GridInfo* __restrict__ gi, int GH, int GW,
-                             float4* __restrict__ pdata, int2* __restrict__ bsort) {
-    const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= *n_good) return;
-    const unsigned k = vals[e];
-    const float u0 = u[k], u1 = u[HW + k];
-    const float f0 = floorf(u0), f1 = floorf(u1);
-    const int b0 = cell_coord(u0, o0), b1 = cell_coord(u1, o1);
-    const int r = b0 - gi->g0, c = b1 - gi->g1;
-    const unsigned pack = (r >= 0 && r < GH && c >= 0 && c < GW) ? ((unsigned)r << 16) | (unsigned)c : ~0u;
-    pdata[e] = make_float4(u0 - f0, u1 - f1, white[k], __uint_as_float(pack));
-    bsort[e] = make_int2(b0, b1);
 }
 
 // Bilinear weight that reference coordinate p receives from a point whose position
@@ -286,12 +399,13 @@ __device__ inline float splat_weight(int p, int base, float t) {
 
 struct GatherArgs {
     const uint16_t* frames;
-    const uint16_t* fsort;    // frames permuted into sorted-entry order: [N][HW]
     const float* dx;
     const float* u;           // error mode: map for the lookups of eps
     const float* refv_in;     // error mode: reference for the lookups
     const float* s2;          // error mode: sigma^2
-    const unsigned* cstart;
+    const unsigned* cstart;   // in-row first entries of the cells ([GH][GW + 1])
+    const unsigned* rstart;   // first entry of every row of cells
+    const unsigned* kstart;   // first entries of the pixels outside the grid, of the bad ones
     const float4* pdata;
     const int2* bsort;
     const unsigned* pidx;     // pixel index of each sorted entry
@@ -304,26 +418,6 @@ struct GatherArgs {
     float* refv_out;          // reference mode: ref with NaN for invalid (may be null)
 };
 
-// fsort[n][e] = frames[n][vals[e]]: a frame value of a sorted entry is then read at the
-// entry's own index, not through its pixel index.
-// One thread per entry and a group of SF_FRAMES frames (grid y): the pixel index is read
-// once per group.
-constexpr int SF_FRAMES = 16;
-__global__ void k_sort_frames(const uint16_t* __restrict__ frames, const unsigned* __restrict__ vals,
-                              int HW, int N, const unsigned* __restrict__ n_good, uint16_t* __restrict__ fsort) {
-    const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= *n_good) return;
-    const size_t k = vals[e];
-    const int n0 = blockIdx.y * SF_FRAMES, n1 = min(N, n0 + SF_FRAMES);
-    uint16_t v[SF_FRAMES];
-#pragma unroll
-    for (int t = 0; t < SF_FRAMES; ++t)
-        if (n0 + t < n1) v[t] = frames[(size_t)(n0 + t) * HW + k];
-#pragma unroll
-    for (int t = 0; t < SF_FRAMES; ++t)
-        if (n0 + t < n1) fsort[(size_t)(n0 + t) * HW + e] = v[t];
-}
-
 // Contribution of sorted entry e in frame n to reference pixel (p0, p1): value and weight.
 template <int MODE>
 __device__ inline void gather_entry(const GatherArgs& a, unsigned e, int n, size_t HW, int p0, int p1,
@@ -334,13 +428,13 @@ __device__ inline void gather_entry(const GatherArgs& a, unsigned e, int n, size
     const float w1 = splat_weight(p1, b.y - s1, pd.y - fd1);
     const float w = w0 * w1;
     if (w == 0.f) return;
-    const float I = (float)a.fsort[(size_t)n * HW + e];
+    const unsigned k = a.pidx[e];
+    const float I = (float)a.frames[(size_t)n * HW + k];
     if (MODE == 0) {
         const float wi = w * pd.z;
         part = fmaf(wi, I, part);
         dpart += (double)wi * (double)pd.z;
     } else {
-        const unsigned k = a.pidx[e];
         const float u0 = a.u[k], u1 = a.u[HW + k];
         const float f0 = floorf(u0), f1 = floorf(u1);
         const float t0 = (u0 - f0) - fd0, t1 = (u1 - f1) - fd1;
@@ -379,8 +473,9 @@ __global__ __launch_bounds__(256) void k_ref_gather(GatherArgs a) {
     const int p0 = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (p0 >= a.Rs || p1 >= a.Rf) return;
     const GridInfo gi = *a.gi;
-    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
-    const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
+    int gr0, gr1, gc0, gc1;
+    grid_region(gi, a.GH, a.GW, gr0, gr1, gc0, gc1);
+    const unsigned ov_begin = a.kstart[0], ov_end = a.kstart[1];
     const size_t HW = (size_t)a.H * a.W;
     const int F = (a.N + a.nchunks - 1) / a.nchunks;
     const int n_begin = blockIdx.z * F, n_end = min(a.N, n_begin + F);
@@ -401,11 +496,11 @@ __global__ __launch_bounds__(256) void k_ref_gather(GatherArgs a) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int r = q0 + d - 1 - gi.g0;
-            const int c_lo = max(q1 - 1 - gi.g1, 0), c_hi = min(q1 + 1 - gi.g1, a.GW - 1);
+            const int c_lo = max(q1 - 1 - gi.g1, gc0), c_hi = min(q1 + 1 - gi.g1, gc1);
             eb[d] = ee[d] = 0;
-            if (r >= 0 && r < a.GH && c_lo <= c_hi) {
-                eb[d] = a.cstart[(unsigned)r * a.GW + c_lo];
-                ee[d] = a.cstart[(unsigned)r * a.GW + c_hi + 1];
+            if (r >= gr0 && r <= gr1 && c_lo <= c_hi) {
+                eb[d] = cell_first(a.cstart, a.rstart, a.GW, r, c_lo);
+                ee[d] = cell_first(a.cstart, a.rstart, a.GW, r, c_hi + 1);
             }
         }
 #pragma unroll
@@ -554,9 +649,12 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 constexpr int RS_THREADS = 256;
 
 struct SplatArgs {
-    const uint16_t* fsort;
+    const uint16_t* frames;
     const float* dx;
     const unsigned* cstart;
+    const unsigned* rstart;
+    const unsigned* kstart;
+    const unsigned* pidx;     // pixel index of each entry
     const float4* pdata;
     const int2* bsort;
     const GridInfo* gi;
@@ -661,10 +759,19 @@ __device__ inline void splat_any(int i0, int j0, float t0, float t1, double vn, 
 }
 
 // Reference tile of RS_TR x RS_TC pixels, frames of one chunk (grid z).  For each frame
-// whose shifted cell block meets the cells' bounding box, wave w takes the block's cell
-// rows w, w + 4, ... and each row's entries 64 at a time (a row of the block holds about
-// RS_TC + 2 entries when u maps one detector pixel per reference pixel).  Loop bounds
-// and cell-table reads are the same for every lane of a wave (scalar).
+// whose shifted cell block meets the cells' region, wave w takes the block's cell rows
+// w, w + 4, ... and each row's entries 64 at a time (a row of the block holds about
+// RS_TC + 2 entries when u maps one detector pixel per reference pixel): the rows'
+// entry ranges, then the first 64 entries of every row (fractions, white-field, cell,
+// pixel index), then their frame values, read through the pixel index, are loaded
+// together.  Everything a frame needs is read with vector loads and made uniform with
+// lane reads (the frame's shift from a lane holding it, a row's range from the lane
+// that loaded it), never with scalar or LDS reads: those share a wait counter with the
+// LDS additions, so each frame would first wait for the previous frame's additions.
+__device__ inline float lane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
     constexpr int WAVES = RS_THREADS / 64;
     // value and weight sums (separate arrays: a wave's 64-bit additions to neighbouring
@@ -673,7 +780,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
     const int P1 = blockIdx.x * RS_TC, P0 = blockIdx.y * RS_TR;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const unsigned lane = (unsigned)(tid & 63);
+    const int lane = tid & 63;
     for (int i = tid; i < RS_PR * RS_PC; i += RS_THREADS) {
         bn[i] = 0ull;
         bd[i] = 0ull;
@@ -682,52 +789,68 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
     int fn, fd;
     splat_scales(gi.wmax, a.N, gi.n_good, fn, fd);
     const double sn = ldexp(1.0, fn), sd = ldexp(1.0, fd);
-    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
-    const unsigned ov_begin = a.cstart[ncells], ov_end = a.cstart[ncells + 1];
+    int gr0, gr1, gc0, gc1;
+    grid_region(gi, a.GH, a.GW, gr0, gr1, gc0, gc1);
+    const unsigned ov_begin = a.kstart[0], ov_end = a.kstart[1];
     const int F = (a.N + a.nchunks - 1) / a.nchunks;
     const int n_begin = blockIdx.z * F, n_end = min(a.N, n_begin + F);
     __syncthreads();
+    float dl0 = 0.f, dl1 = 0.f;   // shift of frame (group start + lane)
     for (int n = n_begin; n < n_end; ++n) {
-        const float d0 = a.dx[2 * n], d1 = a.dx[2 * n + 1];
+        const int fl = (n - n_begin) & 63;
+        if (fl == 0) {
+            const int m = min(n + lane, n_end - 1);
+            dl0 = a.dx[2 * m];
+            dl1 = a.dx[2 * m + 1];
+        }
+        const float d0 = lane_f(dl0, fl), d1 = lane_f(dl1, fl);
         const float fs0 = floorf(d0), fs1 = floorf(d1);
         const float fd0 = d0 - fs0, fd1 = d1 - fs1;
         const int s0 = (int)fs0, s1 = (int)fs1;
         // cells whose points can reach the tile: rows P0 - 1 + s0 .. P0 + RS_TR + s0 and
-        // columns P1 - 1 + s1 .. P1 + RS_TC + s1, within the grid and the bounding box
-        const int r_lo = max(max(P0 - 1 + s0, gi.bmin0) - gi.g0, 0);
-        const int r_hi = min(min(P0 + RS_TR + s0, gi.bmax0) - gi.g0, a.GH - 1);
-        const int c_lo = max(max(P1 - 1 + s1, gi.bmin1) - gi.g1, 0);
-        const int c_hi = min(min(P1 + RS_TC + s1, gi.bmax1) - gi.g1, a.GW - 1);
+        // columns P1 - 1 + s1 .. P1 + RS_TC + s1, within the cells' region
+        const int r_lo = max(P0 - 1 + s0 - gi.g0, gr0);
+        const int r_hi = min(P0 + RS_TR + s0 - gi.g0, gr1);
+        const int c_lo = max(P1 - 1 + s1 - gi.g1, gc0);
+        const int c_hi = min(P1 + RS_TC + s1 - gi.g1, gc1);
         if (c_lo <= c_hi && r_lo + wave <= r_hi) {
             const int K0 = gi.g0 - s0 - P0, K1 = gi.g1 - s1 - P1;
-            const uint16_t* __restrict__ fr = a.fsort + (size_t)n * a.HW;
-            // the wave's rows: entry ranges first, then the first 64 entries of every row
-            // loaded together, then the rest
+            const uint16_t* __restrict__ fr = a.frames + (size_t)n * a.HW;
+            // lane k < RS_KR loads the entry range of the wave's row k
+            unsigned lb = 0u, le = 0u;
+            {
+                const int r = r_lo + wave + lane * WAVES;
+                if (lane < RS_KR && r <= r_hi) {
+                    const unsigned rs = a.rstart[r];
+                    const unsigned* cr = a.cstart + (size_t)r * (a.GW + 1);
+                    lb = rs + cr[c_lo];
+                    le = rs + cr[c_hi + 1];
+                }
+            }
             unsigned eb[RS_KR], ee[RS_KR];
 #pragma unroll
             for (int k = 0; k < RS_KR; ++k) {
-                const int r = r_lo + wave + k * WAVES;
-                eb[k] = ee[k] = 0u;
-                if (r <= r_hi) {
-                    eb[k] = a.cstart[(unsigned)r * a.GW + c_lo];
-                    ee[k] = a.cstart[(unsigned)r * a.GW + c_hi + 1];
-                }
+                eb[k] = (unsigned)__builtin_amdgcn_readlane((int)lb, k);
+                ee[k] = (unsigned)__builtin_amdgcn_readlane((int)le, k);
             }
             float4 pd[RS_KR];
-            unsigned I[RS_KR];
+            unsigned px[RS_KR];
 #pragma unroll
             for (int k = 0; k < RS_KR; ++k) {
-                const unsigned e = eb[k] + lane;
+                const unsigned e = eb[k] + (unsigned)lane;
                 pd[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                I[k] = 0u;
+                px[k] = 0u;
                 if (e < ee[k]) {
                     pd[k] = a.pdata[e];
-                    I[k] = fr[e];
+                    px[k] = a.pidx[e];
                 }
             }
+            unsigned I[RS_KR];
+#pragma unroll
+            for (int k = 0; k < RS_KR; ++k) I[k] = eb[k] + (unsigned)lane < ee[k] ? (unsigned)fr[px[k]] : 0u;
 #pragma unroll
             for (int k = 0; k < RS_KR; ++k) {
-                if (eb[k] + lane < ee[k]) {
+                if (eb[k] + (unsigned)lane < ee[k]) {
                     const unsigned pk = __float_as_uint(pd[k].w);
                     const double Wd = (double)pd[k].z;
                     splat_block((int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, pd[k].x - fd0, pd[k].y - fd1,
@@ -736,24 +859,24 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
             }
             for (int k = 0; k < RS_KR; ++k) {
                 for (unsigned e0 = eb[k] + 64u; e0 < ee[k]; e0 += 64u) {
-                    const unsigned e = e0 + lane;
+                    const unsigned e = e0 + (unsigned)lane;
                     if (e < ee[k]) {
                         const float4 q = a.pdata[e];
                         const unsigned pk = __float_as_uint(q.w);
                         const double Wd = (double)q.z;
                         splat_block((int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, q.x - fd0, q.y - fd1,
-                                    Wd * (double)fr[e] * sn, Wd * Wd * sd, bn, bd);
+                                    Wd * (double)fr[a.pidx[e]] * sn, Wd * Wd * sd, bn, bd);
                     }
                 }
             }
         }
         // good pixels outside the cell grid (none for a sensible map)
-        for (unsigned e = ov_begin + tid; e < ov_end; e += RS_THREADS) {
-            const float4 po = a.pdata[e];
-            const int2 b = a.bsort[e];
+        for (unsigned eo = ov_begin + tid; eo < ov_end; eo += RS_THREADS) {
+            const float4 po = a.pdata[eo];
+            const int2 b = a.bsort[eo];
             const double Wd = (double)po.z;
             splat_any(b.x - s0 - P0, b.y - s1 - P1, po.x - fd0, po.y - fd1,
-                      Wd * (double)a.fsort[(size_t)n * a.HW + e] * sn, Wd * Wd * sd, bn, bd);
+                      Wd * (double)a.frames[(size_t)n * a.HW + a.pidx[eo]] * sn, Wd * Wd * sd, bn, bd);
         }
     }
     __syncthreads();
@@ -817,12 +940,6 @@ inline unsigned grid_blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1
 
 }  // namespace
 
-size_t scan_temp_bound(size_t n) {
-    // exclusive scan of n counts: look-back state of one or two words per block of at
-    // least 64 items; generous bound, checked against the queried size at run time.
-    return n / 64 * 16 + (size_t)(1 << 20);
-}
-
 int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv, int* sat,
                           int* sat_tmp, float* rowmax, int* fscale, hipStream_t s) {
     const size_t RR = g.RR();
@@ -849,35 +966,25 @@ static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u,
     unsigned* cnt = (unsigned*)(ws + L.ccount);
     unsigned* vals = (unsigned*)(ws + L.vals2);
     unsigned* cstart = (unsigned*)(ws + L.cstart);
+    unsigned* rtot = (unsigned*)(ws + L.rtot);
+    unsigned* rstart = (unsigned*)(ws + L.rstart);
+    unsigned* kstart = (unsigned*)(ws + L.kstart);
     const unsigned nparts = grid_blocks(HW, GRID_THREADS);
     GridPart* gpart = (GridPart*)(ws + L.gpart);
     const unsigned ncells = (unsigned)GH * (unsigned)GW;
-    const size_t nkeys = (size_t)ncells + 3;   // cells, outside the grid, bad, end
     hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, sc.white, HW,
                        g.o0, g.o1, gpart);
     hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(GRID_THREADS), 0, s, gpart, (int)nparts, gi, GH,
                        GW);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(nkeys, 256)), dim3(256), 0, s, cnt, nkeys, 0u);
+    hipLaunchKernelGGL(k_count_clear, dim3(GH), dim3(256), 0, s, gi, GH, GW, cnt);
     hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
                        g.o1, gi, GH, GW, keys, cnt);
-    size_t tb = 0;
-    hipError_t e = rocprim::exclusive_scan(nullptr, tb, cnt, cstart, 0u, nkeys, rocprim::plus<unsigned>(), s);
-    if (e != hipSuccess) return check_hip(e, "cell scan size query");
-    if (tb > L.scan_tmp_bytes) {
-        set_error("internal: cell scan needs %zu scratch bytes, %zu reserved", tb, L.scan_tmp_bytes);
-        return PXST_EWORKSPACE;
-    }
-    e = rocprim::exclusive_scan(ws + L.scan_tmp, tb, cnt, cstart, 0u, nkeys, rocprim::plus<unsigned>(), s);
-    if (e != hipSuccess) return check_hip(e, "cell scan");
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, keys, HW, ncells,
-                       cstart, cnt, vals);
-    hipLaunchKernelGGL(k_overflow_order, dim3(1), dim3(OV_THREADS), 0, s, keys, HW, ncells, cstart, vals);
-    hipLaunchKernelGGL(k_cell_order, dim3(grid_blocks(ncells, 256)), dim3(256), 0, s, cstart, ncells, vals);
-    const unsigned* n_good = cstart + ncells + KEY_INVALID_OFF;   // entries of good pixels
-    hipLaunchKernelGGL(k_pixel_data, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.white, vals,
-                       HW, n_good, g.o0, g.o1, gi, GH, GW, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
-    hipLaunchKernelGGL(k_sort_frames, dim3(grid_blocks(HW, 256), (g.N + SF_FRAMES - 1) / SF_FRAMES), dim3(256), 0,
-                       s, sc.frames, vals, HW, g.N, n_good, (uint16_t*)(ws + L.fsort));
+    hipLaunchKernelGGL(k_scan_rows, dim3(GH), dim3(256), 0, s, gi, GH, GW, cnt, cstart, rtot);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, GH, rtot, cnt, ncells, rstart, kstart);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, keys, HW, GW, ncells,
+                       cstart, rstart, cnt, vals);
+    hipLaunchKernelGGL(k_cell_finish, dim3(GH + 1), dim3(256), 0, s, u, sc.white, keys, HW, g.o0, g.o1, gi,
+                       GH, GW, cstart, rstart, kstart, vals, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
     return check_hip(hipGetLastError(), "inverse map");
 }
 
@@ -885,10 +992,11 @@ static GatherArgs gather_args(const Geom& g, const pxst_scan& sc, const float* u
                               char* ws, const Layout& L) {
     GatherArgs a{};
     a.frames = sc.frames;
-    a.fsort = (const uint16_t*)(ws + L.fsort);
     a.dx = dx;
     a.u = u;
     a.cstart = (const unsigned*)(ws + L.cstart);
+    a.rstart = (const unsigned*)(ws + L.rstart);
+    a.kstart = (const unsigned*)(ws + L.kstart);
     a.pdata = (const float4*)(ws + L.pdata);
     a.bsort = (const int2*)(ws + L.bsort);
     a.pidx = (const unsigned*)(ws + L.vals2);
@@ -933,9 +1041,12 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
         return check_hip(hipGetLastError(), "reference update (float32 gather)");
     }
     SplatArgs a{};
-    a.fsort = (const uint16_t*)(ws + L.fsort);
+    a.frames = sc.frames;
     a.dx = dx;
     a.cstart = (const unsigned*)(ws + L.cstart);
+    a.rstart = (const unsigned*)(ws + L.rstart);
+    a.kstart = (const unsigned*)(ws + L.kstart);
+    a.pidx = (const unsigned*)(ws + L.vals2);
     a.pdata = (const float4*)(ws + L.pdata);
     a.bsort = (const int2*)(ws + L.bsort);
     a.gi = (const GridInfo*)(ws + L.ginfo);
