@@ -338,10 +338,30 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
  *   0 <= iter < n_iter : one main-loop iteration (reference, pixel map,
  *                        translations if enabled, error -> err_hist[iter]);
  *   iter == n_iter     : the final reference update.
- * The stages of all jobs run as shared persistent launches (one per stage and
- * kernel variant) whose work items are (job, tile) pairs, so jobs of different
- * sizes overlap on the device.  A job's results do not depend on which other jobs
- * share the call.  `batch_ws` must hold pxst_batch_workspace_bytes(n_jobs).
+ * Stages shared across jobs: the inverted maps and splat of the reference update
+ * (exact arithmetic, also when rounded to bfloat16; one launch per kernel for the
+ * jobs of each frame-chunking form), the summed-area tables of invalid reference
+ * pixels, the pixel-map search (persistent launches over (job, tile) items per group
+ * of jobs with one window; a job large enough to fill the device runs in launches of
+ * its own), the translation search (one launch per kernel per translation window)
+ * and the error (one launch per kernel per reference-lookup form).  Per job: the
+ * frame variance and search setup at iter == 0, the float32-gather reference
+ * arithmetic, the bfloat16 rounding and the map regularisation.  A job's results do
+ * not depend on which other jobs share the call: each kernel computes a job's items
+ * exactly as in a call of its own.
+ * `batch_ws` (device memory, at least pxst_batch_workspace_bytes(n_jobs) bytes)
+ * receives the argument tables, copied from pinned host staging memory in one
+ * transfer before the first launch.  Calls that share `batch_ws` must be ordered
+ * (same stream, or synchronised); the library serialises the host side and waits
+ * for the previous call's table copy before it reuses the staging memory, which it
+ * allocates (pinned, grown on demand) and keeps until the process ends.
+ * Errors: every job and the workspace sizes are validated, and every table is staged,
+ * before anything is enqueued; a PXST_EINVAL / PXST_EUNSUPPORTED / PXST_EWORKSPACE
+ * return therefore leaves every job untouched.  A PXST_EHIP return (a failed HIP
+ * call) can come after some stages were enqueued: the states of all jobs of the call
+ * are then undefined.
+ * A job with pm_sigma > 0 or pm_integrate = 1 regularises with rocBLAS, which may
+ * allocate device memory on first use per device.
  */
 typedef struct {
     pxst_scan scan;

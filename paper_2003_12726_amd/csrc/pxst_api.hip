@@ -172,9 +172,29 @@ BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const st
     char* d = ar.dev + ar.used;
     std::memcpy(h, args, bytes);
     std::memcpy(h + a_bytes, off.data(), off.size() * sizeof(int));
-    hipMemcpyAsync(d, h, a_bytes + o_bytes, hipMemcpyHostToDevice, ar.stream);
     ar.used += a_bytes + o_bytes;
     return BatchUpload{d, (const int*)(d + a_bytes)};
+}
+
+const void* stage_raw(BatchArena& ar, const void* args, size_t bytes) {
+    const size_t a_bytes = align256(bytes);
+    if (ar.overflow || ar.used + a_bytes > ar.cap) {
+        ar.overflow = true;
+        return nullptr;
+    }
+    std::memcpy(ar.host + ar.used, args, bytes);
+    const void* d = ar.dev + ar.used;
+    ar.used += a_bytes;
+    return d;
+}
+
+int flush_tables(BatchArena& ar) {
+    hipError_t e = hipSuccess;
+    if (ar.used > ar.flushed)
+        e = hipMemcpyAsync(ar.dev + ar.flushed, ar.host + ar.flushed, ar.used - ar.flushed,
+                           hipMemcpyHostToDevice, ar.stream);
+    ar.flushed = ar.used;
+    return check_hip(e, "argument table copy");
 }
 
 // --------------------------------------------------------------------------- layout
@@ -794,8 +814,13 @@ size_t pxst_batch_workspace_bytes(int32_t n_jobs) {
         set_error("n_jobs must be >= 0");
         return 0;
     }
-    // argument tables: one classification table plus three per window group
-    return (size_t)(n_jobs + 1) * 4 * (align256(sizeof(PmJobDesc) * 4) + 1024) + 65536;
+    // argument tables of the batched stages: the pixel-map search's, and one table per
+    // group of jobs (at most n_jobs groups) for the inverted maps, the splat, the
+    // summed-area tables, the translation search and the error, each rounded up to 256
+    // bytes
+    const size_t n = (size_t)n_jobs;
+    const size_t per = sizeof(MapArgs) + sizeof(SplatArgs) + sizeof(SatArgs) + sizeof(TrArgs) + sizeof(ErrArgs);
+    return pixel_map_batch_table_bytes(n_jobs) + n * per + 5 * n * 256 + 4096;
 }
 
 int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, size_t batch_ws_bytes,
@@ -860,6 +885,7 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         Layout L;
         char* w;
         float* refv;
+        bool iterates;
     };
     std::vector<JobState> st(n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
@@ -867,28 +893,43 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         st[j].L = make_layout(st[j].g, tr_ct_of(&jobs[j].opts), jobs[j].opts.pm_integrate != 0);
         st[j].w = (char*)jobs[j].ws;
         st[j].refv = (float*)(st[j].w + st[j].L.refv);
+        st[j].iterates = jobs[j].iter < jobs[j].opts.n_iter;
     }
-    int rc = PXST_OK;
-    // (i) reference update of every job; variance once per job
-    for (int j = 0; j < n_jobs && !rc; ++j) {
+
+    // ---- every argument table, staged on the host before anything is enqueued
+    // (1) reference update (exact arithmetic, stored as float32 or rounded to bfloat16):
+    // one group per frame-chunking form; the float32-gather arithmetic runs per job
+    struct RefGroup {
+        std::vector<MapArgs> m;
+        std::vector<SplatArgs> sp;
+        const MapArgs* dm = nullptr;
+        const SplatArgs* ds = nullptr;
+    };
+    RefGroup rg[2];
+    for (int j = 0; j < n_jobs; ++j) {
         const pxst_job& J = jobs[j];
-        if (J.iter == 0) rc = launch_sigma2(st[j].g, J.scan, (float*)(st[j].w + st[j].L.s2), stream);
-        if (!rc && J.iter == 0 && J.opts.n_iter > 0)
-            rc = launch_pm_setup(st[j].g, J.scan, st[j].w, st[j].L, stream);
-        if (!rc)
-            rc = launch_update_reference(st[j].g, J.scan, J.u, J.dx, J.ref, J.wsum, st[j].refv, st[j].w,
-                                         st[j].L, stream, J.opts.ref_mode);
-        if (!rc && J.iter < J.opts.n_iter)
-            rc = launch_prep_reference(st[j].g, nullptr, nullptr, st[j].refv, (int*)(st[j].w + st[j].L.sat),
-                                       (int*)(st[j].w + st[j].L.sat_tmp),
-                                       (float*)(st[j].w + st[j].L.rowmax),
-                                       (int*)(st[j].w + st[j].L.fscale), stream);
+        if (J.opts.ref_mode == PXST_REF_FP32) continue;
+        const SplatArgs sa = make_splat_args(st[j].g, J.scan, J.dx, J.ref, J.wsum, st[j].refv, st[j].w, st[j].L);
+        RefGroup& G = rg[sa.nchunks > 1 ? 1 : 0];
+        G.m.push_back(make_map_args(st[j].g, J.scan, J.u, st[j].w, st[j].L));
+        G.sp.push_back(sa);
     }
-    // (ii) pixel-map search of the jobs that iterate, batched over jobs
+    for (RefGroup& G : rg)
+        if (!G.m.empty()) {
+            G.dm = (const MapArgs*)stage_raw(ar, G.m.data(), G.m.size() * sizeof(MapArgs));
+            G.ds = (const SplatArgs*)stage_raw(ar, G.sp.data(), G.sp.size() * sizeof(SplatArgs));
+        }
+    // (2) summed-area tables of the jobs that iterate
+    std::vector<SatArgs> sat;
+    for (int j = 0; j < n_jobs; ++j)
+        if (st[j].iterates) sat.push_back(make_sat_args(st[j].g, st[j].refv, st[j].w, st[j].L));
+    const SatArgs* sat_dev =
+        sat.empty() ? nullptr : (const SatArgs*)stage_raw(ar, sat.data(), sat.size() * sizeof(SatArgs));
+    // (3) pixel-map search
     std::vector<PmJobDesc> pm;
-    for (int j = 0; j < n_jobs && !rc; ++j) {
+    for (int j = 0; j < n_jobs; ++j) {
         const pxst_job& J = jobs[j];
-        if (J.iter >= J.opts.n_iter) continue;
+        if (!st[j].iterates) continue;
         PmJobDesc d;
         d.g = st[j].g;
         d.sc = J.scan;
@@ -902,24 +943,78 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws, siz
         d.L = &st[j].L;
         pm.push_back(d);
     }
-    if (!rc) rc = launch_pixel_map_batch(pm.data(), (int)pm.size(), ar, stream);
+    std::shared_ptr<PmBatchImpl> pmb;
+    int rc = stage_pixel_map_batch(pm.data(), (int)pm.size(), ar, pmb);
+    if (rc) return rc;
+    // (4) translation search: one group per window
+    std::vector<std::vector<TrArgs>> trg;
+    for (int j = 0; j < n_jobs; ++j) {
+        const pxst_job& J = jobs[j];
+        if (!st[j].iterates || !J.opts.update_dx) continue;
+        const TrArgs t = make_tr_args(st[j].g, J.scan, st[j].refv, J.u, J.dx, J.opts.tr, J.dx, nullptr, nullptr,
+                                      st[j].w, st[j].L);
+        size_t k = 0;
+        while (k < trg.size() && (trg[k][0].tx != t.tx || trg[k][0].ty != t.ty)) ++k;
+        if (k == trg.size()) trg.emplace_back();
+        trg[k].push_back(t);
+    }
+    std::vector<const TrArgs*> trg_dev;
+    for (auto& G : trg) trg_dev.push_back((const TrArgs*)stage_raw(ar, G.data(), G.size() * sizeof(TrArgs)));
+    // (5) error: one group per reference lookup form (pairs of rows or single rows)
+    std::vector<ErrArgs> eg[2];
+    for (int j = 0; j < n_jobs; ++j) {
+        const pxst_job& J = jobs[j];
+        if (!st[j].iterates) continue;
+        double* total = J.err_hist ? J.err_hist + J.iter : (double*)(st[j].w + st[j].L.err_pix) + st[j].g.N;
+        const ErrArgs e = make_err_args(st[j].g, J.scan, st[j].refv, (const float*)(st[j].w + st[j].L.s2), J.u,
+                                        J.dx, nullptr, nullptr, total, st[j].w, st[j].L);
+        eg[(e.Rs >= 2 && e.Rf >= 2) ? 1 : 0].push_back(e);
+    }
+    const ErrArgs* eg_dev[2] = {nullptr, nullptr};
+    for (int k = 0; k < 2; ++k)
+        if (!eg[k].empty()) eg_dev[k] = (const ErrArgs*)stage_raw(ar, eg[k].data(), eg[k].size() * sizeof(ErrArgs));
+    if (ar.overflow) {
+        set_error("batch workspace too small for the argument tables");
+        return PXST_EWORKSPACE;
+    }
+
+    // ---- launches: one copy of all tables, then the stages in order.  Past this point
+    // only a failing HIP call returns early, leaving the jobs' states undefined.
+    rc = flush_tables(ar);
+    if (!rc) rc = check_hip(hipEventRecord(g_batch_done, stream), "event record");
+    // variance and search setup once per job
+    for (int j = 0; j < n_jobs && !rc; ++j) {
+        const pxst_job& J = jobs[j];
+        if (J.iter != 0) continue;
+        rc = launch_sigma2(st[j].g, J.scan, (float*)(st[j].w + st[j].L.s2), stream);
+        if (!rc && J.opts.n_iter > 0) rc = launch_pm_setup(st[j].g, J.scan, st[j].w, st[j].L, stream);
+    }
+    // (i) reference update of every job
+    for (RefGroup& G : rg)
+        if (!rc && !G.m.empty())
+            rc = launch_reference_jobs(G.m.data(), G.sp.data(), (int)G.m.size(), G.dm, G.ds, stream);
+    for (int j = 0; j < n_jobs && !rc; ++j) {
+        const pxst_job& J = jobs[j];
+        if (J.opts.ref_mode == PXST_REF_BF16)
+            rc = launch_round_bf16(st[j].g, J.ref, st[j].refv, stream);
+        else if (J.opts.ref_mode == PXST_REF_FP32)
+            rc = launch_update_reference(st[j].g, J.scan, J.u, J.dx, J.ref, J.wsum, st[j].refv, st[j].w, st[j].L,
+                                         stream, J.opts.ref_mode);
+    }
+    if (!rc && !sat.empty()) rc = launch_sat_jobs(sat.data(), (int)sat.size(), sat_dev, stream);
+    // (ii) pixel-map search of the jobs that iterate
+    if (!rc) rc = run_pixel_map_batch(*pmb, stream);
     // (iii) regularisation of the map, translations and (iv) total error
     for (int j = 0; j < n_jobs && !rc; ++j) {
         const pxst_job& J = jobs[j];
-        if (J.iter >= J.opts.n_iter) continue;
-        if (J.opts.pm_sigma > 0.f || J.opts.pm_integrate)
+        if (st[j].iterates && (J.opts.pm_sigma > 0.f || J.opts.pm_integrate))
             rc = launch_regularise(st[j].g, J.u, J.u, J.opts.pm_sigma, J.opts.pm_integrate, st[j].w, st[j].L,
                                    stream);
-        if (!rc && J.opts.update_dx)
-            rc = launch_translations(st[j].g, J.scan, st[j].refv, J.u, J.dx, J.opts.tr, J.dx, nullptr,
-                                     nullptr, st[j].w, st[j].L, stream);
-        if (!rc)
-            rc = launch_error(st[j].g, J.scan, st[j].refv, (float*)(st[j].w + st[j].L.s2), J.u, J.dx,
-                              nullptr, nullptr,
-                              J.err_hist ? J.err_hist + J.iter : (double*)(st[j].w + st[j].L.err_pix) + st[j].g.N,
-                              st[j].w, st[j].L, stream);
     }
-    hipEventRecord(g_batch_done, stream);
+    for (size_t k = 0; k < trg.size() && !rc; ++k)
+        rc = launch_translations_jobs(trg[k].data(), (int)trg[k].size(), trg_dev[k], stream);
+    for (int k = 0; k < 2 && !rc; ++k)
+        if (!eg[k].empty()) rc = launch_error_jobs(eg[k].data(), (int)eg[k].size(), eg_dev[k], stream);
     return rc;
 }
 

@@ -33,21 +33,6 @@ __global__ void k_sigma2(const uint16_t* __restrict__ frames, const float* __res
     s2[pix] = (S + P) / (float)N;
 }
 
-struct ErrArgs {
-    const uint16_t* frames;
-    const float* white;
-    const uint8_t* mask;
-    const float* refv;
-    const float* s2;
-    const float* u;
-    const float* dx;
-    float* pixel_err;
-    double* part;       // [N][nblk]
-    double* frame_err;  // [N] (workspace copy when the caller passes none)
-    double* frame_out;  // caller's frame errors or null
-    double* total;
-    int N, H, W, Rs, Rf, o0, o1, nblk;
-};
 
 // Lookup of Sec. 4 from four corner values (NaN: invalid or outside the grid).
 __device__ inline float masked_bilinear4(float v00, float v01, float v10, float v11, float fa, float fb) {
@@ -96,9 +81,11 @@ __device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
 // corner inside the grid at its own row and column of the block; otherwise four loads
 // at the corners clamped one by one.
 template <bool PAIRS>
-__global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
+__global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* jobs, ErrArgs one) {
     extern __shared__ double wsum_sh[];   // [N][waves], then the frame table [N]
     constexpr int WAVES = ERR_THREADS / 64;
+    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
+    if ((int)blockIdx.x >= a.nblk) return;
     // per frame: the fractions of its shift and the integer parts (bits of ints)
     float4* ftab = (float4*)(wsum_sh + (size_t)a.N * WAVES);
     for (int n = threadIdx.x; n < a.N; n += ERR_THREADS) {
@@ -215,8 +202,10 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(ErrArgs a) {
 
 // One wave per frame: lanes add the block partials in lane-strided order, a fixed
 // butterfly combines the lanes.
-__global__ __launch_bounds__(64) void k_err_frames(ErrArgs a) {
+__global__ __launch_bounds__(64) void k_err_frames(const ErrArgs* jobs, ErrArgs one) {
+    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
     const int n = blockIdx.x;
+    if (n >= a.N) return;
     double acc = 0.0;
     for (int b = threadIdx.x; b < a.nblk; b += 64) acc += a.part[(size_t)n * a.nblk + b];
     acc = wave_sum<double>(acc);
@@ -227,7 +216,8 @@ __global__ __launch_bounds__(64) void k_err_frames(ErrArgs a) {
 }
 
 // Total: the frame errors added by one wave in the same fixed order.
-__global__ __launch_bounds__(64) void k_err_total(ErrArgs a) {
+__global__ __launch_bounds__(64) void k_err_total(const ErrArgs* jobs, ErrArgs one) {
+    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
     double acc = 0.0;
     for (int n = threadIdx.x; n < a.N; n += 64) acc += a.frame_err[n];
     acc = wave_sum<double>(acc);
@@ -243,9 +233,9 @@ int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s) 
     return check_hip(hipGetLastError(), "pixel variance");
 }
 
-int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2,
-                 const float* u, const float* dx, float* pixel_err, double* frame_err,
-                 double* total, char* ws, const Layout& L, hipStream_t s) {
+ErrArgs make_err_args(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2, const float* u,
+                      const float* dx, float* pixel_err, double* frame_err, double* total, char* ws,
+                      const Layout& L) {
     ErrArgs a{};
     a.frames = sc.frames;
     a.white = sc.white;
@@ -262,30 +252,62 @@ int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const fl
     a.Rf = g.Rf;
     a.o0 = g.o0;
     a.o1 = g.o1;
-    const size_t per_block = (size_t)ERR_THREADS;
-    a.nblk = (int)((g.HW() + per_block - 1) / per_block);
+    a.nblk = (int)((g.HW() + ERR_THREADS - 1) / ERR_THREADS);
     a.part = (double*)(ws + L.err_part);
     a.frame_err = (double*)(ws + L.err_pix);
     a.frame_out = frame_err;
     a.total = total;
-    const size_t sh = (size_t)g.N * (ERR_THREADS / 64) * sizeof(double) + (size_t)g.N * sizeof(float4);
+    return a;
+}
+
+// LDS of the pixel pass: per-wave frame sums and the frame table.
+static size_t err_lds(int N) { return (size_t)N * (ERR_THREADS / 64) * sizeof(double) + (size_t)N * sizeof(float4); }
+
+// The three passes for the jobs of `host` (their arguments also in device memory at
+// `dev`, or one job passed by value when dev is null).  Every job's grid is its own;
+// the launch covers the largest and blocks past a job's grid return at once.
+int launch_error_jobs(const ErrArgs* host, int n, const ErrArgs* dev, hipStream_t s) {
+    int nblk = 1, nf = 1, maxN = 1;
+    bool pairs = true;
+    for (int j = 0; j < n; ++j) {
+        nblk = std::max(nblk, host[j].nblk);
+        nf = std::max(nf, host[j].N);
+        maxN = std::max(maxN, host[j].N);
+        pairs = pairs && host[j].Rs >= 2 && host[j].Rf >= 2;
+    }
+    for (int j = 0; j < n && dev; ++j)
+        if ((host[j].Rs >= 2 && host[j].Rf >= 2) != pairs) {
+            set_error("batched error pass: jobs differ in the reference lookup form");
+            return PXST_EINVAL;
+        }
+    const size_t sh = err_lds(maxN);
     if (sh > 150 * 1024) {
         set_error("error evaluation supports at most %d frames", (int)(150 * 1024 / 48));
         return PXST_EUNSUPPORTED;
     }
+    const ErrArgs one = dev ? ErrArgs{} : host[0];
+    long long work = 0;
+    for (int j = 0; j < n; ++j) work += (long long)host[j].H * host[j].W * host[j].N;
     profile_begin("err_pixels", s);
     // (up to 1920 frames: 92 KB, above the default limit of dynamic LDS)
-    if (g.Rs >= 2 && g.Rf >= 2) {
+    if (pairs) {
         hipFuncSetAttribute((const void*)k_err_pixels<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_err_pixels<true>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
+        hipLaunchKernelGGL(k_err_pixels<true>, dim3(nblk, 1, n), dim3(ERR_THREADS), sh, s, dev, one);
     } else {
         hipFuncSetAttribute((const void*)k_err_pixels<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_err_pixels<false>, dim3(a.nblk), dim3(ERR_THREADS), sh, s, a);
+        hipLaunchKernelGGL(k_err_pixels<false>, dim3(nblk, 1, n), dim3(ERR_THREADS), sh, s, dev, one);
     }
-    profile_end("err_pixels", s, (long long)g.HW() * g.N, nullptr, 0);
-    hipLaunchKernelGGL(k_err_frames, dim3(g.N), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_err_total, dim3(1), dim3(64), 0, s, a);
+    profile_end("err_pixels", s, work, nullptr, 0);
+    hipLaunchKernelGGL(k_err_frames, dim3(nf, 1, n), dim3(64), 0, s, dev, one);
+    hipLaunchKernelGGL(k_err_total, dim3(1, 1, n), dim3(64), 0, s, dev, one);
     return check_hip(hipGetLastError(), "error evaluation");
+}
+
+int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2,
+                 const float* u, const float* dx, float* pixel_err, double* frame_err,
+                 double* total, char* ws, const Layout& L, hipStream_t s) {
+    const ErrArgs a = make_err_args(g, sc, refv, s2, u, dx, pixel_err, frame_err, total, ws, L);
+    return launch_error_jobs(&a, 1, nullptr, s);
 }
 
 }  // namespace pxst

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 #include "../../include/pxst.h"
@@ -162,6 +163,7 @@ struct BatchArena {
     char* host = nullptr;       // pinned staging memory
     char* dev = nullptr;        // batch workspace
     size_t cap = 0, used = 0;
+    size_t flushed = 0;         // bytes already copied to the device
     hipStream_t stream = nullptr;
     bool overflow = false;
 };
@@ -169,8 +171,13 @@ struct BatchUpload {
     const void* args_dev = nullptr;
     const int* off_dev = nullptr;
 };
-// Copies `bytes` of arguments and the item offsets (njobs + 1 ints) into the arena.
+// Places `bytes` of arguments and the item offsets (njobs + 1 ints) in the staging
+// memory and returns where they will be on the device; flush_tables copies everything
+// staged since the last flush in one transfer, before the launches that read it.
 BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const std::vector<int>& off);
+// As stage_table, without offsets; returns the device address (null on overflow).
+const void* stage_raw(BatchArena& ar, const void* args, size_t bytes);
+int flush_tables(BatchArena& ar);
 // Persistent work-groups of a batched launch.
 constexpr int PERSISTENT_GROUPS = 256 * 4;
 
@@ -191,8 +198,65 @@ struct PmJobDesc {
 // ------------------------------------------------------------------------ kernel entry
 // Each returns PXST_OK or a negative code (and sets the message).
 
-// Reference preparation for lookups: refv = ref where wsum > 0, else NaN; and (when
-// `sat` is non-null) the summed-area table of invalid reference pixels.
+// Arguments of the kernels that build a job's inverted map (cell sort of the pixels).
+struct MapArgs {
+    const float* u;
+    const uint8_t* mask;
+    const float* white;
+    int HW, o0, o1, GH, GW, nparts;
+    GridInfo* gi;
+    GridPart* gpart;
+    unsigned* keys;
+    unsigned* cnt;
+    unsigned* vals;
+    unsigned* cstart;
+    unsigned* rtot;
+    unsigned* rstart;
+    unsigned* kstart;
+    float4* pdata;
+    int2* bsort;
+};
+// Arguments of the reference splat of one job.
+struct SplatArgs {
+    const uint16_t* frames;
+    const float* dx;
+    const unsigned* cstart;
+    const unsigned* rstart;
+    const unsigned* kstart;
+    const unsigned* pidx;     // pixel index of each entry
+    const float4* pdata;
+    const int2* bsort;
+    const GridInfo* gi;
+    int N, HW, Rs, Rf, GH, GW, nchunks;
+    int tiles_x, tiles_y;     // reference tiles of the splat
+    longlong2* part;   // [nchunks][Rs * Rf] quantised (numerator, weight) sums
+    float* ref;
+    double* wsum;
+    float* refv;
+};
+// Arguments of the summed-area table of invalid reference pixels (and the fixed-point
+// exponent of the matrix-core search) of one job.
+struct SatArgs {
+    const float* refv;
+    int Rs, Rf;
+    int* tmp;
+    int* sat;
+    float* rowmax;
+    int* fscale;
+};
+MapArgs make_map_args(const Geom& g, const pxst_scan& sc, const float* u, char* ws, const Layout& L);
+SplatArgs make_splat_args(const Geom& g, const pxst_scan& sc, const float* dx, float* ref, double* wsum,
+                          float* refv, char* ws, const Layout& L);
+SatArgs make_sat_args(const Geom& g, float* refv, char* ws, const Layout& L);
+// The reference update (exact arithmetic) of n jobs: inverted maps, splat, combine; one
+// launch per kernel covers all of them when the tables are in device memory (dev*
+// non-null), else one job by value.
+int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const MapArgs* dm,
+                          const SplatArgs* ds, hipStream_t s);
+// bfloat16 storage of an exact reference update: ref and refv rounded in place.
+int launch_round_bf16(const Geom& g, float* ref, float* refv, hipStream_t s);
+// The summed-area tables and fixed-point exponents of n jobs.
+int launch_sat_jobs(const SatArgs* h, int n, const SatArgs* d, hipStream_t s);
 // refv = reference with NaN where the weight sum is 0; when sat is given also the
 // summed-area table of invalid pixels and, from the per-row maxima of |refv|, the
 // exponent F of the fixed-point reference used by the matrix-core search.
@@ -218,9 +282,39 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
                      const float* dx, const float* u_in, const pxst_window& win, float* u_out,
                      float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s);
 
-int launch_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, hipStream_t s);
+// Batched pixel-map search in two phases: argument tables staged (host only; copied by
+// flush_tables), then the launches.  Jobs large enough to fill the device are searched
+// in launches of their own.
+struct PmBatchImpl;
+int stage_pixel_map_batch(const PmJobDesc* jobs, int n, BatchArena& ar, std::shared_ptr<PmBatchImpl>& out);
+int run_pixel_map_batch(const PmBatchImpl& b, hipStream_t s);
+// Upper bound of the table bytes stage_pixel_map_batch takes for n jobs.
+size_t pixel_map_batch_table_bytes(int n);
 
 // Translation search.
+// Arguments of the translation search of one job.
+struct TrArgs {
+    const uint16_t* frames;
+    const float* white;
+    const uint8_t* mask;
+    const float* refv;
+    const float* u;
+    const float* dx_in;
+    float* dx_out;
+    float* err_out;
+    int* arg_out;
+    float* part;      // [N][nblk][Ct][3]: error, variance, a positive value when any lookup was valid
+    int4* bbox;       // [nblk]: min / max of floor(u0), min / max of floor(u1) over good pixels
+    int N, H, W, Rs, Rf, o0, o1;
+    int nblk, tiles_x, refine;
+    int tx, ty;       // window radii (the kernels are compiled per window)
+};
+
+TrArgs make_tr_args(const Geom& g, const pxst_scan& sc, const float* refv, const float* u, const float* dx_in,
+                    const pxst_window& win, float* dx_out, float* err_min, int32_t* argmin, char* ws,
+                    const Layout& L);
+// The translation search of n jobs with the same window (device table as for the error).
+int launch_translations_jobs(const TrArgs* host, int n, const TrArgs* dev, hipStream_t s);
 int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
                         const float* dx_in, const pxst_window& win, float* dx_out,
                         float* err_min, int32_t* argmin, char* ws, const Layout& L,
@@ -250,6 +344,29 @@ int launch_defocus_sweep(const Geom& g, const pxst_scan& sc, const float* dx, co
 int launch_sigma2(const Geom& g, const pxst_scan& sc, float* s2, hipStream_t s);
 
 // Figures of merit.
+// Arguments of the error passes of one job.
+struct ErrArgs {
+    const uint16_t* frames;
+    const float* white;
+    const uint8_t* mask;
+    const float* refv;
+    const float* s2;
+    const float* u;
+    const float* dx;
+    float* pixel_err;
+    double* part;       // [N][nblk]
+    double* frame_err;  // [N] (workspace copy when the caller passes none)
+    double* frame_out;  // caller's frame errors or null
+    double* total;
+    int N, H, W, Rs, Rf, o0, o1, nblk;
+};
+
+ErrArgs make_err_args(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2, const float* u,
+                      const float* dx, float* pixel_err, double* frame_err, double* total, char* ws,
+                      const Layout& L);
+// The error passes of n jobs (arguments in host memory and, when dev is non-null, the
+// same table in device memory: then one launch per pass covers all of them).
+int launch_error_jobs(const ErrArgs* host, int n, const ErrArgs* dev, hipStream_t s);
 int launch_error(const Geom& g, const pxst_scan& sc, const float* refv, const float* s2,
                  const float* u, const float* dx, float* pixel_err, double* frame_err,
                  double* total, char* ws, const Layout& L, hipStream_t s);

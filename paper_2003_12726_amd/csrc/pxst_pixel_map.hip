@@ -16,6 +16,8 @@
 #include <algorithm>
 
 #include "pxst_device.hpp"
+#include <memory>
+
 #include "pxst_internal.hpp"
 
 namespace pxst {
@@ -2151,12 +2153,35 @@ int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& 
     return check_hip(hipGetLastError(), "pixel-map setup");
 }
 
-// Batched pixel-map search of several jobs.  Per job: counters reset; then one
-// persistent classification over every tile of every job; then, per group of jobs
-// sharing a window, one persistent launch of each kernel class.  `table` is device
-// memory with room for 3 * n PmArgs and the item offsets.
-int launch_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar, hipStream_t s) {
-    if (n_in <= 0) return PXST_OK;
+// Batched pixel-map search of several jobs, in two phases so that a caller can stage the
+// argument tables of all its batched stages before one copy: staging (host only) and
+// launching.  Per group of jobs sharing a window: counters reset and one persistent
+// classification over every tile of every job, then one persistent launch of each
+// kernel class.
+struct PmGroup {
+    PmPlan pl;
+    int m = 0, grid = 0, max_n = 1, mm_on = 0;
+    std::vector<PmArgs> ga;
+    BatchUpload g, f, e;     // tables: plain, fast-kernel and edge-kernel arguments
+};
+struct PmBatchImpl {
+    std::vector<PmJobDesc> solo;
+    int n = 0, cls_grid = 0;
+    BatchUpload cls;
+    std::vector<PmGroup> groups;
+};
+
+size_t pixel_map_batch_table_bytes(int n) {
+    // classification table and offsets, then at most three tables with offsets per group
+    // (each rounded up to 256 bytes; at most n groups)
+    const size_t P = sizeof(PmArgs);
+    return (size_t)n * P + 256 + (size_t)(n + 1) * 4 + 256 +
+           3 * ((size_t)n * P + (size_t)n * 256 + (size_t)2 * n * 4 + (size_t)n * 256);
+}
+
+int stage_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar,
+                          std::shared_ptr<PmBatchImpl>& out) {
+    auto b = std::make_shared<PmBatchImpl>();
     // A job of at least PM_SOLO_TILES tiles whose workspace holds the operand planes fills
     // the device by itself: it is searched as it would be alone (planes, tile halves,
     // per-XCD work runs), each such job in its own launches; the smaller jobs share the
@@ -2166,114 +2191,106 @@ int launch_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar, h
     for (int j = 0; j < n_in; ++j) {
         const PmJobDesc& d = jobs_in[j];
         const long long tiles = (long long)((d.g.H + TILE - 1) / TILE) * ((d.g.W + TILE - 1) / TILE);
-        if (d.L->planes_on && d.g.Rs >= 2 && d.g.Rf >= 2 && tiles >= PM_SOLO_TILES) {
-            const int rc = launch_pixel_map(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
-                                            nullptr, d.ws, *d.L, s);
-            if (rc) return rc;
-        } else {
+        if (d.L->planes_on && d.g.Rs >= 2 && d.g.Rf >= 2 && tiles >= PM_SOLO_TILES)
+            b->solo.push_back(d);
+        else
             small.push_back(d);
-        }
     }
-    const PmJobDesc* jobs = small.data();
     const int n = (int)small.size();
-    if (n <= 0) return PXST_OK;
-    const int persistent_groups = PERSISTENT_GROUPS;
-    // argument table: [fast args n][edge args n][plain args n]; offsets per launch
-    std::vector<PmArgs> base(n);
-    for (int j = 0; j < n; ++j) {
-        const PmJobDesc& d = jobs[j];
-        base[j] = make_pm_args(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
-                               nullptr, d.ws, *d.L, false);
-    }
-    // classification of all jobs in one launch
-    {
+    b->n = n;
+    if (n > 0) {
+        std::vector<PmArgs> base(n);
+        for (int j = 0; j < n; ++j) {
+            const PmJobDesc& d = small[j];
+            base[j] = make_pm_args(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
+                                   nullptr, d.ws, *d.L, false);
+        }
         std::vector<int> off(n + 1, 0);
         for (int j = 0; j < n; ++j) off[j + 1] = off[j] + base[j].ntiles;
-        const BatchUpload up = stage_table(ar, base.data(), n * sizeof(PmArgs), off);
-        if (!ar.overflow) {
-            hipLaunchKernelGGL(k_classify_batch, dim3(std::min(off[n], 256 * 16)), dim3(64), 0, s,
-                               (const PmArgs*)up.args_dev, up.off_dev, n);
-            hipLaunchKernelGGL(k_compact_batch, dim3(n), dim3(COMPACT_THREADS), 0, s,
-                               (const PmArgs*)up.args_dev);
+        b->cls = stage_table(ar, base.data(), n * sizeof(PmArgs), off);
+        b->cls_grid = std::min(off[n], 256 * 16);
+        // groups of jobs with the same window and the same kernel choice (each job's
+        // choice depends on its own sizes only, so a job is classified and searched the
+        // same way alone and in a batch)
+        std::vector<int> done(n, 0);
+        for (int j0 = 0; j0 < n; ++j0) {
+            if (done[j0]) continue;
+            std::vector<int> grp;
+            for (int j = j0; j < n; ++j)
+                if (!done[j] && base[j].NX == base[j0].NX && base[j].NY == base[j0].NY &&
+                    base[j].mm_on == base[j0].mm_on) {
+                    grp.push_back(j);
+                    done[j] = 1;
+                }
+            PmGroup G;
+            G.pl = pm_plan(base[j0].NX, base[j0].NY);
+            G.m = (int)grp.size();
+            G.mm_on = base[j0].mm_on;
+            std::vector<PmArgs> fa(G.m), ea(G.m);
+            G.ga.resize(G.m);
+            std::vector<int> go(G.m + 1, 0);
+            for (int q = 0; q < G.m; ++q) {
+                fa[q] = G.pl.fast_args(base[grp[q]]);
+                ea[q] = G.pl.edge_args(base[grp[q]]);
+                G.ga[q] = base[grp[q]];
+                go[q + 1] = go[q] + base[grp[q]].ntiles;
+                G.max_n = std::max(G.max_n, base[grp[q]].N);
+            }
+            G.grid = std::min(go[G.m], PERSISTENT_GROUPS);
+            G.g = stage_table(ar, G.ga.data(), G.m * sizeof(PmArgs), go);
+            if (!(G.mm_on & 1)) G.f = stage_table(ar, fa.data(), G.m * sizeof(PmArgs), go);
+            G.e = stage_table(ar, ea.data(), G.m * sizeof(PmArgs), go);
+            b->groups.push_back(std::move(G));
         }
     }
     if (ar.overflow) {
-        set_error("batch workspace too small");
+        set_error("batch workspace too small for the argument tables");
         return PXST_EWORKSPACE;
     }
+    out = b;
+    return PXST_OK;
+}
+
+int run_pixel_map_batch(const PmBatchImpl& b, hipStream_t s) {
+    for (const PmJobDesc& d : b.solo) {
+        const int rc = launch_pixel_map(d.g, d.sc, d.refv, d.sat, d.dx, d.u_in, d.win, d.u_out, nullptr,
+                                        nullptr, d.ws, *d.L, s);
+        if (rc) return rc;
+    }
+    if (b.n <= 0) return PXST_OK;
+    hipLaunchKernelGGL(k_classify_batch, dim3(b.cls_grid), dim3(64), 0, s, (const PmArgs*)b.cls.args_dev,
+                       b.cls.off_dev, b.n);
+    hipLaunchKernelGGL(k_compact_batch, dim3(b.n), dim3(COMPACT_THREADS), 0, s,
+                       (const PmArgs*)b.cls.args_dev);
     int rc = check_hip(hipGetLastError(), "batched pixel-map classification");
     if (rc) return rc;
-    // groups of jobs with the same window and the same kernel choice (each job's choice
-    // depends on its own sizes only, so a job is classified and searched the same way
-    // alone and in a batch)
-    std::vector<int> done(n, 0);
-    for (int j0 = 0; j0 < n; ++j0) {
-        if (done[j0]) continue;
-        std::vector<int> grp;
-        for (int j = j0; j < n; ++j)
-            if (!done[j] && base[j].NX == base[j0].NX && base[j].NY == base[j0].NY &&
-                base[j].mm_on == base[j0].mm_on) {
-                grp.push_back(j);
-                done[j] = 1;
-            }
-        const PmPlan pl = pm_plan(base[j0].NX, base[j0].NY);
-        const int m = (int)grp.size();
-        std::vector<PmArgs> fa(m), ea(m), ga(m);
-        std::vector<int> off(m + 1, 0);
-        for (int q = 0; q < m; ++q) {
-            fa[q] = pl.fast_args(base[grp[q]]);
-            ea[q] = pl.edge_args(base[grp[q]]);
-            ga[q] = base[grp[q]];
-            off[q + 1] = off[q] + base[grp[q]].ntiles;
-        }
-        const int grid = std::min(off[m], persistent_groups);
-        int max_n = 1;
-        for (int q = 0; q < m; ++q) max_n = std::max(max_n, base[grp[q]].N);
-        if (base[j0].mm_on & 1) {
-            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
-            if (ar.overflow) break;
+    for (const PmGroup& G : b.groups) {
+        const PmArgs* gd = (const PmArgs*)G.g.args_dev;
+        if (G.mm_on & 1) {
             profile_begin("pm_fast", s);
-            rc = launch_mma(ga.data(), m, (const PmArgs*)up.args_dev, up.off_dev, grid, false, s);
+            rc = launch_mma(G.ga.data(), G.m, gd, G.g.off_dev, G.grid, false, s);
             profile_end("pm_fast", s, 0, nullptr, 0);
             if (rc) return rc;
         } else {
-            const BatchUpload up = stage_table(ar, fa.data(), m * sizeof(PmArgs), off);
-            if (ar.overflow) break;
-            const size_t sh = lds_bytes(pl.lf, max_n);
-            hipFuncSetAttribute((const void*)pl.fs.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+            const size_t sh = lds_bytes(G.pl.lf, G.max_n);
+            hipFuncSetAttribute((const void*)G.pl.fs.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)sh);
             profile_begin("pm_fast", s);
-            hipLaunchKernelGGL(pl.fs.batch, dim3(grid), dim3(pl.lf.waves * 64), sh, s,
-                               (const PmArgs*)up.args_dev, up.off_dev, m);
+            hipLaunchKernelGGL(G.pl.fs.batch, dim3(G.grid), dim3(G.pl.lf.waves * 64), sh, s,
+                               (const PmArgs*)G.f.args_dev, G.f.off_dev, G.m);
             profile_end("pm_fast", s, 0, nullptr, 0);
         }
-        if (base[j0].mm_on & 2) {
-            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
-            if (ar.overflow) break;
+        if (G.mm_on & 2) {
             profile_begin("pm_edge_mma", s);
-            rc = launch_mma(ga.data(), m, (const PmArgs*)up.args_dev, up.off_dev, grid, true, s);
+            rc = launch_mma(G.ga.data(), G.m, gd, G.g.off_dev, G.grid, true, s);
             profile_end("pm_edge_mma", s, 0, nullptr, 0);
             if (rc) return rc;
         }
-        {
-            const BatchUpload up = stage_table(ar, ea.data(), m * sizeof(PmArgs), off);
-            if (ar.overflow) break;
-            const size_t sh = lds_bytes(pl.le, max_n);
-            hipFuncSetAttribute((const void*)pl.es.batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sh);
-            hipLaunchKernelGGL(pl.es.batch, dim3(grid), dim3(pl.le.waves * 64), sh, s,
-                               (const PmArgs*)up.args_dev, up.off_dev, m);
-        }
-        {
-            const BatchUpload up = stage_table(ar, ga.data(), m * sizeof(PmArgs), off);
-            if (ar.overflow) break;
-            hipLaunchKernelGGL(k_pm_generic_batch, dim3(grid), dim3(256), 0, s,
-                               (const PmArgs*)up.args_dev, up.off_dev, m);
-        }
-        if (ar.overflow) {
-            set_error("batch workspace too small");
-            return PXST_EWORKSPACE;
-        }
+        const size_t sh = lds_bytes(G.pl.le, G.max_n);
+        hipFuncSetAttribute((const void*)G.pl.es.batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        hipLaunchKernelGGL(G.pl.es.batch, dim3(G.grid), dim3(G.pl.le.waves * 64), sh, s,
+                           (const PmArgs*)G.e.args_dev, G.e.off_dev, G.m);
+        hipLaunchKernelGGL(k_pm_generic_batch, dim3(G.grid), dim3(256), 0, s, gd, G.g.off_dev, G.m);
         rc = check_hip(hipGetLastError(), "batched pixel-map search");
         if (rc) return rc;
     }

@@ -34,10 +34,14 @@ __device__ inline int cell_coord(float u, int o) {
     return (int)f - o;
 }
 
-__global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restrict__ u,
-                                                            const uint8_t* __restrict__ mask,
-                                                            const float* __restrict__ white, int HW,
-                                                            int o0, int o1, GridPart* __restrict__ part) {
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const MapArgs* jobs, MapArgs one) {
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    if ((int)blockIdx.x >= a.nparts) return;
+    const float* __restrict__ u = a.u;
+    const uint8_t* __restrict__ mask = a.mask;
+    const float* __restrict__ white = a.white;
+    const int HW = a.HW, o0 = a.o0, o1 = a.o1;
+    GridPart* __restrict__ part = a.gpart;
     __shared__ GridPart wp[GRID_THREADS / 64];
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const bool good = k < HW && mask[k] != 0;
@@ -80,9 +84,11 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const float* __restr
 // Reduces the partials and sets the grid origin: the bounding box (plus a one-cell
 // margin) when it fits the capacity, else a window of the capacity centred on the
 // mean cell.
-__global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const GridPart* __restrict__ part,
-                                                              int nparts, GridInfo* gi, int GH,
-                                                              int GW) {
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const MapArgs* jobs, MapArgs one) {
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const GridPart* __restrict__ part = a.gpart;
+    const int nparts = a.nparts, GH = a.GH, GW = a.GW;
+    GridInfo* gi = a.gi;
     __shared__ GridPart wp[GRID_THREADS / 64];
     GridPart t;
     t.bmin0 = t.bmin1 = INT_MAX;
@@ -164,9 +170,12 @@ __device__ inline void grid_region(const GridInfo& gi, int GH, int GW, int& r0, 
 
 // One work-group per row of cells: clears the counts of the region's cells (and the two
 // other keys' counts).
-__global__ __launch_bounds__(256) void k_count_clear(const GridInfo* __restrict__ gi_, int GH, int GW,
-                                                     unsigned* __restrict__ cnt) {
-    const GridInfo gi = *gi_;
+__global__ __launch_bounds__(256) void k_count_clear(const MapArgs* jobs, MapArgs one) {
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const int GH = a.GH, GW = a.GW;
+    unsigned* __restrict__ cnt = a.cnt;
+    if ((int)blockIdx.x >= GH) return;
+    const GridInfo gi = *a.gi;
     int r0, r1, c0, c1;
     grid_region(gi, GH, GW, r0, r1, c0, c1);
     const int r = blockIdx.x;
@@ -175,10 +184,15 @@ __global__ __launch_bounds__(256) void k_count_clear(const GridInfo* __restrict_
     for (int c = c0 + (int)threadIdx.x; c <= c1; c += 256) cnt[(size_t)r * GW + c] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_keys(const float* __restrict__ u, const uint8_t* __restrict__ mask,
-                                              int HW, int o0, int o1, const GridInfo* __restrict__ gi,
-                                              int GH, int GW, unsigned* __restrict__ keys,
-                                              unsigned* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void k_keys(const MapArgs* jobs, MapArgs one) {
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const float* __restrict__ u = a.u;
+    const uint8_t* __restrict__ mask = a.mask;
+    const int HW = a.HW, o0 = a.o0, o1 = a.o1, GH = a.GH, GW = a.GW;
+    const GridInfo* __restrict__ gi = a.gi;
+    unsigned* __restrict__ keys = a.keys;
+    unsigned* __restrict__ cnt = a.cnt;
+    if ((int)(blockIdx.x * blockDim.x) >= HW) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned ncells = (unsigned)GH * (unsigned)GW;
     unsigned key = ncells + KEY_INVALID_OFF;
@@ -232,11 +246,15 @@ __device__ inline unsigned block_excl_scan(unsigned v, unsigned* tmp4, unsigned&
 
 // One work-group per row of cells: in-row exclusive scan of the region's counts, with
 // the row's end after its last cell, and the row's total (0 outside the region).
-__global__ __launch_bounds__(256) void k_scan_rows(const GridInfo* __restrict__ gi_, int GH, int GW,
-                                                   const unsigned* __restrict__ cnt, unsigned* __restrict__ cstart,
-                                                   unsigned* __restrict__ rtot) {
+__global__ __launch_bounds__(256) void k_scan_rows(const MapArgs* jobs, MapArgs one) {
     __shared__ unsigned tmp4[4];
-    const GridInfo gi = *gi_;
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const int GH = a.GH, GW = a.GW;
+    const unsigned* __restrict__ cnt = a.cnt;
+    unsigned* __restrict__ cstart = a.cstart;
+    unsigned* __restrict__ rtot = a.rtot;
+    if ((int)blockIdx.x >= GH) return;
+    const GridInfo gi = *a.gi;
     int r0, r1, c0, c1;
     grid_region(gi, GH, GW, r0, r1, c0, c1);
     const int r = blockIdx.x;
@@ -264,10 +282,15 @@ __global__ __launch_bounds__(256) void k_scan_rows(const GridInfo* __restrict__ 
 // One work-group: exclusive scan of the row totals into rstart[0 .. GH] and the starts
 // of the other keys: kstart[0] = first entry outside the grid, kstart[1] = number of
 // good pixels, kstart[2] = end.
-__global__ __launch_bounds__(256) void k_scan_top(int GH, const unsigned* __restrict__ rtot,
-                                                  const unsigned* __restrict__ cnt, unsigned ncells,
-                                                  unsigned* __restrict__ rstart, unsigned* __restrict__ kstart) {
+__global__ __launch_bounds__(256) void k_scan_top(const MapArgs* jobs, MapArgs one) {
     __shared__ unsigned tmp4[4];
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const int GH = a.GH;
+    const unsigned* __restrict__ rtot = a.rtot;
+    const unsigned* __restrict__ cnt = a.cnt;
+    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
+    unsigned* __restrict__ rstart = a.rstart;
+    unsigned* __restrict__ kstart = a.kstart;
     unsigned run = 0;
     for (int rb = 0; rb < GH; rb += 256) {
         const int r = rb + (int)threadIdx.x;
@@ -293,9 +316,15 @@ __device__ inline unsigned cell_first(const unsigned* __restrict__ cstart, const
 
 // Places the pixels of grid cells: slot = remaining count - 1 (the order inside a cell
 // is fixed afterwards); the counts end at 0.
-__global__ void k_cell_scatter(const unsigned* __restrict__ keys, int HW, int GW, unsigned ncells,
-                               const unsigned* __restrict__ cstart, const unsigned* __restrict__ rstart,
-                               unsigned* __restrict__ cnt, unsigned* __restrict__ vals) {
+__global__ void k_cell_scatter(const MapArgs* jobs, MapArgs one) {
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const unsigned* __restrict__ keys = a.keys;
+    const int HW = a.HW, GW = a.GW;
+    const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
+    const unsigned* __restrict__ cstart = a.cstart;
+    const unsigned* __restrict__ rstart = a.rstart;
+    unsigned* __restrict__ cnt = a.cnt;
+    unsigned* __restrict__ vals = a.vals;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= HW) return;
     const unsigned key = keys[k];
@@ -325,16 +354,21 @@ __device__ inline void entry_data(const float* __restrict__ u, const float* __re
 // pixel index (a cell holds one or two pixels when u maps about one pixel per reference
 // pixel) and writes their data.  The last work-group places the pixels outside the grid
 // in pixel order and writes theirs (nothing to do for a sensible map).
-__global__ __launch_bounds__(256) void k_cell_finish(const float* __restrict__ u, const float* __restrict__ white,
-                                                     const unsigned* __restrict__ keys, int HW, int o0, int o1,
-                                                     const GridInfo* __restrict__ gi_, int GH, int GW,
-                                                     const unsigned* __restrict__ cstart,
-                                                     const unsigned* __restrict__ rstart,
-                                                     const unsigned* __restrict__ kstart,
-                                                     unsigned* __restrict__ vals, float4* __restrict__ pdata,
-                                                     int2* __restrict__ bsort) {
+__global__ __launch_bounds__(256) void k_cell_finish(const MapArgs* jobs, MapArgs one) {
     __shared__ unsigned wc[4];
-    const GridInfo gi = *gi_;
+    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const float* __restrict__ u = a.u;
+    const float* __restrict__ white = a.white;
+    const unsigned* __restrict__ keys = a.keys;
+    const int HW = a.HW, o0 = a.o0, o1 = a.o1, GH = a.GH, GW = a.GW;
+    const unsigned* __restrict__ cstart = a.cstart;
+    const unsigned* __restrict__ rstart = a.rstart;
+    const unsigned* __restrict__ kstart = a.kstart;
+    unsigned* __restrict__ vals = a.vals;
+    float4* __restrict__ pdata = a.pdata;
+    int2* __restrict__ bsort = a.bsort;
+    if ((int)blockIdx.x > GH) return;
+    const GridInfo gi = *a.gi;
     const int r = blockIdx.x;
     if (r < GH) {
         int r0, r1, c0, c1;
@@ -545,11 +579,16 @@ __global__ void k_prep_refv(const float* __restrict__ ref, const double* __restr
 
 // Inclusive prefix sums of the invalid flags along each reference row, written
 // transposed: tmp[c][r]; rowmax[r] = max |refv| over the valid pixels of row r.
-__global__ __launch_bounds__(256) void k_sat_rows(const float* __restrict__ refv, int Rs, int Rf,
-                                                  int* __restrict__ tmp, float* __restrict__ rowmax) {
+__global__ __launch_bounds__(256) void k_sat_rows(const SatArgs* jobs, SatArgs one) {
     __shared__ int part[256];
     __shared__ float pmax[256 / 64];
+    const SatArgs a = jobs ? jobs[blockIdx.z] : one;
+    const float* __restrict__ refv = a.refv;
+    const int Rs = a.Rs, Rf = a.Rf;
+    int* __restrict__ tmp = a.tmp;
+    float* __restrict__ rowmax = a.fscale ? a.rowmax : nullptr;
     const int r = blockIdx.x;
+    if (r >= Rs) return;
     const int per = (Rf + 255) / 256;
     const int c0 = threadIdx.x * per;
     int s = 0;
@@ -585,9 +624,14 @@ __global__ __launch_bounds__(256) void k_sat_rows(const float* __restrict__ refv
 }
 
 // Column prefix sums of tmp[c][:] into sat[(r+1)][(c+1)] (row 0 and column 0 are 0).
-__global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, int Rs, int Rf,
-                                                  int* __restrict__ sat, const float* __restrict__ rowmax,
-                                                  int* __restrict__ fscale) {
+__global__ __launch_bounds__(256) void k_sat_cols(const SatArgs* jobs, SatArgs one) {
+    const SatArgs a = jobs ? jobs[blockIdx.z] : one;
+    const int* __restrict__ tmp = a.tmp;
+    const int Rs = a.Rs, Rf = a.Rf;
+    int* __restrict__ sat = a.sat;
+    const float* __restrict__ rowmax = a.rowmax;
+    int* __restrict__ fscale = a.fscale;
+    if ((int)blockIdx.x >= Rf) return;
     __shared__ int part[256];
     const int c = blockIdx.x;
     if (c == 0 && fscale) {
@@ -648,22 +692,6 @@ __global__ __launch_bounds__(256) void k_sat_cols(const int* __restrict__ tmp, i
 // second pass adds; the quotient is formed in FP64.
 constexpr int RS_THREADS = 256;
 
-struct SplatArgs {
-    const uint16_t* frames;
-    const float* dx;
-    const unsigned* cstart;
-    const unsigned* rstart;
-    const unsigned* kstart;
-    const unsigned* pidx;     // pixel index of each entry
-    const float4* pdata;
-    const int2* bsort;
-    const GridInfo* gi;
-    int N, HW, Rs, Rf, GH, GW, nchunks;
-    longlong2* part;   // [nchunks][Rs * Rf] quantised (numerator, weight) sums
-    float* ref;
-    double* wsum;
-    float* refv;
-};
 
 // Quantum exponents: |W I| 2^fn < 2^T and W^2 2^fd < 2^T for every term (counts are at
 // most 65535), T = min(43, 62 - bits(N n_good)): a sum of at most N n_good terms stays
@@ -772,12 +800,16 @@ __device__ inline float lane_f(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
+__global__ __launch_bounds__(RS_THREADS) void k_ref_splat(const SplatArgs* jobs, SplatArgs one) {
     constexpr int WAVES = RS_THREADS / 64;
     // value and weight sums (separate arrays: a wave's 64-bit additions to neighbouring
     // pixels then fall on neighbouring 8-byte words)
     __shared__ unsigned long long bn[RS_PR * RS_PC], bd[RS_PR * RS_PC];
-    const int P1 = blockIdx.x * RS_TC, P0 = blockIdx.y * RS_TR;
+    const SplatArgs a = jobs ? jobs[blockIdx.z] : one;
+    // grid: x = tile column, y = tile row + tile rows x frame chunk
+    if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y * a.nchunks) return;
+    const int chunk = (int)blockIdx.y / a.tiles_y, trow = (int)blockIdx.y - chunk * a.tiles_y;
+    const int P1 = blockIdx.x * RS_TC, P0 = trow * RS_TR;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -793,7 +825,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
     grid_region(gi, a.GH, a.GW, gr0, gr1, gc0, gc1);
     const unsigned ov_begin = a.kstart[0], ov_end = a.kstart[1];
     const int F = (a.N + a.nchunks - 1) / a.nchunks;
-    const int n_begin = blockIdx.z * F, n_end = min(a.N, n_begin + F);
+    const int n_begin = chunk * F, n_end = min(a.N, n_begin + F);
     __syncthreads();
     float dl0 = 0.f, dl1 = 0.f;   // shift of frame (group start + lane)
     for (int n = n_begin; n < n_end; ++n) {
@@ -888,7 +920,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(SplatArgs a) {
         const size_t p = (size_t)p0 * a.Rf + p1;
         const int q = (ti + 2) * RS_PC + (tj + 2);
         if (a.nchunks > 1) {
-            a.part[(size_t)blockIdx.z * RR + p] = make_longlong2((long long)bn[q], (long long)bd[q]);
+            a.part[(size_t)chunk * RR + p] = make_longlong2((long long)bn[q], (long long)bd[q]);
         } else {
             const double num = (double)(long long)bn[q] * ldexp(1.0, -fn);
             const double den = (double)(long long)bd[q] * ldexp(1.0, -fd);
@@ -916,7 +948,8 @@ __global__ void k_round_bf16(float* __restrict__ ref, float* __restrict__ refv, 
 }
 
 // Adds the exact chunk partials and writes the reference.
-__global__ void k_ref_splat_combine(SplatArgs a) {
+__global__ void k_ref_splat_combine(const SplatArgs* jobs, SplatArgs one) {
+    const SplatArgs a = jobs ? jobs[blockIdx.z] : one;
     const size_t RR = (size_t)a.Rs * a.Rf;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= RR) return;
@@ -940,6 +973,30 @@ inline unsigned grid_blocks(size_t n, unsigned b) { return (unsigned)((n + b - 1
 
 }  // namespace
 
+SatArgs make_sat_args(const Geom& g, float* refv, char* ws, const Layout& L) {
+    SatArgs a{};
+    a.refv = refv;
+    a.Rs = g.Rs;
+    a.Rf = g.Rf;
+    a.tmp = (int*)(ws + L.sat_tmp);
+    a.sat = (int*)(ws + L.sat);
+    a.rowmax = (float*)(ws + L.rowmax);
+    a.fscale = (int*)(ws + L.fscale);
+    return a;
+}
+
+int launch_sat_jobs(const SatArgs* h, int n, const SatArgs* d, hipStream_t s) {
+    int rs = 1, rf = 1;
+    for (int j = 0; j < n; ++j) {
+        rs = std::max(rs, h[j].Rs);
+        rf = std::max(rf, h[j].Rf);
+    }
+    const SatArgs one = d ? SatArgs{} : h[0];
+    hipLaunchKernelGGL(k_sat_rows, dim3(rs, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_sat_cols, dim3(rf, 1, n), dim3(256), 0, s, d, one);
+    return check_hip(hipGetLastError(), "prepare reference");
+}
+
 int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, float* refv, int* sat,
                           int* sat_tmp, float* rowmax, int* fscale, hipStream_t s) {
     const size_t RR = g.RR();
@@ -947,45 +1004,71 @@ int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, f
         hipLaunchKernelGGL(k_prep_refv, dim3(grid_blocks(RR, 256)), dim3(256), 0, s, ref, wsum,
                            (int)RR, refv);
     if (sat != nullptr) {
-        hipLaunchKernelGGL(k_sat_rows, dim3(g.Rs), dim3(256), 0, s, refv, g.Rs, g.Rf, sat_tmp,
-                           fscale ? rowmax : nullptr);
-        hipLaunchKernelGGL(k_sat_cols, dim3(g.Rf), dim3(256), 0, s, sat_tmp, g.Rs, g.Rf, sat, rowmax,
-                           fscale);
+        SatArgs a{};
+        a.refv = refv;
+        a.Rs = g.Rs;
+        a.Rf = g.Rf;
+        a.tmp = sat_tmp;
+        a.sat = sat;
+        a.rowmax = rowmax;
+        a.fscale = fscale;
+        return launch_sat_jobs(&a, 1, nullptr, s);
     }
     return check_hip(hipGetLastError(), "prepare reference");
 }
 
 // Builds the inverted map (sorted cells) of u; shared by the reference update and
 // the reference-plane error.
+MapArgs make_map_args(const Geom& g, const pxst_scan& sc, const float* u, char* ws, const Layout& L) {
+    MapArgs a{};
+    a.u = u;
+    a.mask = sc.mask;
+    a.white = sc.white;
+    a.HW = (int)g.HW();
+    a.o0 = g.o0;
+    a.o1 = g.o1;
+    a.GH = grid_h(g);
+    a.GW = grid_w(g);
+    a.nparts = (int)grid_blocks(g.HW(), GRID_THREADS);
+    a.gi = (GridInfo*)(ws + L.ginfo);
+    a.gpart = (GridPart*)(ws + L.gpart);
+    a.keys = (unsigned*)(ws + L.keys);
+    a.cnt = (unsigned*)(ws + L.ccount);
+    a.vals = (unsigned*)(ws + L.vals2);
+    a.cstart = (unsigned*)(ws + L.cstart);
+    a.rtot = (unsigned*)(ws + L.rtot);
+    a.rstart = (unsigned*)(ws + L.rstart);
+    a.kstart = (unsigned*)(ws + L.kstart);
+    a.pdata = (float4*)(ws + L.pdata);
+    a.bsort = (int2*)(ws + L.bsort);
+    return a;
+}
+
+// The inverted maps of n jobs (one launch per kernel; blocks past a job's grid return).
+static int launch_maps(const MapArgs* h, int n, const MapArgs* d, hipStream_t s) {
+    int parts = 1, gh = 1, hwb = 1;
+    for (int j = 0; j < n; ++j) {
+        parts = std::max(parts, h[j].nparts);
+        gh = std::max(gh, h[j].GH);
+        hwb = std::max(hwb, (int)grid_blocks((size_t)h[j].HW, 256));
+    }
+    const MapArgs one = d ? MapArgs{} : h[0];
+    hipLaunchKernelGGL(k_grid_bbox, dim3(parts, 1, n), dim3(GRID_THREADS), 0, s, d, one);
+    hipLaunchKernelGGL(k_grid_origin, dim3(1, 1, n), dim3(GRID_THREADS), 0, s, d, one);
+    hipLaunchKernelGGL(k_count_clear, dim3(gh, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_keys, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_scan_rows, dim3(gh, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_scan_top, dim3(1, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
+    hipLaunchKernelGGL(k_cell_finish, dim3(gh + 1, 1, n), dim3(256), 0, s, d, one);
+    return check_hip(hipGetLastError(), "inverse map");
+}
+
+// The reference-plane error and the float32 update use the same map.
 static int build_inverse_map(const Geom& g, const pxst_scan& sc, const float* u, char* ws,
                              const Layout& L, hipStream_t s) {
-    const int HW = (int)g.HW();
-    const int GH = grid_h(g), GW = grid_w(g);
-    GridInfo* gi = (GridInfo*)(ws + L.ginfo);
-    unsigned* keys = (unsigned*)(ws + L.keys);
-    unsigned* cnt = (unsigned*)(ws + L.ccount);
-    unsigned* vals = (unsigned*)(ws + L.vals2);
-    unsigned* cstart = (unsigned*)(ws + L.cstart);
-    unsigned* rtot = (unsigned*)(ws + L.rtot);
-    unsigned* rstart = (unsigned*)(ws + L.rstart);
-    unsigned* kstart = (unsigned*)(ws + L.kstart);
-    const unsigned nparts = grid_blocks(HW, GRID_THREADS);
-    GridPart* gpart = (GridPart*)(ws + L.gpart);
-    const unsigned ncells = (unsigned)GH * (unsigned)GW;
-    hipLaunchKernelGGL(k_grid_bbox, dim3(nparts), dim3(GRID_THREADS), 0, s, u, sc.mask, sc.white, HW,
-                       g.o0, g.o1, gpart);
-    hipLaunchKernelGGL(k_grid_origin, dim3(1), dim3(GRID_THREADS), 0, s, gpart, (int)nparts, gi, GH,
-                       GW);
-    hipLaunchKernelGGL(k_count_clear, dim3(GH), dim3(256), 0, s, gi, GH, GW, cnt);
-    hipLaunchKernelGGL(k_keys, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, u, sc.mask, HW, g.o0,
-                       g.o1, gi, GH, GW, keys, cnt);
-    hipLaunchKernelGGL(k_scan_rows, dim3(GH), dim3(256), 0, s, gi, GH, GW, cnt, cstart, rtot);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, GH, rtot, cnt, ncells, rstart, kstart);
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_blocks(HW, 256)), dim3(256), 0, s, keys, HW, GW, ncells,
-                       cstart, rstart, cnt, vals);
-    hipLaunchKernelGGL(k_cell_finish, dim3(GH + 1), dim3(256), 0, s, u, sc.white, keys, HW, g.o0, g.o1, gi,
-                       GH, GW, cstart, rstart, kstart, vals, (float4*)(ws + L.pdata), (int2*)(ws + L.bsort));
-    return check_hip(hipGetLastError(), "inverse map");
+    const MapArgs a = make_map_args(g, sc, u, ws, L);
+    return launch_maps(&a, 1, nullptr, s);
 }
 
 static GatherArgs gather_args(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
@@ -1025,21 +1108,8 @@ static void launch_gather(const GatherArgs& a, int mode, const Geom& g, hipStrea
         hipLaunchKernelGGL(k_ref_combine, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, a, mode);
 }
 
-int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
-                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s, int ref_mode) {
-    int rc = build_inverse_map(g, sc, u, ws, L, s);
-    if (rc) return rc;
-    if (ref_mode == PXST_REF_FP32) {
-        GatherArgs b = gather_args(g, sc, u, dx, ws, L);
-        b.out = ref;
-        b.wsum = wsum;
-        b.refv_out = refv;
-        profile_begin("ref_gather", s);
-        launch_gather(b, 0, g, s);
-        profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
-        return check_hip(hipGetLastError(), "reference update (float32 gather)");
-    }
+SplatArgs make_splat_args(const Geom& g, const pxst_scan& sc, const float* dx, float* ref, double* wsum,
+                          float* refv, char* ws, const Layout& L) {
     SplatArgs a{};
     a.frames = sc.frames;
     a.dx = dx;
@@ -1057,20 +1127,66 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     a.GH = grid_h(g);
     a.GW = grid_w(g);
     a.nchunks = L.splat_chunks;
+    a.tiles_x = (g.Rf + RS_TC - 1) / RS_TC;
+    a.tiles_y = (g.Rs + RS_TR - 1) / RS_TR;
     a.part = (longlong2*)(ws + L.rpart);
     a.ref = ref;
     a.wsum = wsum;
     a.refv = refv;
-    const dim3 grid((g.Rf + RS_TC - 1) / RS_TC, (g.Rs + RS_TR - 1) / RS_TR, a.nchunks);
+    return a;
+}
+
+int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const MapArgs* dm,
+                          const SplatArgs* ds, hipStream_t s) {
+    for (int j = 1; j < n; ++j)
+        if ((hs[j].nchunks > 1) != (hs[0].nchunks > 1)) {
+            set_error("batched reference update: the jobs differ in frame chunking");
+            return PXST_EINVAL;
+        }
+    int rc = launch_maps(hm, n, dm, s);
+    if (rc) return rc;
+    int tx = 1, tyc = 1, rrb = 1;
+    long long work = 0;
+    for (int j = 0; j < n; ++j) {
+        tx = std::max(tx, hs[j].tiles_x);
+        tyc = std::max(tyc, hs[j].tiles_y * hs[j].nchunks);
+        rrb = std::max(rrb, (int)grid_blocks((size_t)hs[j].Rs * hs[j].Rf, 256));
+        work += (long long)hs[j].HW * hs[j].N;
+    }
+    const SplatArgs one = ds ? SplatArgs{} : hs[0];
     profile_begin("ref_gather", s);
-    hipLaunchKernelGGL(k_ref_splat, grid, dim3(RS_THREADS), 0, s, a);
-    if (a.nchunks > 1)
-        hipLaunchKernelGGL(k_ref_splat_combine, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, a);
-    if (ref_mode == PXST_REF_BF16)
-        hipLaunchKernelGGL(k_round_bf16, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, ref, refv,
-                           g.RR());
-    profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
+    hipLaunchKernelGGL(k_ref_splat, dim3(tx, tyc, n), dim3(RS_THREADS), 0, s, ds, one);
+    if (hs[0].nchunks > 1)
+        hipLaunchKernelGGL(k_ref_splat_combine, dim3(rrb, 1, n), dim3(256), 0, s, ds, one);
+    profile_end("ref_gather", s, work, nullptr, 0);
     return check_hip(hipGetLastError(), "reference update");
+}
+
+int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
+                            float* ref, double* wsum, float* refv, char* ws, const Layout& L,
+                            hipStream_t s, int ref_mode) {
+    if (ref_mode == PXST_REF_FP32) {
+        int rc = build_inverse_map(g, sc, u, ws, L, s);
+        if (rc) return rc;
+        GatherArgs b = gather_args(g, sc, u, dx, ws, L);
+        b.out = ref;
+        b.wsum = wsum;
+        b.refv_out = refv;
+        profile_begin("ref_gather", s);
+        launch_gather(b, 0, g, s);
+        profile_end("ref_gather", s, (long long)g.HW() * g.N, nullptr, 0);
+        return check_hip(hipGetLastError(), "reference update (float32 gather)");
+    }
+    const MapArgs m = make_map_args(g, sc, u, ws, L);
+    const SplatArgs a = make_splat_args(g, sc, dx, ref, wsum, refv, ws, L);
+    int rc = launch_reference_jobs(&m, &a, 1, nullptr, nullptr, s);
+    if (rc || ref_mode != PXST_REF_BF16) return rc;
+    return launch_round_bf16(g, ref, refv, s);
+}
+
+int launch_round_bf16(const Geom& g, float* ref, float* refv, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_bf16, dim3(grid_blocks(g.RR(), 256)), dim3(256), 0, s, ref, refv, g.RR());
+    return check_hip(hipGetLastError(), "reference update (bfloat16)");
 }
 
 int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,

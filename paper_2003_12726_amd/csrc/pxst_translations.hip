@@ -24,26 +24,13 @@ namespace pxst {
 
 namespace {
 
-struct TrArgs {
-    const uint16_t* frames;
-    const float* white;
-    const uint8_t* mask;
-    const float* refv;
-    const float* u;
-    const float* dx_in;
-    float* dx_out;
-    float* err_out;
-    int* arg_out;
-    float* part;      // [N][nblk][Ct][3]: error, variance, a positive value when any lookup was valid
-    int4* bbox;       // [nblk]: min / max of floor(u0), min / max of floor(u1) over good pixels
-    int N, H, W, Rs, Rf, o0, o1;
-    int nblk, tiles_x, refine;
-};
 
 // Pass 0: integer bounding box of the map over each tile's good pixels (min > max when
 // the tile has none; |u| beyond 2^24 marks the box as unusable).
-__global__ __launch_bounds__(256) void k_tr_bbox(TrArgs a) {
+__global__ __launch_bounds__(256) void k_tr_bbox(const TrArgs* jobs, TrArgs one) {
+    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
     const int tile = blockIdx.x;
+    if (tile >= a.nblk) return;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
     const size_t HW = (size_t)a.H * a.W;
     int mn0 = INT_MAX, mx0 = INT_MIN, mn1 = INT_MAX, mx1 = INT_MIN;
@@ -235,10 +222,12 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
 // Pass 1.  STAGED: the tiles whose region fits the LDS; the others (and tiles without a
 // good pixel) in the launch without staging.  Every tile is written by exactly one.
 template <int TX, int TY, bool STAGED>
-__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
+__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* jobs, TrArgs one) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
     __shared__ float reg[STAGED ? TR_LDS_FLOATS : 1];
+    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
     const int tile = blockIdx.x, n = blockIdx.y;
+    if (tile >= a.nblk || n >= a.N) return;
     const int tyi = tile / a.tiles_x, txi = tile - tyi * a.tiles_x;
     const int4 bb = a.bbox[tile];
     const bool any_px = bb.x <= bb.y;
@@ -354,10 +343,12 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(TrArgs a) {
 // One wave per frame: lanes add the block partials of each shift (compensated, blocks
 // in lane-strided order), a fixed butterfly combines the lanes, lane 0 decides.
 template <int TX, int TY>
-__global__ __launch_bounds__(64) void k_tr_final(TrArgs a) {
+__global__ __launch_bounds__(64) void k_tr_final(const TrArgs* jobs, TrArgs one) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
     __shared__ float Es[CT];
+    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
     const int n = blockIdx.x;
+    if (n >= a.N) return;
     const int lane = threadIdx.x;
     for (int s = 0; s < CT; ++s) {
         float eS = 0.f, eC = 0.f, vS = 0.f, vC = 0.f, c = 0.f;
@@ -406,7 +397,7 @@ __global__ __launch_bounds__(64) void k_tr_final(TrArgs a) {
     if (a.arg_out) a.arg_out[n] = bk;
 }
 
-typedef void (*TrKernel)(TrArgs);
+typedef void (*TrKernel)(const TrArgs*, TrArgs);
 
 template <int TX, int TY>
 void pick(TrKernel& ps, TrKernel& pg, TrKernel& f) {
@@ -432,14 +423,9 @@ bool pick_tr(int tx, int ty, TrKernel& ps, TrKernel& pg, TrKernel& f) {
 
 }  // namespace
 
-int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
-                        const float* dx_in, const pxst_window& win, float* dx_out, float* err_min,
-                        int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
-    TrKernel kp = nullptr, kg = nullptr, kf = nullptr;
-    if (!pick_tr(win.r_ss, win.r_fs, kp, kg, kf)) {
-        set_error("translation window radii must be in 0..%d", PXST_MAX_TR_RADIUS);
-        return PXST_EUNSUPPORTED;
-    }
+TrArgs make_tr_args(const Geom& g, const pxst_scan& sc, const float* refv, const float* u, const float* dx_in,
+                    const pxst_window& win, float* dx_out, float* err_min, int32_t* argmin, char* ws,
+                    const Layout& L) {
     TrArgs a{};
     a.frames = sc.frames;
     a.white = sc.white;
@@ -462,14 +448,43 @@ int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, c
     a.nblk = a.tiles_x * ((g.H + TR_TILE - 1) / TR_TILE);
     a.bbox = (int4*)(ws + L.tr_bbox);
     a.refine = win.refine != 0;
-    hipLaunchKernelGGL(k_tr_bbox, dim3(a.nblk), dim3(256), 0, s, a);
+    a.tx = win.r_ss;
+    a.ty = win.r_fs;
+    return a;
+}
+
+int launch_translations_jobs(const TrArgs* host, int n, const TrArgs* dev, hipStream_t s) {
+    TrKernel kp = nullptr, kg = nullptr, kf = nullptr;
+    if (!pick_tr(host[0].tx, host[0].ty, kp, kg, kf)) {
+        set_error("translation window radii must be in 0..%d", PXST_MAX_TR_RADIUS);
+        return PXST_EUNSUPPORTED;
+    }
+    int nblk = 1, nf = 1;
+    long long work = 0;
+    for (int j = 0; j < n; ++j) {
+        if (host[j].tx != host[0].tx || host[j].ty != host[0].ty) {
+            set_error("batched translation search: jobs differ in window");
+            return PXST_EINVAL;
+        }
+        nblk = std::max(nblk, host[j].nblk);
+        nf = std::max(nf, host[j].N);
+        work += (long long)host[j].H * host[j].W * host[j].N * (2 * host[j].tx + 1) * (2 * host[j].ty + 1);
+    }
+    const TrArgs one = dev ? TrArgs{} : host[0];
+    hipLaunchKernelGGL(k_tr_bbox, dim3(nblk, 1, n), dim3(256), 0, s, dev, one);
     profile_begin("tr_partial", s);
-    hipLaunchKernelGGL(kp, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
-    hipLaunchKernelGGL(kg, dim3(a.nblk, g.N), dim3(TR_THREADS), 0, s, a);
-    profile_end("tr_partial", s,
-                (long long)g.HW() * g.N * (2 * win.r_ss + 1) * (2 * win.r_fs + 1), nullptr, 0);
-    hipLaunchKernelGGL(kf, dim3(g.N), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(kp, dim3(nblk, nf, n), dim3(TR_THREADS), 0, s, dev, one);
+    hipLaunchKernelGGL(kg, dim3(nblk, nf, n), dim3(TR_THREADS), 0, s, dev, one);
+    profile_end("tr_partial", s, work, nullptr, 0);
+    hipLaunchKernelGGL(kf, dim3(nf, 1, n), dim3(64), 0, s, dev, one);
     return check_hip(hipGetLastError(), "translation search");
+}
+
+int launch_translations(const Geom& g, const pxst_scan& sc, const float* refv, const float* u,
+                        const float* dx_in, const pxst_window& win, float* dx_out, float* err_min,
+                        int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+    const TrArgs a = make_tr_args(g, sc, refv, u, dx_in, win, dx_out, err_min, argmin, ws, L);
+    return launch_translations_jobs(&a, 1, nullptr, s);
 }
 
 }  // namespace pxst
