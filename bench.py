@@ -206,10 +206,10 @@ def _gen_job(args):
             s.iters, tuple(s.window))
 
 
-def served_requests(n_jobs: int, workers: int):
+def served_requests(n_jobs: int, workers: int, seed: int = 5000):
     """The served stream's jobs (Poisson arrivals, mean gap 0.5 s), generated in parallel."""
     from synth import served_job_specs
-    specs, gaps = served_job_specs(n_jobs)
+    specs, gaps = served_job_specs(n_jobs, seed=seed)
     arrivals = [float(x) for x in __import__("numpy").cumsum(gaps)]
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
@@ -226,9 +226,11 @@ def run_served(rows, time_scale: float):
             for (k, arr, f, w, m, u, d, rs, o, it, win) in rows]
     evals = sum(r.pm_evals() for r in reqs)
     out = {}
-    for mode in ("one_by_one", "batched"):
-        if mode == "batched":
-            srv = serve.Server(budget_bytes=200 << 30, max_slots=64, keep_results=False)
+    for mode in ("one_by_one", "batched", "batched_all"):
+        print(f"[served] {len(reqs)} jobs replayed {time_scale:g}x, {mode}", file=sys.stderr, flush=True)
+        if mode != "one_by_one":
+            srv = serve.Server(budget_bytes=200 << 30, max_slots=64, keep_results=False,
+                               policy="srpt" if mode == "batched" else "all")
             res = srv.run(reqs, time_scale=time_scale)
         else:
             res = serve.run_one_by_one(reqs, time_scale=time_scale, keep_results=False)
@@ -237,7 +239,7 @@ def run_served(rows, time_scale: float):
         st = serve.latency_stats(res)
         st["pm_evals_per_s"] = evals / (last - first)
         st["makespan_s"] = last - first
-        if mode == "batched":
+        if mode != "one_by_one":
             st["ticks"] = srv.ticks
             st["max_resident"] = srv.max_resident
         out[mode] = st
@@ -529,6 +531,36 @@ def pct(xs, q):
     return xs[k]
 
 
+def served_study(n_jobs: int, seeds, rates, workers: int):
+    """The served stream over several arrival seeds, at each replay rate (1 = the real
+    arrival rate): latency p50 / p99 / max and throughput, batched and one by one."""
+    import torch
+    import paper_2003_12726_amd as pxst
+    streams = []
+    # the generator forks worker processes: every stream is made before this process
+    # loads the HIP library or touches the GPU
+    for seed in seeds:
+        print(f"[served] generating stream seed {seed}", file=sys.stderr, flush=True)
+        streams.append((seed, served_requests(n_jobs, workers, seed)))
+    pxst.load_library()
+    runs = []
+    for seed, rows in streams:
+        for rate in rates:
+            r = run_served(rows, rate)
+            r["seed"] = seed
+            r["replay_rate"] = rate
+            runs.append(r)
+            torch.cuda.empty_cache()
+    table = []
+    for r in runs:
+        for mode in ("one_by_one", "batched", "batched_all"):
+            st = r[mode]
+            table.append({"seed": r["seed"], "replay_rate": r["replay_rate"], "mode": mode,
+                          "p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_s": st["max_s"],
+                          "pm_evals_per_s": st["pm_evals_per_s"], "makespan_s": st["makespan_s"]})
+    return {"workload": runs[0]["workload"].split(" replayed")[0] if runs else None, "runs": table}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,6 +575,10 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--served-jobs", type=int, default=64)
     ap.add_argument("--served-speedup", type=float, default=50.0)
+    ap.add_argument("--served-study", nargs="*", type=int, metavar="SEED",
+                    help="only the served stream: these arrival seeds (default 5000 6000 7000), "
+                         "each replayed at the rates of --served-rates; prints one JSON line")
+    ap.add_argument("--served-rates", nargs="+", type=float, default=[1.0, 50.0])
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="end with one device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -561,6 +597,12 @@ def main():
     import torch
     import paper_2003_12726_amd as pxst
     from synth.scans import cached_scan
+
+    if args.served_study is not None:
+        seeds = args.served_study or [5000, 6000, 7000]
+        print(json.dumps(served_study(args.served_jobs, seeds, args.served_rates,
+                                      args.cpu_workers or min(16, os.cpu_count() or 1))), flush=True)
+        return
 
     if args.divergent_only:
         pxst.load_library()

@@ -2,13 +2,17 @@
 
 Requests (scans with their solve options) arrive over time.  The server keeps every
 admitted job's frames, state and workspace resident in HBM, admits waiting jobs in
-arrival order while the job-slot count and the HBM budget allow, and advances all
-resident jobs together: one tick is one call of ``pxst_batch_iterate``, which runs
-one main-loop iteration (or the final reference update) of every resident job, with
-the pixel-map search of all of them in shared persistent launches.  Jobs join and
-leave at tick boundaries; a finished job's memory is released before the next tick's
-admission.  Latency is measured from a request's arrival to the end of the tick that
-finishes it.
+arrival order while the job-slot count and the HBM budget allow, and advances resident
+jobs together: one tick is one call of ``pxst_batch_iterate``, which runs one
+main-loop iteration (or the final reference update) of each job of the tick, every
+stage of all of them in shared launches.  Which resident jobs a tick takes is the
+policy: "srpt" (default) takes them in order of least remaining work until the
+tick's pixel-map work reaches ``tick_evals`` (enough to fill the device), so short
+jobs overtake long ones as in shortest-remaining-processing-time scheduling and a
+tick still fills the device; "all" advances every resident job each tick.  Jobs join
+and leave at tick boundaries; a finished job's memory is released before the next
+tick's admission.  Latency is measured from a request's arrival to the end of the
+tick that finishes it.
 
 ``run_one_by_one`` serves the same arrivals with one ``pxst_solve`` per job in arrival
 order, for comparison.
@@ -44,9 +48,11 @@ class Request:
     tr_window: Sequence[int] = (2, 2)
 
     def pm_evals(self) -> int:
+        return self.evals_per_iter() * int(self.n_iter)
+
+    def evals_per_iter(self) -> int:
         rx, ry = self.window
-        return int(self.mask.astype(bool).sum()) * (2 * rx + 1) * (2 * ry + 1) * \
-            int(self.frames.shape[0]) * int(self.n_iter)
+        return int(self.mask.astype(bool).sum()) * (2 * rx + 1) * (2 * ry + 1) * int(self.frames.shape[0])
 
 
 @dataclasses.dataclass
@@ -98,6 +104,11 @@ class _Resident:
         self.opts = make_opts(req.n_iter, req.window, req.refine, req.update_dx, req.tr_window)
         self.ws = alloc_workspace(self.scan.geom, self.opts, dev)
         self.iter = 0
+        self.per_iter = req.evals_per_iter()
+
+    def remaining(self) -> int:
+        """Pixel-map work left (the final reference update counts as none)."""
+        return self.per_iter * max(0, self.req.n_iter - self.iter)
 
     def cjob(self) -> CJob:
         j = CJob()
@@ -122,11 +133,18 @@ class _Resident:
 class Server:
     """Continuous-batching server for PXST solves on one GPU.
 
-    budget_bytes: HBM budget for resident jobs; max_slots: resident job limit.
+    budget_bytes: HBM budget for resident jobs; max_slots: resident job limit;
+    policy: "srpt" or "all" (which resident jobs a tick advances); tick_evals: the
+    pixel-map work at which an "srpt" tick stops taking jobs.
     """
 
-    def __init__(self, budget_bytes: int, max_slots: int = 64, device="cuda", keep_results=True):
+    def __init__(self, budget_bytes: int, max_slots: int = 64, device="cuda", keep_results=True,
+                 policy: str = "srpt", tick_evals: float = 2e10):
         import torch
+        if policy not in ("srpt", "all"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.policy = policy
+        self.tick_evals = float(tick_evals)
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.dev = torch.device(device)
@@ -142,6 +160,19 @@ class Server:
         if self.batch_ws is None or self.batch_ws.numel() < need:
             self.batch_ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
         return self.batch_ws
+
+    def _pick(self, resident: List[tuple]) -> List[tuple]:
+        """The resident jobs this tick advances."""
+        if self.policy == "all":
+            return resident
+        order = sorted(resident, key=lambda r: (r[0].remaining(), r[1]))
+        tick, work = [], 0
+        for r in order:
+            if tick and work >= self.tick_evals:
+                break
+            tick.append(r)
+            work += r[0].per_iter if r[0].iter < r[0].req.n_iter else 0
+        return tick
 
     def run(self, requests: List[Request], time_scale: float = 1.0) -> Dict[int, Result]:
         """Serve requests whose arrivals are given in seconds (divided by time_scale)."""
@@ -184,7 +215,8 @@ class Server:
                         time.sleep(max(0.0, pend[0].arrival / time_scale - now()))
                     continue
             self.max_resident = max(self.max_resident, len(resident))
-            jobs = [r[0].cjob() for r in resident]
+            tick = self._pick(resident)
+            jobs = [r[0].cjob() for r in tick]
             batch_iterate(jobs, self._batch_ws(len(jobs)))
             # while the tick runs, admit what has arrived: the host-side staging of their
             # frames overlaps the device's work, their uploads follow the tick on the
@@ -194,7 +226,11 @@ class Server:
             self.ticks += 1
             fin = now()
             keep = []
+            advanced = set(id(r[0]) for r in tick)
             for res, arr, adm, nb in resident:
+                if id(res) not in advanced:
+                    keep.append((res, arr, adm, nb))
+                    continue
                 res.iter += 1
                 if res.iter > res.req.n_iter:
                     if self.keep_results:

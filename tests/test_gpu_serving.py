@@ -53,12 +53,15 @@ def assert_same(a, b):
         assert np.array_equal(x, y), (a.job_id, name, np.abs(x - y).max())
 
 
-def test_batched_equals_alone_bitwise():
+@pytest.mark.parametrize("policy,tick_evals", [("srpt", 2e10), ("srpt", 1.0), ("all", 0.0)])
+def test_batched_equals_alone_bitwise(policy, tick_evals):
+    """tick_evals = 1 makes every srpt tick take one job (plus the jobs whose final
+    reference update is due), so jobs overtake each other as often as possible."""
     reqs = requests()
     say("[serve] one by one")
     alone = serve.run_one_by_one(reqs)
-    say("[serve] continuous batching")
-    srv = serve.Server(budget_bytes=8 << 30, max_slots=16)
+    say(f"[serve] continuous batching, policy {policy}, tick work {tick_evals:g}")
+    srv = serve.Server(budget_bytes=8 << 30, max_slots=16, policy=policy, tick_evals=tick_evals)
     mixed = srv.run(reqs)
     assert srv.max_resident >= 3, srv.max_resident
     for k in alone:
