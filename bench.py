@@ -120,6 +120,31 @@ def write_traffic(fetch_dir: str, write_dir: str, copy_mib: int):
     with open(p, "w") as fh:
         json.dump(d, fh, indent=1)
     print(json.dumps(d["realistic"], indent=1))
+    print(kernel_traffic_table(fetch_dir, write_dir, copy_mib))
+
+
+def kernel_traffic_table(fetch_dir: str, write_dir: str, copy_mib: int) -> str:
+    """Markdown table of every kernel's HBM bytes per dispatch in the two counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the calibration copy's reading)."""
+    import re
+    nb = copy_mib << 20
+    per = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        disp = _per_dispatch(_counter_rows(d), counter)
+        cp = [v for k, g, v in disp if "copyBuffer" in k or "copy" in k.lower()]
+        factor = (nb / 1024.0) / max(cp)
+        for k, g, v in disp:
+            name = re.sub(r"\(anonymous namespace\)::", "", k)
+            name = re.sub(r"\(.*", "", name).replace("void ", "").replace("pxst::", "").strip()
+            ent = per.setdefault(name, {"FETCH_SIZE": [], "WRITE_SIZE": []})
+            ent[counter].append(v * 1024.0 * factor)
+    rows = ["| kernel | dispatches | fetch MB / dispatch | write MB / dispatch |", "|---|---|---|---|"]
+    for name, ent in sorted(per.items(), key=lambda kv: -sum(kv[1]["FETCH_SIZE"] + kv[1]["WRITE_SIZE"])):
+        f, w = ent["FETCH_SIZE"], ent["WRITE_SIZE"]
+        fm = sum(f) / len(f) / 1e6 if f else float("nan")
+        wm = sum(w) / len(w) / 1e6 if w else float("nan")
+        rows.append(f"| `{name}` | {max(len(f), len(w))} | {fm:.2f} | {wm:.2f} |")
+    return "\n".join(rows)
 
 
 def roofline(mm, avg_ms, launches, evals_per_launch, achieved_tflops, traffic):
@@ -622,7 +647,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         nw = args.cpu_workers or min(16, os.cpu_count() or 1)
-        cpu = cpu_baseline(scan, nw, 192)
+        cpu = cpu_baseline(scan, nw, 3072)
     served_rows = None
     if args.served_jobs > 0:
         served_rows = served_requests(args.served_jobs, args.cpu_workers or min(16, os.cpu_count() or 1))

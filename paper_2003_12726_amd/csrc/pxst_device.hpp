@@ -221,4 +221,35 @@ __device__ inline int wave_max_i(int v) {
     return v;
 }
 
+
+// Arguments of a kernel that serves one job (passed by value) or a table of jobs in
+// device memory (the job index is blockIdx.z).  The form is a compile-time choice: a
+// run-time select between the two would take the by-value arguments' address and move
+// them from scalar to vector registers.
+// The table is read through the constant address space, so that the loads are scalar
+// and the arguments stay in scalar registers in both forms (the table is not written
+// while a kernel runs).
+template <bool BATCH, class X>
+__device__ __forceinline__ X job_args(const X* __restrict__ jobs, const X& one) {
+    if constexpr (BATCH) {
+        typedef const __attribute__((address_space(4))) X* ConstPtr;
+        X out;
+        __builtin_memcpy(&out, (ConstPtr)jobs + blockIdx.z, sizeof(X));
+        return out;
+    } else {
+        return one;
+    }
+}
+
+// Work item of block b out of n items.  Work-groups go to the eight XCDs in turn
+// (block b to XCD b mod 8) and each XCD has its own L2, so consecutive items of the
+// work list -- neighbouring tiles, whose regions overlap -- would each be read into a
+// different L2.  Instead each XCD takes one contiguous run of the list: XCD x holds
+// the items [x q + min(x, r), ...) with q = n / 8, r = n mod 8 (a bijection of [0, n)).
+__device__ inline int xcd_item(int b, int n) {
+    if (b >= n) return b;
+    const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + i;
+}
+
 }  // namespace pxst

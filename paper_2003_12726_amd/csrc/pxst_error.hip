@@ -80,11 +80,11 @@ __device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
 // come from two 8-byte loads of the 2x2 block at the lookup clamped into the grid, each
 // corner inside the grid at its own row and column of the block; otherwise four loads
 // at the corners clamped one by one.
-template <bool PAIRS>
-__global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* jobs, ErrArgs one) {
+template <bool PAIRS, bool BATCH>
+__global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* __restrict__ jobs, ErrArgs one) {
     extern __shared__ double wsum_sh[];   // [N][waves], then the frame table [N]
     constexpr int WAVES = ERR_THREADS / 64;
-    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
+    const ErrArgs a = job_args<BATCH>(jobs, one);
     if ((int)blockIdx.x >= a.nblk) return;
     // per frame: the fractions of its shift and the integer parts (bits of ints)
     float4* ftab = (float4*)(wsum_sh + (size_t)a.N * WAVES);
@@ -202,8 +202,9 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* jobs,
 
 // One wave per frame: lanes add the block partials in lane-strided order, a fixed
 // butterfly combines the lanes.
-__global__ __launch_bounds__(64) void k_err_frames(const ErrArgs* jobs, ErrArgs one) {
-    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(64) void k_err_frames(const ErrArgs* __restrict__ jobs, ErrArgs one) {
+    const ErrArgs a = job_args<BATCH>(jobs, one);
     const int n = blockIdx.x;
     if (n >= a.N) return;
     double acc = 0.0;
@@ -216,8 +217,9 @@ __global__ __launch_bounds__(64) void k_err_frames(const ErrArgs* jobs, ErrArgs 
 }
 
 // Total: the frame errors added by one wave in the same fixed order.
-__global__ __launch_bounds__(64) void k_err_total(const ErrArgs* jobs, ErrArgs one) {
-    const ErrArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(64) void k_err_total(const ErrArgs* __restrict__ jobs, ErrArgs one) {
+    const ErrArgs a = job_args<BATCH>(jobs, one);
     double acc = 0.0;
     for (int n = threadIdx.x; n < a.N; n += 64) acc += a.frame_err[n];
     acc = wave_sum<double>(acc);
@@ -261,6 +263,13 @@ ErrArgs make_err_args(const Geom& g, const pxst_scan& sc, const float* refv, con
 }
 
 // LDS of the pixel pass: per-wave frame sums and the frame table.
+template <bool PAIRS, bool BATCH>
+static void launch_err_pixels(int nblk, int n, size_t sh, hipStream_t s, const ErrArgs* dev, const ErrArgs& one) {
+    // (up to 1920 frames: 92 KB, above the default limit of dynamic LDS)
+    (void)hipFuncSetAttribute((const void*)k_err_pixels<PAIRS, BATCH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    k_err_pixels<PAIRS, BATCH><<<dim3(nblk, 1, n), dim3(ERR_THREADS), sh, s>>>(dev, one);
+}
+
 static size_t err_lds(int N) { return (size_t)N * (ERR_THREADS / 64) * sizeof(double) + (size_t)N * sizeof(float4); }
 
 // The three passes for the jobs of `host` (their arguments also in device memory at
@@ -289,17 +298,16 @@ int launch_error_jobs(const ErrArgs* host, int n, const ErrArgs* dev, hipStream_
     long long work = 0;
     for (int j = 0; j < n; ++j) work += (long long)host[j].H * host[j].W * host[j].N;
     profile_begin("err_pixels", s);
-    // (up to 1920 frames: 92 KB, above the default limit of dynamic LDS)
     if (pairs) {
-        hipFuncSetAttribute((const void*)k_err_pixels<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_err_pixels<true>, dim3(nblk, 1, n), dim3(ERR_THREADS), sh, s, dev, one);
+        if (dev) launch_err_pixels<true, true>(nblk, n, sh, s, dev, one);
+        else launch_err_pixels<true, false>(nblk, n, sh, s, dev, one);
     } else {
-        hipFuncSetAttribute((const void*)k_err_pixels<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipLaunchKernelGGL(k_err_pixels<false>, dim3(nblk, 1, n), dim3(ERR_THREADS), sh, s, dev, one);
+        if (dev) launch_err_pixels<false, true>(nblk, n, sh, s, dev, one);
+        else launch_err_pixels<false, false>(nblk, n, sh, s, dev, one);
     }
     profile_end("err_pixels", s, work, nullptr, 0);
-    hipLaunchKernelGGL(k_err_frames, dim3(nf, 1, n), dim3(64), 0, s, dev, one);
-    hipLaunchKernelGGL(k_err_total, dim3(1, 1, n), dim3(64), 0, s, dev, one);
+    PXST_LAUNCH_JOBS(k_err_frames, dim3(nf, 1, n), dim3(64), 0, s, dev, one);
+    PXST_LAUNCH_JOBS(k_err_total, dim3(1, 1, n), dim3(64), 0, s, dev, one);
     return check_hip(hipGetLastError(), "error evaluation");
 }
 

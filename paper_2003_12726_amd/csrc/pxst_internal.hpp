@@ -159,6 +159,16 @@ void profile_end_snap(const char* family, hipStream_t s, int snap, int index, co
 // Argument tables of a batched launch live in the caller's batch workspace; they are
 // written into a pinned host buffer owned by the library and copied with
 // hipMemcpyAsync on the launch stream just before the launch that reads them.
+// Launches the batched form (job table `dev` in device memory, job index blockIdx.z) or
+// the single-job form (arguments `one` by value) of a kernel templated on <bool BATCH>.
+#define PXST_LAUNCH_JOBS(K, grid, block, sh, s, dev, one)                \
+    do {                                                                  \
+        if (dev)                                                          \
+            K<true><<<(grid), (block), (sh), (s)>>>((dev), (one));        \
+        else                                                              \
+            K<false><<<(grid), (block), (sh), (s)>>>((dev), (one));       \
+    } while (0)
+
 struct BatchArena {
     char* host = nullptr;       // pinned staging memory
     char* dev = nullptr;        // batch workspace

@@ -1770,17 +1770,6 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
         }                                                                                     \
     }
 
-// Work item of block b out of n items.  Work-groups go to the eight XCDs in turn
-// (block b to XCD b mod 8) and each XCD has its own L2, so consecutive items of the
-// work list -- neighbouring tiles, whose regions overlap -- would each be read into a
-// different L2.  Instead each XCD takes one contiguous run of the list: XCD x holds
-// the items [x q + min(x, r), ...) with q = n / 8, r = n mod 8 (a bijection of [0, n)).
-__device__ inline int xcd_item(int b, int n) {
-    if (b >= n) return b;
-    const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
-    return x * q + min(x, r) + i;
-}
-
 // single-job launch of a matrix-core search over the list counted by CNT, items in
 // contiguous runs per XCD
 #define PXST_WRAP_XCD(NAME, BODY, CNT)                                                        \

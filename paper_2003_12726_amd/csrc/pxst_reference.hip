@@ -34,8 +34,9 @@ __device__ inline int cell_coord(float u, int o) {
     return (int)f - o;
 }
 
-__global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const MapArgs* jobs, MapArgs one) {
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const MapArgs* __restrict__ jobs, MapArgs one) {
+    const MapArgs a = job_args<BATCH>(jobs, one);
     if ((int)blockIdx.x >= a.nparts) return;
     const float* __restrict__ u = a.u;
     const uint8_t* __restrict__ mask = a.mask;
@@ -84,8 +85,9 @@ __global__ __launch_bounds__(GRID_THREADS) void k_grid_bbox(const MapArgs* jobs,
 // Reduces the partials and sets the grid origin: the bounding box (plus a one-cell
 // margin) when it fits the capacity, else a window of the capacity centred on the
 // mean cell.
-__global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const MapArgs* jobs, MapArgs one) {
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(GRID_THREADS) void k_grid_origin(const MapArgs* __restrict__ jobs, MapArgs one) {
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const GridPart* __restrict__ part = a.gpart;
     const int nparts = a.nparts, GH = a.GH, GW = a.GW;
     GridInfo* gi = a.gi;
@@ -170,8 +172,9 @@ __device__ inline void grid_region(const GridInfo& gi, int GH, int GW, int& r0, 
 
 // One work-group per row of cells: clears the counts of the region's cells (and the two
 // other keys' counts).
-__global__ __launch_bounds__(256) void k_count_clear(const MapArgs* jobs, MapArgs one) {
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_count_clear(const MapArgs* __restrict__ jobs, MapArgs one) {
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const int GH = a.GH, GW = a.GW;
     unsigned* __restrict__ cnt = a.cnt;
     if ((int)blockIdx.x >= GH) return;
@@ -184,8 +187,9 @@ __global__ __launch_bounds__(256) void k_count_clear(const MapArgs* jobs, MapArg
     for (int c = c0 + (int)threadIdx.x; c <= c1; c += 256) cnt[(size_t)r * GW + c] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_keys(const MapArgs* jobs, MapArgs one) {
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_keys(const MapArgs* __restrict__ jobs, MapArgs one) {
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const float* __restrict__ u = a.u;
     const uint8_t* __restrict__ mask = a.mask;
     const int HW = a.HW, o0 = a.o0, o1 = a.o1, GH = a.GH, GW = a.GW;
@@ -246,9 +250,10 @@ __device__ inline unsigned block_excl_scan(unsigned v, unsigned* tmp4, unsigned&
 
 // One work-group per row of cells: in-row exclusive scan of the region's counts, with
 // the row's end after its last cell, and the row's total (0 outside the region).
-__global__ __launch_bounds__(256) void k_scan_rows(const MapArgs* jobs, MapArgs one) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_scan_rows(const MapArgs* __restrict__ jobs, MapArgs one) {
     __shared__ unsigned tmp4[4];
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const int GH = a.GH, GW = a.GW;
     const unsigned* __restrict__ cnt = a.cnt;
     unsigned* __restrict__ cstart = a.cstart;
@@ -282,9 +287,10 @@ __global__ __launch_bounds__(256) void k_scan_rows(const MapArgs* jobs, MapArgs 
 // One work-group: exclusive scan of the row totals into rstart[0 .. GH] and the starts
 // of the other keys: kstart[0] = first entry outside the grid, kstart[1] = number of
 // good pixels, kstart[2] = end.
-__global__ __launch_bounds__(256) void k_scan_top(const MapArgs* jobs, MapArgs one) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_scan_top(const MapArgs* __restrict__ jobs, MapArgs one) {
     __shared__ unsigned tmp4[4];
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const int GH = a.GH;
     const unsigned* __restrict__ rtot = a.rtot;
     const unsigned* __restrict__ cnt = a.cnt;
@@ -316,8 +322,9 @@ __device__ inline unsigned cell_first(const unsigned* __restrict__ cstart, const
 
 // Places the pixels of grid cells: slot = remaining count - 1 (the order inside a cell
 // is fixed afterwards); the counts end at 0.
-__global__ void k_cell_scatter(const MapArgs* jobs, MapArgs one) {
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ void k_cell_scatter(const MapArgs* __restrict__ jobs, MapArgs one) {
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const unsigned* __restrict__ keys = a.keys;
     const int HW = a.HW, GW = a.GW;
     const unsigned ncells = (unsigned)a.GH * (unsigned)a.GW;
@@ -354,9 +361,10 @@ __device__ inline void entry_data(const float* __restrict__ u, const float* __re
 // pixel index (a cell holds one or two pixels when u maps about one pixel per reference
 // pixel) and writes their data.  The last work-group places the pixels outside the grid
 // in pixel order and writes theirs (nothing to do for a sensible map).
-__global__ __launch_bounds__(256) void k_cell_finish(const MapArgs* jobs, MapArgs one) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_cell_finish(const MapArgs* __restrict__ jobs, MapArgs one) {
     __shared__ unsigned wc[4];
-    const MapArgs a = jobs ? jobs[blockIdx.z] : one;
+    const MapArgs a = job_args<BATCH>(jobs, one);
     const float* __restrict__ u = a.u;
     const float* __restrict__ white = a.white;
     const unsigned* __restrict__ keys = a.keys;
@@ -579,10 +587,11 @@ __global__ void k_prep_refv(const float* __restrict__ ref, const double* __restr
 
 // Inclusive prefix sums of the invalid flags along each reference row, written
 // transposed: tmp[c][r]; rowmax[r] = max |refv| over the valid pixels of row r.
-__global__ __launch_bounds__(256) void k_sat_rows(const SatArgs* jobs, SatArgs one) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_sat_rows(const SatArgs* __restrict__ jobs, SatArgs one) {
     __shared__ int part[256];
     __shared__ float pmax[256 / 64];
-    const SatArgs a = jobs ? jobs[blockIdx.z] : one;
+    const SatArgs a = job_args<BATCH>(jobs, one);
     const float* __restrict__ refv = a.refv;
     const int Rs = a.Rs, Rf = a.Rf;
     int* __restrict__ tmp = a.tmp;
@@ -624,8 +633,9 @@ __global__ __launch_bounds__(256) void k_sat_rows(const SatArgs* jobs, SatArgs o
 }
 
 // Column prefix sums of tmp[c][:] into sat[(r+1)][(c+1)] (row 0 and column 0 are 0).
-__global__ __launch_bounds__(256) void k_sat_cols(const SatArgs* jobs, SatArgs one) {
-    const SatArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_sat_cols(const SatArgs* __restrict__ jobs, SatArgs one) {
+    const SatArgs a = job_args<BATCH>(jobs, one);
     const int* __restrict__ tmp = a.tmp;
     const int Rs = a.Rs, Rf = a.Rf;
     int* __restrict__ sat = a.sat;
@@ -800,12 +810,13 @@ __device__ inline float lane_f(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_ref_splat(const SplatArgs* jobs, SplatArgs one) {
+template <bool BATCH>
+__global__ __launch_bounds__(RS_THREADS) void k_ref_splat(const SplatArgs* __restrict__ jobs, SplatArgs one) {
     constexpr int WAVES = RS_THREADS / 64;
     // value and weight sums (separate arrays: a wave's 64-bit additions to neighbouring
     // pixels then fall on neighbouring 8-byte words)
     __shared__ unsigned long long bn[RS_PR * RS_PC], bd[RS_PR * RS_PC];
-    const SplatArgs a = jobs ? jobs[blockIdx.z] : one;
+    const SplatArgs a = job_args<BATCH>(jobs, one);
     // grid: x = tile column, y = tile row + tile rows x frame chunk
     if ((int)blockIdx.x >= a.tiles_x || (int)blockIdx.y >= a.tiles_y * a.nchunks) return;
     const int chunk = (int)blockIdx.y / a.tiles_y, trow = (int)blockIdx.y - chunk * a.tiles_y;
@@ -948,8 +959,9 @@ __global__ void k_round_bf16(float* __restrict__ ref, float* __restrict__ refv, 
 }
 
 // Adds the exact chunk partials and writes the reference.
-__global__ void k_ref_splat_combine(const SplatArgs* jobs, SplatArgs one) {
-    const SplatArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ void k_ref_splat_combine(const SplatArgs* __restrict__ jobs, SplatArgs one) {
+    const SplatArgs a = job_args<BATCH>(jobs, one);
     const size_t RR = (size_t)a.Rs * a.Rf;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= RR) return;
@@ -992,8 +1004,8 @@ int launch_sat_jobs(const SatArgs* h, int n, const SatArgs* d, hipStream_t s) {
         rf = std::max(rf, h[j].Rf);
     }
     const SatArgs one = d ? SatArgs{} : h[0];
-    hipLaunchKernelGGL(k_sat_rows, dim3(rs, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_sat_cols, dim3(rf, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_sat_rows, dim3(rs, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_sat_cols, dim3(rf, 1, n), dim3(256), 0, s, d, one);
     return check_hip(hipGetLastError(), "prepare reference");
 }
 
@@ -1053,14 +1065,14 @@ static int launch_maps(const MapArgs* h, int n, const MapArgs* d, hipStream_t s)
         hwb = std::max(hwb, (int)grid_blocks((size_t)h[j].HW, 256));
     }
     const MapArgs one = d ? MapArgs{} : h[0];
-    hipLaunchKernelGGL(k_grid_bbox, dim3(parts, 1, n), dim3(GRID_THREADS), 0, s, d, one);
-    hipLaunchKernelGGL(k_grid_origin, dim3(1, 1, n), dim3(GRID_THREADS), 0, s, d, one);
-    hipLaunchKernelGGL(k_count_clear, dim3(gh, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_keys, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_scan_rows, dim3(gh, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_scan_top, dim3(1, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_cell_scatter, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
-    hipLaunchKernelGGL(k_cell_finish, dim3(gh + 1, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_grid_bbox, dim3(parts, 1, n), dim3(GRID_THREADS), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_grid_origin, dim3(1, 1, n), dim3(GRID_THREADS), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_count_clear, dim3(gh, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_keys, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_scan_rows, dim3(gh, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_scan_top, dim3(1, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_cell_scatter, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_cell_finish, dim3(gh + 1, 1, n), dim3(256), 0, s, d, one);
     return check_hip(hipGetLastError(), "inverse map");
 }
 
@@ -1155,9 +1167,9 @@ int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const M
     }
     const SplatArgs one = ds ? SplatArgs{} : hs[0];
     profile_begin("ref_gather", s);
-    hipLaunchKernelGGL(k_ref_splat, dim3(tx, tyc, n), dim3(RS_THREADS), 0, s, ds, one);
+    PXST_LAUNCH_JOBS(k_ref_splat, dim3(tx, tyc, n), dim3(RS_THREADS), 0, s, ds, one);
     if (hs[0].nchunks > 1)
-        hipLaunchKernelGGL(k_ref_splat_combine, dim3(rrb, 1, n), dim3(256), 0, s, ds, one);
+        PXST_LAUNCH_JOBS(k_ref_splat_combine, dim3(rrb, 1, n), dim3(256), 0, s, ds, one);
     profile_end("ref_gather", s, work, nullptr, 0);
     return check_hip(hipGetLastError(), "reference update");
 }

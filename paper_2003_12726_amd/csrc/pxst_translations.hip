@@ -27,8 +27,9 @@ namespace {
 
 // Pass 0: integer bounding box of the map over each tile's good pixels (min > max when
 // the tile has none; |u| beyond 2^24 marks the box as unusable).
-__global__ __launch_bounds__(256) void k_tr_bbox(const TrArgs* jobs, TrArgs one) {
-    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_tr_bbox(const TrArgs* __restrict__ jobs, TrArgs one) {
+    const TrArgs a = job_args<BATCH>(jobs, one);
     const int tile = blockIdx.x;
     if (tile >= a.nblk) return;
     const int ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
@@ -221,11 +222,11 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
 
 // Pass 1.  STAGED: the tiles whose region fits the LDS; the others (and tiles without a
 // good pixel) in the launch without staging.  Every tile is written by exactly one.
-template <int TX, int TY, bool STAGED>
-__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* jobs, TrArgs one) {
+template <int TX, int TY, bool STAGED, bool BATCH>
+__global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* __restrict__ jobs, TrArgs one) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
     __shared__ float reg[STAGED ? TR_LDS_FLOATS : 1];
-    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
+    const TrArgs a = job_args<BATCH>(jobs, one);
     const int tile = blockIdx.x, n = blockIdx.y;
     if (tile >= a.nblk || n >= a.N) return;
     const int tyi = tile / a.tiles_x, txi = tile - tyi * a.tiles_x;
@@ -342,11 +343,11 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* jobs, T
 
 // One wave per frame: lanes add the block partials of each shift (compensated, blocks
 // in lane-strided order), a fixed butterfly combines the lanes, lane 0 decides.
-template <int TX, int TY>
-__global__ __launch_bounds__(64) void k_tr_final(const TrArgs* jobs, TrArgs one) {
+template <int TX, int TY, bool BATCH>
+__global__ __launch_bounds__(64) void k_tr_final(const TrArgs* __restrict__ jobs, TrArgs one) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1, CT = NXs * NYs;
     __shared__ float Es[CT];
-    const TrArgs a = jobs ? jobs[blockIdx.z] : one;
+    const TrArgs a = job_args<BATCH>(jobs, one);
     const int n = blockIdx.x;
     if (n >= a.N) return;
     const int lane = threadIdx.x;
@@ -399,26 +400,31 @@ __global__ __launch_bounds__(64) void k_tr_final(const TrArgs* jobs, TrArgs one)
 
 typedef void (*TrKernel)(const TrArgs*, TrArgs);
 
-template <int TX, int TY>
+template <int TX, int TY, bool BATCH>
 void pick(TrKernel& ps, TrKernel& pg, TrKernel& f) {
-    ps = k_tr_partial<TX, TY, true>;
-    pg = k_tr_partial<TX, TY, false>;
-    f = k_tr_final<TX, TY>;
+    ps = k_tr_partial<TX, TY, true, BATCH>;
+    pg = k_tr_partial<TX, TY, false, BATCH>;
+    f = k_tr_final<TX, TY, BATCH>;
 }
 
-bool pick_tr(int tx, int ty, TrKernel& ps, TrKernel& pg, TrKernel& f) {
+template <bool BATCH>
+bool pick_form(int tx, int ty, TrKernel& ps, TrKernel& pg, TrKernel& f) {
     switch (tx * 3 + ty) {
-        case 0: pick<0, 0>(ps, pg, f); return true;
-        case 1: pick<0, 1>(ps, pg, f); return true;
-        case 2: pick<0, 2>(ps, pg, f); return true;
-        case 3: pick<1, 0>(ps, pg, f); return true;
-        case 4: pick<1, 1>(ps, pg, f); return true;
-        case 5: pick<1, 2>(ps, pg, f); return true;
-        case 6: pick<2, 0>(ps, pg, f); return true;
-        case 7: pick<2, 1>(ps, pg, f); return true;
-        case 8: pick<2, 2>(ps, pg, f); return true;
+        case 0: pick<0, 0, BATCH>(ps, pg, f); return true;
+        case 1: pick<0, 1, BATCH>(ps, pg, f); return true;
+        case 2: pick<0, 2, BATCH>(ps, pg, f); return true;
+        case 3: pick<1, 0, BATCH>(ps, pg, f); return true;
+        case 4: pick<1, 1, BATCH>(ps, pg, f); return true;
+        case 5: pick<1, 2, BATCH>(ps, pg, f); return true;
+        case 6: pick<2, 0, BATCH>(ps, pg, f); return true;
+        case 7: pick<2, 1, BATCH>(ps, pg, f); return true;
+        case 8: pick<2, 2, BATCH>(ps, pg, f); return true;
     }
     return false;
+}
+
+bool pick_tr(int tx, int ty, bool batch, TrKernel& ps, TrKernel& pg, TrKernel& f) {
+    return batch ? pick_form<true>(tx, ty, ps, pg, f) : pick_form<false>(tx, ty, ps, pg, f);
 }
 
 }  // namespace
@@ -455,7 +461,7 @@ TrArgs make_tr_args(const Geom& g, const pxst_scan& sc, const float* refv, const
 
 int launch_translations_jobs(const TrArgs* host, int n, const TrArgs* dev, hipStream_t s) {
     TrKernel kp = nullptr, kg = nullptr, kf = nullptr;
-    if (!pick_tr(host[0].tx, host[0].ty, kp, kg, kf)) {
+    if (!pick_tr(host[0].tx, host[0].ty, dev != nullptr, kp, kg, kf)) {
         set_error("translation window radii must be in 0..%d", PXST_MAX_TR_RADIUS);
         return PXST_EUNSUPPORTED;
     }
@@ -471,7 +477,7 @@ int launch_translations_jobs(const TrArgs* host, int n, const TrArgs* dev, hipSt
         work += (long long)host[j].H * host[j].W * host[j].N * (2 * host[j].tx + 1) * (2 * host[j].ty + 1);
     }
     const TrArgs one = dev ? TrArgs{} : host[0];
-    hipLaunchKernelGGL(k_tr_bbox, dim3(nblk, 1, n), dim3(256), 0, s, dev, one);
+    PXST_LAUNCH_JOBS(k_tr_bbox, dim3(nblk, 1, n), dim3(256), 0, s, dev, one);
     profile_begin("tr_partial", s);
     hipLaunchKernelGGL(kp, dim3(nblk, nf, n), dim3(TR_THREADS), 0, s, dev, one);
     hipLaunchKernelGGL(kg, dim3(nblk, nf, n), dim3(TR_THREADS), 0, s, dev, one);
