@@ -307,8 +307,9 @@ int pxst_error_noalloc(const pxst_scan* scan, const float* ref, const double* ws
  * sigma: finite, >= 0, int(4 sigma + 0.5) <= 256 (else PXST_EINVAL /
  * PXST_EUNSUPPORTED); integrate: 0 or 1.  The workspace must come from
  * pxst_workspace_bytes with opts->pm_integrate = 1 when integrate = 1
- * (PXST_EWORKSPACE otherwise).  Ordered on `stream`; the library holds one rocBLAS
- * handle per device for the transforms.
+ * (PXST_EWORKSPACE otherwise).  Ordered on `stream`; allocates nothing (the DCT
+ * products run in the library's own kernels, the transform matrices generated on
+ * the fly).
  */
 int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u_out, float sigma,
                               int32_t integrate, void* workspace, size_t workspace_bytes,
@@ -360,8 +361,6 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
  * return therefore leaves every job untouched.  A PXST_EHIP return (a failed HIP
  * call) can come after some stages were enqueued: the states of all jobs of the call
  * are then undefined.
- * A job with pm_sigma > 0 or pm_integrate = 1 regularises with rocBLAS, which may
- * allocate device memory on first use per device.
  */
 typedef struct {
     pxst_scan scan;

@@ -289,8 +289,6 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     // every call that does not integrate
     L.integ = integ;
     if (integ) {
-        L.dct_h = take((size_t)g.H * g.H * sizeof(double));
-        L.dct_w = take((size_t)g.W * g.W * sizeof(double));
         L.ibuf0 = take(HW * sizeof(double));
         L.ibuf1 = take(HW * sizeof(double));
     }

@@ -104,7 +104,7 @@ struct Layout {
     // defocus sweep: a candidate's map, reference, weights and contrast partials
     size_t sweep_u, sweep_ref, sweep_w, sweep_part;
     bool integ;
-    size_t dct_h, dct_w, ibuf0, ibuf1;
+    size_t ibuf0, ibuf1;
     size_t total;
 };
 
