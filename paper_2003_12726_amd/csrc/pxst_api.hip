@@ -592,9 +592,12 @@ int pxst_split_half_pixel_map(const pxst_scan* scan, const float* ref, const dou
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     char* w = (char*)ws;
     float* refv = (float*)(w + L.refv);
-    if ((rc = launch_prep_reference(g, ref, wsum, refv, nullptr, nullptr, nullptr, nullptr, stream))) return rc;
-    return launch_split_half(g, *scan, refv, dx, u_in, window, half, u_a, u_b, (double)hist_range, nbins, hist, w,
-                             L, stream);
+    int* sat = (int*)(w + L.sat);
+    if ((rc = launch_prep_reference(g, ref, wsum, refv, sat, (int*)(w + L.sat_tmp), (float*)(w + L.rowmax),
+                                    (int*)(w + L.fscale), stream)))
+        return rc;
+    return launch_split_half(g, *scan, refv, sat, dx, u_in, window, half, u_a, u_b, (double)hist_range, nbins, hist,
+                             w, L, stream);
 }
 
 int pxst_defocus_sweep(const pxst_scan* scan, const float* dx, const float* scales, int32_t n_cand,

@@ -288,9 +288,12 @@ int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, c
                            hipStream_t s);
 
 // Pixel-map search.
+// With `half` non-null, the split-half search: only the (frame, pixel) terms whose
+// half[n][pixel] equals hval count.
 int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
                      const float* dx, const float* u_in, const pxst_window& win, float* u_out,
-                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s);
+                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s,
+                     const uint8_t* half = nullptr, int hval = 0);
 
 // Batched pixel-map search in two phases: argument tables staged (host only; copied by
 // flush_tables), then the launches.  Jobs large enough to fill the device are searched
@@ -343,9 +346,9 @@ int launch_pixel_map_fractional(const Geom& g, const pxst_scan& sc, const float*
                                 hipStream_t s);
 // Split-half analysis: two pixel-map searches, one per half of the (frame, pixel) terms,
 // and the histogram of their differences (hist may be null).
-int launch_split_half(const Geom& g, const pxst_scan& sc, const float* refv, const float* dx, const float* u_in,
-                      const pxst_window& win, const uint8_t* half, float* u_a, float* u_b, double hist_range,
-                      int nbins, int32_t* hist, char* ws, const Layout& L, hipStream_t s);
+int launch_split_half(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat, const float* dx,
+                      const float* u_in, const pxst_window& win, const uint8_t* half, float* u_a, float* u_b,
+                      double hist_range, int nbins, int32_t* hist, char* ws, const Layout& L, hipStream_t s);
 // Defocus sweep: reference update and contrast for every candidate scale pair (scales
 // in host memory), first maximum into best (may be null).
 int launch_defocus_sweep(const Geom& g, const pxst_scan& sc, const float* dx, const float* scales, int n_cand,

@@ -67,6 +67,10 @@ struct PmArgs {
     const double* pgu;
     const unsigned* pvb;
     int pl_ref;
+    // split-half search: only the (frame, pixel) terms with half[n][pixel] == hval
+    // count (null: all terms)
+    const uint8_t* half;
+    int hval;
 };
 
 
@@ -593,6 +597,10 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
 
         const uint16_t* fp = a.frames + pix;
         float I = (float)fp[0];
+        // split-half search: a term outside the half adds a zero residual and no variance
+        const bool split = a.half != nullptr;
+        const uint8_t* hp = split ? a.half + pix : nullptr;
+        bool hin = !split || hp[0] == a.hval;
         for (int n0 = 0; n0 < N; n0 += FOLD) {
         const int nend = min(n0 + FOLD, N);
         for (int n = n0; n < nend; ++n) {
@@ -600,11 +608,12 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
             const float* G = smem + (n & 1) * bufsz + base;
             float* Gn = smem + ((n + 1) & 1) * bufsz;
             const float Inext = (float)fp[(size_t)n1 * HW];
+            const bool hnext = !split || hp[(size_t)n1 * HW] == a.hval;
             const float v = I - Wp;
             if (!slow_cur) {
-                eval_rows<KR, CW>(G, rowoff, nW, I, eP);
-                vP = fmaf(v, v, vP);
-                ++nfast;
+                eval_rows<KR, CW>(G, rowoff, hin ? nW : 0.f, hin ? I : 0.f, eP);
+                vP = fmaf(hin ? v : 0.f, v, vP);
+                nfast += hin ? 1 : 0;
             } else {
                 const float v2 = v * v;
 #pragma unroll
@@ -612,7 +621,7 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
 #pragma unroll
                     for (int m = 0; m < CW; ++m) {
                         const float gv = G[rowoff[r] + m];
-                        const bool ok = valid(gv);
+                        const bool ok = valid(gv) && hin;
                         const float rr = ok ? fmaf(nW, gv, I) : 0.f;
                         eP[r][m] = fmaf(rr, rr, eP[r][m]);
                         vK[r][m] += ok ? v2 : -0.f;
@@ -632,6 +641,7 @@ __device__ void pm_edge_item(const PmArgs& a, int slot) {
                 mine |= valid(g) ? 0 : 1;
             }
             I = Inext;
+            hin = hnext;
             slow_cur = __syncthreads_or(mine);
         }
 #pragma unroll
@@ -676,7 +686,8 @@ __device__ inline float eval_candidate(const PmArgs& a, size_t pix, size_t HW, i
         const AxisShift s0 = axis_shift(a.dx[2 * n], a.o0);
         const AxisShift s1 = axis_shift(a.dx[2 * n + 1], a.o1);
         const float g = masked_bilinear(a.refv, a.Rs, a.Rf, t0 - s0.e, t1 - s1.e, s0.t, s1.t);
-        if (valid(g)) {
+        // (split-half search: only the half's terms)
+        if (valid(g) && (!a.half || a.half[(size_t)n * HW + pix] == a.hval)) {
             const float I = (float)a.frames[(size_t)n * HW + pix];
             const float rr = fmaf(-Wp, g, I);
             eP = fmaf(rr, rr, eP);
@@ -2055,10 +2066,20 @@ PmPlan pm_plan(int NX, int NY) {
 
 int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, const int* sat,
                      const float* dx, const float* u_in, const pxst_window& win, float* u_out,
-                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s) {
+                     float* err_min, int32_t* argmin, char* ws, const Layout& L, hipStream_t s,
+                     const uint8_t* half, int hval) {
     // interior tiles read precomputed operand planes when the workspace holds them
-    const bool use_planes = L.planes_on && g.Rs >= 2 && g.Rf >= 2;
-    const PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L, use_planes);
+    const bool use_planes = !half && L.planes_on && g.Rs >= 2 && g.Rf >= 2;
+    PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L, use_planes);
+    if (half) {
+        // split-half search: the halves differ per (frame, pixel), so the frame sums of
+        // the matrix-core contraction do not apply; every staged tile goes to the LDS
+        // kernel that checks each lookup (and each term's half), the rest to the generic one
+        a.half = half;
+        a.hval = hval;
+        a.mm_on = 0;
+        a.fast_cap = 0;
+    }
     const PmPlan pl = pm_plan(a.NX, a.NY);
     hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(COMPACT_THREADS), 0, s, a);
