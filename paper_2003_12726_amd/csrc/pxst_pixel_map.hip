@@ -449,6 +449,11 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
 
         const uint16_t* fp = a.frames + pix;
         float I = (float)fp[0];
+        // split-half search: a term outside the half adds a zero residual and no variance
+        const bool split = a.half != nullptr;
+        const uint8_t* hp = split ? a.half + pix : nullptr;
+        bool hin = !split || hp[0] == a.hval;
+        int nv = 0;
         // blocks of FOLD frames: plain sums inside a block, compensated fold after it
         // (keeping the fold out of the frame loop keeps the accumulators in place)
         for (int n0 = 0; n0 < N; n0 += FOLD) {
@@ -458,6 +463,7 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
             const float* G = smem + (n & 1) * bufsz + base;
             float* Gn = smem + ((n + 1) & 1) * bufsz;
             const float Inext = (float)fp[(size_t)n1 * HW];
+            const bool hnext = !split || hp[(size_t)n1 * HW] == a.hval;
             const FrameShift fn = frame_shift(shn, Rf);
             shn = tab[min(n + 2, N - 1)];
             float pv[PFS][4];
@@ -473,9 +479,10 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
             }
             __builtin_amdgcn_sched_barrier(0);
 
-            eval_rows<KR, CW>(G, rowoff, nW, I, eP);
+            eval_rows<KR, CW>(G, rowoff, hin ? nW : 0.f, hin ? I : 0.f, eP);
             const float v = I - Wp;
-            vP = fmaf(v, v, vP);
+            vP = fmaf(hin ? v : 0.f, v, vP);
+            nv += hin ? 1 : 0;
             __builtin_amdgcn_sched_barrier(0);
 
 #pragma unroll
@@ -483,6 +490,7 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
                 if (s < nst)
                     Gn[st_lds[s]] = bilinear4(pv[s][0], pv[s][1], pv[s][2], pv[s][3], fn.t0, fn.t1);
             I = Inext;
+            hin = hnext;
             __syncthreads();
         }
 #pragma unroll
@@ -503,7 +511,7 @@ __device__ void pm_fast_item(const PmArgs& a, int slot) {
             for (int m = 0; m < CW; ++m) {
                 float E = INFINITY;
                 if (good && kx0 + r < NX) {
-                    E = normalised_error(eS[r][m] + eP[r][m], var, N);
+                    E = normalised_error(eS[r][m] + eP[r][m], var, nv);
                     if (E < bestE) {
                         bestE = E;
                         bestK = (kx0 + r) * CW + m;
@@ -2073,12 +2081,11 @@ int launch_pixel_map(const Geom& g, const pxst_scan& sc, const float* refv, cons
     PmArgs a = make_pm_args(g, sc, refv, sat, dx, u_in, win, u_out, err_min, argmin, ws, L, use_planes);
     if (half) {
         // split-half search: the halves differ per (frame, pixel), so the frame sums of
-        // the matrix-core contraction do not apply; every staged tile goes to the LDS
-        // kernel that checks each lookup (and each term's half), the rest to the generic one
+        // the matrix-core contraction do not apply; the tiles go to the LDS-staged
+        // kernels (which skip the terms outside the half) and the generic one
         a.half = half;
         a.hval = hval;
         a.mm_on = 0;
-        a.fast_cap = 0;
     }
     const PmPlan pl = pm_plan(a.NX, a.NY);
     hipLaunchKernelGGL(k_classify, dim3(a.ntiles), dim3(64), 0, s, a);

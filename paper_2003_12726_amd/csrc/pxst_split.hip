@@ -6,9 +6,9 @@
 // Each half is the pixel-map search itself, run with the half mask: the halves are
 // arbitrary per (frame, pixel), so the frame sums that the matrix-core contraction
 // shares between the pixels of a tile do not exist, and the tiles go to the LDS-staged
-// search that checks each lookup, where a term outside the half adds a zero residual
-// (the reference region of a tile staged once per frame for its 64 pixels), and the
-// tiles whose region does not fit to the generic search.
+// searches (the reference region of a tile staged once per frame for its 64 pixels;
+// a term outside the half adds a zero residual and no variance), the tiles whose
+// region does not fit to the generic search.
 #include "pxst_device.hpp"
 #include "pxst_internal.hpp"
 
