@@ -107,7 +107,8 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* __res
     const float f0 = floorf(u0), f1 = floorf(u1);
     const float fu0 = u0 - f0, fu1 = u1 - f1;
     const int i0 = (int)f0 - a.o0, i1 = (int)f1 - a.o1;
-    float pS = 0.f, pC = 0.f;
+    // the pixel's error summed in float64 over its frames
+    double pS = 0.0;
     for (int n0 = 0; n0 < a.N; n0 += ERR_FB) {
         // PAIRS: v holds the 2x2 block read at the lookup clamped into the grid; else the
         // four corners clamped one by one
@@ -143,14 +144,35 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* __res
             }
             I[t] = (float)a.frames[(size_t)n * HW + pc];
         }
+        // the common case, taken when it holds for every lane of the wave: every frame's
+        // four corners inside the grid and valid (a NaN reaches the corners' sum); lanes
+        // whose pixel is not used contribute zeros either way
+        bool fast = true;
+#pragma unroll
+        for (int t = 0; t < ERR_FB; ++t) {
+            const bool in = (unsigned)rr[t] <= (unsigned)(a.Rs - 2) && (unsigned)cq[t] <= (unsigned)(a.Rf - 2);
+            fast = fast && in && valid((v[t][0] + v[t][1]) + (v[t][2] + v[t][3]));
+        }
         double e[ERR_FB];
+        if (__all(fast || !use)) {
+#pragma unroll
+            for (int t = 0; t < ERR_FB; ++t) {
+                const float h0 = fmaf(fb[t], v[t][1] - v[t][0], v[t][0]);
+                const float h1 = fmaf(fb[t], v[t][3] - v[t][2], v[t][2]);
+                const float g = fmaf(fa[t], h1 - h0, h0);
+                const float res = fmaf(-Wp, g, I[t]);
+                const float eps = (res * res) * inv_s2;
+                e[t] = (double)(use && n0 + t < a.N ? eps : 0.f);
+                pS += e[t];
+            }
+        } else {
 #pragma unroll
         for (int t = 0; t < ERR_FB; ++t) {
             const int r = rr[t], c = cq[t];
             // all four corners inside the grid: the values read are the corners
             const bool in = (unsigned)r <= (unsigned)(a.Rs - 2) && (unsigned)c <= (unsigned)(a.Rf - 2);
             float g;
-            if (__builtin_expect(in && valid(v[t][0]) && valid(v[t][1]) && valid(v[t][2]) && valid(v[t][3]), 1)) {
+            if (in && valid(v[t][0]) && valid(v[t][1]) && valid(v[t][2]) && valid(v[t][3])) {
                 const float h0 = fmaf(fb[t], v[t][1] - v[t][0], v[t][0]);
                 const float h1 = fmaf(fb[t], v[t][3] - v[t][2], v[t][2]);
                 g = fmaf(fa[t], h1 - h0, h0);
@@ -180,17 +202,17 @@ __global__ __launch_bounds__(ERR_THREADS) void k_err_pixels(const ErrArgs* __res
             }
             e[t] = 0.0;
             if (use && n0 + t < a.N && valid(g)) {
-                const float rr = fmaf(-Wp, g, I[t]);
-                const float eps = (rr * rr) * inv_s2;
-                kahan_add(pS, pC, eps);
-                e[t] = (double)eps;
+                const float res = fmaf(-Wp, g, I[t]);
+                e[t] = (double)((res * res) * inv_s2);
             }
+            pS += e[t];
+        }
         }
         const double fsum = wave_sum8(e, lane);
         const int f = n0 + ((lane >> 3) & 7);
         if ((lane & 7) == 0 && f < a.N) wsum_sh[(size_t)f * WAVES + wave] = fsum;
     }
-    if (a.pixel_err && inb) a.pixel_err[pix] = use ? pS : 0.f;
+    if (a.pixel_err && inb) a.pixel_err[pix] = use ? (float)pS : 0.f;
     __syncthreads();
     for (int n = threadIdx.x; n < a.N; n += ERR_THREADS) {
         double acc = 0.0;
