@@ -595,6 +595,9 @@ def main():
     ap.add_argument("--no-divergent", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the regularisation, fractional, split-half and defocus sections")
+    ap.add_argument("--section", choices=["precision_study", "regularisation", "fractional_search", "split_half",
+                                          "defocus_sweep"],
+                    help="profiling aid: run only this extras section on the realistic scan and print its JSON")
     ap.add_argument("--divergent-only", action="store_true",
                     help="profiling aid: time only the divergent scan's solve and print its line")
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -627,6 +630,14 @@ def main():
         seeds = args.served_study or [5000, 6000, 7000]
         print(json.dumps(served_study(args.served_jobs, seeds, args.served_rates,
                                       args.cpu_workers or min(16, os.cpu_count() or 1))), flush=True)
+        return
+
+    if args.section:
+        pxst.load_library()
+        fn = {"precision_study": precision_study, "regularisation": regularisation_bench,
+              "fractional_search": fractional_bench, "split_half": split_half_bench,
+              "defocus_sweep": defocus_bench}[args.section]
+        print(json.dumps({args.section: fn(cached_scan("realistic"), torch.device("cuda:0"))}), flush=True)
         return
 
     if args.divergent_only:
