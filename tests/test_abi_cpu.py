@@ -119,6 +119,33 @@ def test_batch_rejects_bad_jobs(lib):
     assert lib.pxst_batch_iterate(None, 2, None, 0, None) == pxst.PXST_EINVAL
 
 
+def test_batch_workspace_checked_before_any_launch(lib):
+    """Valid jobs with a batch workspace one byte short of pxst_batch_workspace_bytes are
+    refused with PXST_EWORKSPACE before anything is enqueued (no GPU here: a launch would
+    fail differently); the size grows with the number of jobs."""
+    sizes = [pxst.batch_workspace_bytes(n) for n in (1, 2, 8, 64)]
+    assert all(b > a for a, b in zip(sizes, sizes[1:])), sizes
+    jobs = []
+    for k in range(3):
+        job = pxst.CJob()
+        job.scan = _scan()
+        job.opts = pxst.make_opts(2, (2, 2))
+        job.u, job.dx, job.ref, job.wsum = 0x10000, 0x20000, 0x30000, 0x40000
+        job.err_hist = 0x50000
+        job.iter = k % 3
+        job.ws = 0x100000
+        job.ws_bytes = pxst.workspace_bytes(job.scan.geom, job.opts)
+        jobs.append(job)
+    arr = (pxst.CJob * 3)(*jobs)
+    need = pxst.batch_workspace_bytes(3)
+    assert lib.pxst_batch_iterate(arr, 3, 0x1000000, need - 1, None) == pxst.PXST_EWORKSPACE
+    assert "workspace" in pxst.last_error()
+    # a job's own workspace one byte short is refused the same way
+    jobs[1].ws_bytes -= 1
+    arr = (pxst.CJob * 3)(*jobs)
+    assert lib.pxst_batch_iterate(arr, 3, 0x1000000, need, None) == pxst.PXST_EWORKSPACE
+
+
 def test_product_path_does_not_import_oracle():
     """The package and its sources never reference the oracle."""
     root = os.path.dirname(pxst.__file__)
