@@ -251,11 +251,11 @@ def run_served(rows, time_scale: float):
             for (k, arr, f, w, m, u, d, rs, o, it, win) in rows]
     evals = sum(r.pm_evals() for r in reqs)
     out = {}
-    for mode in ("one_by_one", "batched", "batched_all"):
+    for mode in ("one_by_one", "batched", "batched_srpt", "batched_all"):
         print(f"[served] {len(reqs)} jobs replayed {time_scale:g}x, {mode}", file=sys.stderr, flush=True)
         if mode != "one_by_one":
             srv = serve.Server(budget_bytes=200 << 30, max_slots=64, keep_results=False,
-                               policy="srpt" if mode == "batched" else "all")
+                               policy={"batched": "aged", "batched_srpt": "srpt", "batched_all": "all"}[mode])
             res = srv.run(reqs, time_scale=time_scale)
         else:
             res = serve.run_one_by_one(reqs, time_scale=time_scale, keep_results=False)
@@ -578,7 +578,7 @@ def served_study(n_jobs: int, seeds, rates, workers: int):
             torch.cuda.empty_cache()
     table = []
     for r in runs:
-        for mode in ("one_by_one", "batched", "batched_all"):
+        for mode in ("one_by_one", "batched", "batched_srpt", "batched_all"):
             st = r[mode]
             table.append({"seed": r["seed"], "replay_rate": r["replay_rate"], "mode": mode,
                           "p50_s": st["p50_s"], "p99_s": st["p99_s"], "max_s": st["max_s"],

@@ -6,10 +6,13 @@ arrival order while the job-slot count and the HBM budget allow, and advances re
 jobs together: one tick is one call of ``pxst_batch_iterate``, which runs one
 main-loop iteration (or the final reference update) of each job of the tick, every
 stage of all of them in shared launches.  Which resident jobs a tick takes is the
-policy: "srpt" (default) takes them in order of least remaining work until the
-tick's pixel-map work reaches ``tick_evals`` (enough to fill the device), so short
-jobs overtake long ones as in shortest-remaining-processing-time scheduling and a
-tick still fills the device; "all" advances every resident job each tick.  Jobs join
+policy: "srpt" takes them in order of least remaining work until the tick's
+pixel-map work reaches ``tick_evals`` (enough to fill the device), so short jobs
+overtake long ones as in shortest-remaining-processing-time scheduling and a tick
+still fills the device; "aged" (default) orders them by remaining work expressed as
+time at a nominal device rate minus the time waited since arrival, so that a long job
+that has waited is no longer overtaken without bound; "all" advances every resident
+job each tick.  Jobs join
 and leave at tick boundaries; a finished job's memory is released before the next
 tick's admission.  Latency is measured from a request's arrival to the end of the
 tick that finishes it.
@@ -134,17 +137,20 @@ class Server:
     """Continuous-batching server for PXST solves on one GPU.
 
     budget_bytes: HBM budget for resident jobs; max_slots: resident job limit;
-    policy: "srpt" or "all" (which resident jobs a tick advances); tick_evals: the
-    pixel-map work at which an "srpt" tick stops taking jobs.
+    policy: "aged", "srpt" or "all" (which resident jobs a tick advances); tick_evals:
+    the pixel-map work at which an "aged" or "srpt" tick stops taking jobs; rate: the
+    nominal device rate (pixel-map evaluations per second) that turns the remaining
+    work of "aged" into time.
     """
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, device="cuda", keep_results=True,
-                 policy: str = "srpt", tick_evals: float = 2e10):
+                 policy: str = "aged", tick_evals: float = 2e10, rate: float = 6e12):
         import torch
-        if policy not in ("srpt", "all"):
+        if policy not in ("aged", "srpt", "all"):
             raise ValueError(f"unknown policy {policy!r}")
         self.policy = policy
         self.tick_evals = float(tick_evals)
+        self.rate = float(rate)
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.dev = torch.device(device)
@@ -161,11 +167,14 @@ class Server:
             self.batch_ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
         return self.batch_ws
 
-    def _pick(self, resident: List[tuple]) -> List[tuple]:
-        """The resident jobs this tick advances."""
+    def _pick(self, resident: List[tuple], now: float) -> List[tuple]:
+        """The resident jobs this tick advances (resident entries: job, arrival, ...)."""
         if self.policy == "all":
             return resident
-        order = sorted(resident, key=lambda r: (r[0].remaining(), r[1]))
+        if self.policy == "srpt":
+            order = sorted(resident, key=lambda r: (r[0].remaining(), r[1]))
+        else:
+            order = sorted(resident, key=lambda r: (r[0].remaining() / self.rate - (now - r[1]), r[1]))
         tick, work = [], 0
         for r in order:
             if tick and work >= self.tick_evals:
@@ -215,7 +224,7 @@ class Server:
                         time.sleep(max(0.0, pend[0].arrival / time_scale - now()))
                     continue
             self.max_resident = max(self.max_resident, len(resident))
-            tick = self._pick(resident)
+            tick = self._pick(resident, now())
             jobs = [r[0].cjob() for r in tick]
             batch_iterate(jobs, self._batch_ws(len(jobs)))
             # while the tick runs, admit what has arrived: the host-side staging of their

@@ -53,7 +53,7 @@ def assert_same(a, b):
         assert np.array_equal(x, y), (a.job_id, name, np.abs(x - y).max())
 
 
-@pytest.mark.parametrize("policy,tick_evals", [("srpt", 2e10), ("srpt", 1.0), ("all", 0.0)])
+@pytest.mark.parametrize("policy,tick_evals", [("aged", 2e10), ("srpt", 2e10), ("srpt", 1.0), ("all", 0.0)])
 def test_batched_equals_alone_bitwise(policy, tick_evals):
     """tick_evals = 1 makes every srpt tick take one job (plus the jobs whose final
     reference update is due), so jobs overtake each other as often as possible."""
