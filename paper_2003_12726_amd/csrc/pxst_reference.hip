@@ -773,59 +773,6 @@ __device__ inline void splat_block(int i0, int j0, float t0, float t1, double vn
     }
 }
 
-// The same for the points of a wave's lanes that hold consecutive entries of one cell
-// row (v: the lane holds a point).  A point's upper column of bins is the lower column
-// of the next lane's point whenever both fall on the same row of bins and in
-// neighbouring columns (the usual case: consecutive entries are neighbouring cells), so
-// that lane adds both points' terms of that column and one atomic pair per bin is
-// saved; neighbours are found with row shifts inside 16-lane rows.  The sums are exact
-// integers, so where each term is added does not change the result.
-__device__ inline void splat_wave(bool v, int i0, int j0, float t0, float t1, double vn, double vd,
-                                  unsigned long long* bn, unsigned long long* bd) {
-    int i, j;
-    float wl0, wh0, wl1, wh1;
-    splat_axis(i0, t0, i, wl0, wh0);
-    splat_axis(j0, t1, j, wl1, wh1);
-    const int b = (i + 2) * RS_PC + (j + 2);
-    unsigned long long n[4], d[4];   // corners (0,0), (0,1), (1,0), (1,1)
-#pragma unroll
-    for (int di = 0; di < 2; ++di)
-#pragma unroll
-        for (int dj = 0; dj < 2; ++dj) {
-            const double w = (double)((di ? wh0 : wl0) * (dj ? wh1 : wl1));
-            n[2 * di + dj] = quantise(w, vn);
-            d[2 * di + dj] = quantise(w, vd);
-        }
-    // the left neighbour's bin and upper-column terms (a lane without a point sends a bin
-    // no point has; the first lane of each 16-lane row receives that value too)
-    constexpr int SR1 = 0x111, SL1 = 0x101, NONE = -1000000;
-    const int bl = __builtin_amdgcn_update_dpp(NONE, v ? b : NONE, SR1, 0xf, 0xf, false);
-    const bool take = v && bl + 1 == b;
-    auto from_left = [&](unsigned long long x) -> unsigned long long {
-        const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)x, SR1, 0xf, 0xf, false);
-        const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), SR1, 0xf, 0xf, false);
-        return take ? (((unsigned long long)hi << 32) | lo) : 0ull;
-    };
-    n[0] += from_left(n[1]);
-    n[2] += from_left(n[3]);
-    d[0] += from_left(d[1]);
-    d[2] += from_left(d[3]);
-    // whether the right neighbour took this point's upper column
-    const bool given = __builtin_amdgcn_update_dpp(0, take ? 1 : 0, SL1, 0xf, 0xf, false) != 0;
-    if (v) {
-        atomicAdd(&bn[b], n[0]);
-        atomicAdd(&bd[b], d[0]);
-        atomicAdd(&bn[b + RS_PC], n[2]);
-        atomicAdd(&bd[b + RS_PC], d[2]);
-        if (!given) {
-            atomicAdd(&bn[b + 1], n[1]);
-            atomicAdd(&bd[b + 1], d[1]);
-            atomicAdd(&bn[b + RS_PC + 1], n[3]);
-            atomicAdd(&bd[b + RS_PC + 1], d[3]);
-        }
-    }
-}
-
 // Same for a point anywhere (good pixels outside the cell grid): corners outside the
 // tile are skipped.
 __device__ inline void splat_any(int i0, int j0, float t0, float t1, double vn, double vd,
@@ -946,14 +893,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_ref_splat(const SplatArgs* __res
             for (int k = 0; k < RS_KR; ++k) I[k] = eb[k] + (unsigned)lane < ee[k] ? (unsigned)fr[px[k]] : 0u;
 #pragma unroll
             for (int k = 0; k < RS_KR; ++k) {
-                // every lane takes part (the neighbour exchange); lanes past the row's
-                // entries add nothing
-                if (eb[k] < ee[k]) {
-                    const bool v = eb[k] + (unsigned)lane < ee[k];
+                if (eb[k] + (unsigned)lane < ee[k]) {
                     const unsigned pk = __float_as_uint(pd[k].w);
                     const double Wd = (double)pd[k].z;
-                    splat_wave(v, (int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, pd[k].x - fd0, pd[k].y - fd1,
-                               Wd * (double)I[k] * sn, Wd * Wd * sd, bn, bd);
+                    splat_block((int)(pk >> 16) + K0, (int)(pk & 0xFFFFu) + K1, pd[k].x - fd0, pd[k].y - fd1,
+                                Wd * (double)I[k] * sn, Wd * Wd * sd, bn, bd);
                 }
             }
             for (int k = 0; k < RS_KR; ++k) {
