@@ -324,8 +324,13 @@ int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u
  * then a final reference update from the last (u, dx).
  *   u [2][H][W], dx [N][2]: in/out.  ref [Rs][Rf], wsum [Rs][Rf]: out.
  *   err_hist [n_iter] float64: out (optional).
- * Everything runs on `stream` without host synchronisation; since the whole
- * state is in the caller's buffers, calling again continues the iteration.
+ * Everything is ordered on `stream` without host synchronisation: iteration k's
+ * error pass runs on a library-internal second stream of the device (created on first
+ * use, default priority, kept until the process ends) while iteration k + 1 updates
+ * the reference, and `stream` waits for it before the search of iteration k + 1 and
+ * before the call's last work, so work enqueued on `stream` afterwards sees every
+ * output.  Concurrent calls on one device are enqueued one after the other.  Since
+ * the whole state is in the caller's buffers, calling again continues the iteration.
  */
 int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, float* dx,
                float* ref, double* wsum, double* err_hist, void* ws, size_t ws_bytes,

@@ -210,6 +210,7 @@ Layout make_layout(const Geom& g, int tr_ct, bool integ) {
     };
     const size_t HW = g.HW(), RR = g.RR();
     L.refv = take(RR * sizeof(float));
+    L.refv2 = take(RR * sizeof(float));
     L.sat = take((size_t)(g.Rs + 1) * (g.Rf + 1) * sizeof(int));
     L.sat_tmp = take(RR * sizeof(int));
     L.s2 = take(HW * sizeof(float));
@@ -717,6 +718,44 @@ int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u
     return launch_regularise(g, u_in, u_out, sigma, integrate, (char*)ws, L, stream);
 }
 
+// A second stream per device (default priority, non-blocking) and a fork and a join
+// event, created on first use and kept until the process ends.  The returned lock
+// serialises the enqueueing of solves on one device, so that the events' records and
+// waits of concurrent callers do not interleave.
+namespace {
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex mu;
+};
+std::mutex g_aux_mu;
+std::map<int, AuxStream*> g_aux;
+}  // namespace
+
+static int aux_stream(std::unique_lock<std::mutex>& lk, hipStream_t& s, hipEvent_t& fork, hipEvent_t& join) {
+    int dev = 0;
+    int rc = check_hip(hipGetDevice(&dev), "device");
+    if (rc) return rc;
+    AuxStream* x = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_aux_mu);
+        AuxStream*& slot = g_aux[dev];
+        if (!slot) slot = new AuxStream();
+        x = slot;
+    }
+    lk = std::unique_lock<std::mutex>(x->mu);
+    if (!x->s) {
+        if ((rc = check_hip(hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking), "stream create"))) return rc;
+        if ((rc = check_hip(hipEventCreateWithFlags(&x->fork, hipEventDisableTiming), "event create")) ||
+            (rc = check_hip(hipEventCreateWithFlags(&x->join, hipEventDisableTiming), "event create")))
+            return rc;
+    }
+    s = x->s;
+    fork = x->fork;
+    join = x->join;
+    return PXST_OK;
+}
+
 int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, float* dx, float* ref,
                double* wsum, double* err_hist, void* ws, size_t ws_bytes, hipStream_t stream) {
     int rc;
@@ -742,18 +781,30 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     const Layout L = make_layout(g, tr_ct_of(opts), opts->pm_integrate != 0);
     if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
     char* w = (char*)ws;
-    float* refv = (float*)(w + L.refv);
     int* sat = (int*)(w + L.sat);
     int* sat_tmp = (int*)(w + L.sat_tmp);
     float* s2 = (float*)(w + L.s2);
+    // Iteration k's error pass reads (u, dx) of the iteration and its reference copy
+    // only, so it runs on a second stream while iteration k + 1 updates the reference
+    // into the other copy; the main stream waits for it before the search of
+    // iteration k + 1 overwrites the map (and before returning).
+    std::unique_lock<std::mutex> lk;
+    hipStream_t es = stream;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (opts->n_iter > 0 && (rc = aux_stream(lk, es, fork, join))) return rc;
+    auto refv_of = [&](int k) { return (float*)(w + ((k & 1) ? L.refv2 : L.refv)); };
     if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
     if (opts->n_iter > 0 && (rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
+    bool err_pending = false;
     for (int k = 0; k < opts->n_iter; ++k) {
+        float* refv = refv_of(k);
         if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream,
                                           opts->ref_mode)))
             return rc;
         if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, (float*)(w + L.rowmax),
                                              (int*)(w + L.fscale), stream))) return rc;
+        if (err_pending && (rc = check_hip(hipStreamWaitEvent(stream, join, 0), "stream wait"))) return rc;
+        err_pending = false;
         if ((rc = launch_pixel_map(g, *scan, refv, sat, dx, u, opts->pm, u, nullptr, nullptr, w, L,
                                    stream)))
             return rc;
@@ -765,10 +816,19 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
                                       stream)))
             return rc;
         double* tot = err_hist ? err_hist + k : (double*)(w + L.err_pix) + g.N;
-        if ((rc = launch_error(g, *scan, refv, s2, u, dx, nullptr, nullptr, tot, w, L, stream)))
+        if ((rc = check_hip(hipEventRecord(fork, stream), "event record")) ||
+            (rc = check_hip(hipStreamWaitEvent(es, fork, 0), "stream wait")))
             return rc;
+        if ((rc = launch_error(g, *scan, refv, s2, u, dx, nullptr, nullptr, tot, w, L, es))) return rc;
+        if ((rc = check_hip(hipEventRecord(join, es), "event record"))) return rc;
+        err_pending = true;
     }
-    return launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream, opts->ref_mode);
+    rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv_of(opts->n_iter), w, L, stream, opts->ref_mode);
+    if (err_pending) {
+        const int rj = check_hip(hipStreamWaitEvent(stream, join, 0), "stream wait");
+        if (!rc) rc = rj;
+    }
+    return rc;
 }
 
 int pxst_profile_enable(int32_t on) {

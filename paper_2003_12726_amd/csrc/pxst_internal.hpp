@@ -77,7 +77,7 @@ struct RefPart {
 // Workspace layout: every section at a 256-byte aligned offset.
 struct Layout {
     // common
-    size_t refv, sat, sat_tmp, s2;
+    size_t refv, refv2, sat, sat_tmp, s2;   // refv2: the solve loop's second reference copy
     // reference update
     size_t ginfo, gpart, keys, ccount, vals2, cstart, rtot, rstart, kstart, pdata, bsort, rpart;
     int ref_chunks;   // frame chunks of the reference gather
