@@ -718,21 +718,22 @@ int pxst_regularise_pixel_map(const pxst_geom* geom, const float* u_in, float* u
     return launch_regularise(g, u_in, u_out, sigma, integrate, (char*)ws, L, stream);
 }
 
-// A second stream per device (default priority, non-blocking) and a fork and a join
-// event, created on first use and kept until the process ends.  The returned lock
+// A second stream per device (default priority, non-blocking) and three events (fork,
+// join, inverted map built), created on first use and kept until the process ends.  The returned lock
 // serialises the enqueueing of solves on one device, so that the events' records and
 // waits of concurrent callers do not interleave.
 namespace {
 struct AuxStream {
     hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, mapped = nullptr;
     std::mutex mu;
 };
 std::mutex g_aux_mu;
 std::map<int, AuxStream*> g_aux;
 }  // namespace
 
-static int aux_stream(std::unique_lock<std::mutex>& lk, hipStream_t& s, hipEvent_t& fork, hipEvent_t& join) {
+static int aux_stream(std::unique_lock<std::mutex>& lk, hipStream_t& s, hipEvent_t& fork, hipEvent_t& join,
+                      hipEvent_t& mapped) {
     int dev = 0;
     int rc = check_hip(hipGetDevice(&dev), "device");
     if (rc) return rc;
@@ -747,12 +748,14 @@ static int aux_stream(std::unique_lock<std::mutex>& lk, hipStream_t& s, hipEvent
     if (!x->s) {
         if ((rc = check_hip(hipStreamCreateWithFlags(&x->s, hipStreamNonBlocking), "stream create"))) return rc;
         if ((rc = check_hip(hipEventCreateWithFlags(&x->fork, hipEventDisableTiming), "event create")) ||
-            (rc = check_hip(hipEventCreateWithFlags(&x->join, hipEventDisableTiming), "event create")))
+            (rc = check_hip(hipEventCreateWithFlags(&x->join, hipEventDisableTiming), "event create")) ||
+            (rc = check_hip(hipEventCreateWithFlags(&x->mapped, hipEventDisableTiming), "event create")))
             return rc;
     }
     s = x->s;
     fork = x->fork;
     join = x->join;
+    mapped = x->mapped;
     return PXST_OK;
 }
 
@@ -787,20 +790,28 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
     // Iteration k's error pass reads (u, dx) of the iteration and its reference copy
     // only, so it runs on a second stream while iteration k + 1 updates the reference
     // into the other copy; the main stream waits for it before the search of
-    // iteration k + 1 overwrites the map (and before returning).
+    // iteration k + 1 overwrites the map (and before returning).  With the translation
+    // update on, the next reference update's inverted map (which depends on the map u
+    // only) is built on the second stream too, while the translations are searched.
     std::unique_lock<std::mutex> lk;
     hipStream_t es = stream;
-    hipEvent_t fork = nullptr, join = nullptr;
-    if (opts->n_iter > 0 && (rc = aux_stream(lk, es, fork, join))) return rc;
+    hipEvent_t fork = nullptr, join = nullptr, mapped = nullptr;
+    if (opts->n_iter > 0 && (rc = aux_stream(lk, es, fork, join, mapped))) return rc;
     auto refv_of = [&](int k) { return (float*)(w + ((k & 1) ? L.refv2 : L.refv)); };
     if ((rc = launch_sigma2(g, *scan, s2, stream))) return rc;
     if (opts->n_iter > 0 && (rc = launch_pm_setup(g, *scan, w, L, stream))) return rc;
-    bool err_pending = false;
+    bool err_pending = false, map_ready = false;
+    auto fork_to_aux = [&]() {
+        int r = check_hip(hipEventRecord(fork, stream), "event record");
+        return r ? r : check_hip(hipStreamWaitEvent(es, fork, 0), "stream wait");
+    };
     for (int k = 0; k < opts->n_iter; ++k) {
         float* refv = refv_of(k);
-        if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream,
-                                          opts->ref_mode)))
+        if (map_ready && (rc = check_hip(hipStreamWaitEvent(stream, mapped, 0), "stream wait"))) return rc;
+        if ((rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv, w, L, stream, opts->ref_mode,
+                                          !map_ready)))
             return rc;
+        map_ready = false;
         if ((rc = launch_prep_reference(g, nullptr, nullptr, refv, sat, sat_tmp, (float*)(w + L.rowmax),
                                              (int*)(w + L.fscale), stream))) return rc;
         if (err_pending && (rc = check_hip(hipStreamWaitEvent(stream, join, 0), "stream wait"))) return rc;
@@ -811,19 +822,23 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
         if ((opts->pm_sigma > 0.f || opts->pm_integrate) &&
             (rc = launch_regularise(g, u, u, opts->pm_sigma, opts->pm_integrate, w, L, stream)))
             return rc;
-        if (opts->update_dx &&
-            (rc = launch_translations(g, *scan, refv, u, dx, opts->tr, dx, nullptr, nullptr, w, L,
-                                      stream)))
-            return rc;
+        if (opts->update_dx) {
+            if ((rc = fork_to_aux()) || (rc = launch_inverse_map(g, *scan, u, w, L, es)) ||
+                (rc = check_hip(hipEventRecord(mapped, es), "event record")))
+                return rc;
+            map_ready = true;
+            if ((rc = launch_translations(g, *scan, refv, u, dx, opts->tr, dx, nullptr, nullptr, w, L, stream)))
+                return rc;
+        }
         double* tot = err_hist ? err_hist + k : (double*)(w + L.err_pix) + g.N;
-        if ((rc = check_hip(hipEventRecord(fork, stream), "event record")) ||
-            (rc = check_hip(hipStreamWaitEvent(es, fork, 0), "stream wait")))
-            return rc;
+        if ((rc = fork_to_aux())) return rc;
         if ((rc = launch_error(g, *scan, refv, s2, u, dx, nullptr, nullptr, tot, w, L, es))) return rc;
         if ((rc = check_hip(hipEventRecord(join, es), "event record"))) return rc;
         err_pending = true;
     }
-    rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv_of(opts->n_iter), w, L, stream, opts->ref_mode);
+    if (map_ready && (rc = check_hip(hipStreamWaitEvent(stream, mapped, 0), "stream wait"))) return rc;
+    rc = launch_update_reference(g, *scan, u, dx, ref, wsum, refv_of(opts->n_iter), w, L, stream, opts->ref_mode,
+                                 !map_ready);
     if (err_pending) {
         const int rj = check_hip(hipStreamWaitEvent(stream, join, 0), "stream wait");
         if (!rc) rc = rj;

@@ -278,9 +278,13 @@ int launch_prep_reference(const Geom& g, const float* ref, const double* wsum, f
 int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& L, hipStream_t s);
 
 // Reference update (splat as a deterministic gather over the inverted map).
+// build_map = false: the inverted map of u is already in the workspace (launch_inverse_map).
 int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
                             float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s, int ref_mode = PXST_REF_EXACT);
+                            hipStream_t s, int ref_mode = PXST_REF_EXACT, bool build_map = true);
+// The inverted map of u (the reference update's first part, independent of the shifts).
+int launch_inverse_map(const Geom& g, const pxst_scan& sc, const float* u, char* ws, const Layout& L,
+                       hipStream_t s);
 
 // Reference-plane error: ref_err = sum w M eps / sum w M (needs sigma2 in ws s2).
 int launch_reference_error(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,

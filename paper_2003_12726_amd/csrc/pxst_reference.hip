@@ -1148,15 +1148,13 @@ SplatArgs make_splat_args(const Geom& g, const pxst_scan& sc, const float* dx, f
     return a;
 }
 
-int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const MapArgs* dm,
-                          const SplatArgs* ds, hipStream_t s) {
+// The splat and combine of n jobs whose inverted maps are built.
+static int launch_splats(const SplatArgs* hs, int n, const SplatArgs* ds, hipStream_t s) {
     for (int j = 1; j < n; ++j)
         if ((hs[j].nchunks > 1) != (hs[0].nchunks > 1)) {
             set_error("batched reference update: the jobs differ in frame chunking");
             return PXST_EINVAL;
         }
-    int rc = launch_maps(hm, n, dm, s);
-    if (rc) return rc;
     int tx = 1, tyc = 1, rrb = 1;
     long long work = 0;
     for (int j = 0; j < n; ++j) {
@@ -1174,11 +1172,27 @@ int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const M
     return check_hip(hipGetLastError(), "reference update");
 }
 
+int launch_reference_jobs(const MapArgs* hm, const SplatArgs* hs, int n, const MapArgs* dm,
+                          const SplatArgs* ds, hipStream_t s) {
+    for (int j = 1; j < n; ++j)
+        if ((hs[j].nchunks > 1) != (hs[0].nchunks > 1)) {
+            set_error("batched reference update: the jobs differ in frame chunking");
+            return PXST_EINVAL;
+        }
+    const int rc = launch_maps(hm, n, dm, s);
+    return rc ? rc : launch_splats(hs, n, ds, s);
+}
+
+int launch_inverse_map(const Geom& g, const pxst_scan& sc, const float* u, char* ws, const Layout& L,
+                       hipStream_t s) {
+    return build_inverse_map(g, sc, u, ws, L, s);
+}
+
 int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, const float* dx,
                             float* ref, double* wsum, float* refv, char* ws, const Layout& L,
-                            hipStream_t s, int ref_mode) {
+                            hipStream_t s, int ref_mode, bool build_map) {
     if (ref_mode == PXST_REF_FP32) {
-        int rc = build_inverse_map(g, sc, u, ws, L, s);
+        int rc = build_map ? build_inverse_map(g, sc, u, ws, L, s) : PXST_OK;
         if (rc) return rc;
         GatherArgs b = gather_args(g, sc, u, dx, ws, L);
         b.out = ref;
@@ -1191,7 +1205,7 @@ int launch_update_reference(const Geom& g, const pxst_scan& sc, const float* u, 
     }
     const MapArgs m = make_map_args(g, sc, u, ws, L);
     const SplatArgs a = make_splat_args(g, sc, dx, ref, wsum, refv, ws, L);
-    int rc = launch_reference_jobs(&m, &a, 1, nullptr, nullptr, s);
+    int rc = build_map ? launch_reference_jobs(&m, &a, 1, nullptr, nullptr, s) : launch_splats(&a, 1, nullptr, s);
     if (rc || ref_mode != PXST_REF_BF16) return rc;
     return launch_round_bf16(g, ref, refv, s);
 }
