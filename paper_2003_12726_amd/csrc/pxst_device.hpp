@@ -229,6 +229,16 @@ __device__ inline int wave_max_i(int v) {
 // The table is read through the constant address space, so that the loads are scalar
 // and the arguments stay in scalar registers in both forms (the table is not written
 // while a kernel runs).
+// Entry j (wave-uniform) of a job table in device memory, read through the constant
+// address space (scalar loads, arguments in scalar registers).
+template <class X>
+__device__ __forceinline__ X table_entry(const X* __restrict__ jobs, int j) {
+    typedef const __attribute__((address_space(4))) X* ConstPtr;
+    X out;
+    __builtin_memcpy(&out, (ConstPtr)jobs + j, sizeof(X));
+    return out;
+}
+
 template <bool BATCH, class X>
 __device__ __forceinline__ X job_args(const X* __restrict__ jobs, const X& one) {
     if constexpr (BATCH) {

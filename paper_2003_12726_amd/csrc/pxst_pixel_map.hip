@@ -227,7 +227,7 @@ __device__ void compact_item(const PmArgs& a) {
 
 __global__ __launch_bounds__(COMPACT_THREADS) void k_compact(const PmArgs a) { compact_item(a); }
 __global__ __launch_bounds__(COMPACT_THREADS) void k_compact_batch(const PmArgs* __restrict__ jobs) {
-    compact_item(jobs[blockIdx.x]);
+    compact_item(table_entry(jobs, (int)blockIdx.x));
 }
 
 // Cross-thread first minimum, 3x3 stencil and refinement of one pass's pixels; E
@@ -1784,7 +1784,7 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
         const int total = off[njobs];                                                         \
         for (int item = blockIdx.x; item < total; item += gridDim.x) {                        \
             const int j = batch_job(off, njobs, item);                                        \
-            const PmArgs a = jobs[j];                                                         \
+            const PmArgs a = table_entry(jobs, j);                                            \
             BODY(a, item - off[j]);                                                           \
         }                                                                                     \
     }
@@ -1833,7 +1833,7 @@ __global__ __launch_bounds__(512) void k_pm_fast_batch(const PmArgs* __restrict_
     const int total = off[njobs];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int j = batch_job(off, njobs, item);
-        const PmArgs a = jobs[j];
+        const PmArgs a = table_entry(jobs, j);
         pm_fast_item<CW, KR>(a, item - off[j]);
     }
 }
@@ -1847,7 +1847,7 @@ __global__ __launch_bounds__(512) void k_pm_edge_batch(const PmArgs* __restrict_
     const int total = off[njobs];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int j = batch_job(off, njobs, item);
-        const PmArgs a = jobs[j];
+        const PmArgs a = table_entry(jobs, j);
         pm_edge_item<CW, KR>(a, item - off[j]);
     }
 }
