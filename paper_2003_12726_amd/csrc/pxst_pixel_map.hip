@@ -826,7 +826,10 @@ struct MmPix {
 __global__ __launch_bounds__(256) void k_pm_pack(const uint16_t* __restrict__ frames,
                                                  const uint8_t* __restrict__ mask, int N, int H, int W,
                                                  int tiles_x, int KB, uint4* __restrict__ ipk) {
-    const int tile = blockIdx.x / KB, kb = blockIdx.x - tile * KB;
+    // (tile, K-block) items in contiguous runs per XCD: horizontally neighbouring tiles,
+    // whose 16-byte row segments share lines, are read through one L2
+    const int item = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int tile = item / KB, kb = item - tile * KB;
     const int m = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p = m * 16 + (lane & 15);
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
