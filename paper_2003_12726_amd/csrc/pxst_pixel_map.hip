@@ -152,9 +152,29 @@ __device__ void classify_item(const PmArgs& a, int tile) {
     if (lane == 0) a.tinfo[tile] = make_int4(cls, ngood, (int)pos, 0);
 }
 
-// Work lists of the classes in tile order and the counters, by one work-group of 1024
-// threads per job (ordered compaction with wave ballots; no atomics).
+// Work lists of the classes and the counters, by one work-group of 1024 threads per
+// job (ordered compaction with wave ballots; no atomics).
 constexpr int COMPACT_THREADS = 1024;
+
+// Tile of position i in the order of the work lists: vertical strips of STRIP tiles,
+// each taken row by row, so that a tile's neighbours below follow it within STRIP
+// items; with the work items in contiguous per-XCD runs, the operand-plane regions
+// that vertically neighbouring tiles share are then still in the XCD's L2.
+constexpr int STRIP = 8;
+__device__ inline int strip_tile(int i, int tiles_x, int ntiles) {
+    const int tiles_y = ntiles / tiles_x, ns = tiles_x / STRIP, full = ns * STRIP * tiles_y;
+    int tx, ty;
+    if (i < full) {
+        const int s = i / (STRIP * tiles_y), r = i - s * (STRIP * tiles_y);
+        ty = r / STRIP;
+        tx = s * STRIP + (r - ty * STRIP);
+    } else {
+        const int rw = tiles_x - ns * STRIP, r = i - full;
+        ty = r / rw;
+        tx = ns * STRIP + (r - ty * rw);
+    }
+    return ty * tiles_x + tx;
+}
 
 __device__ void compact_item(const PmArgs& a) {
     __shared__ int wcnt[COMPACT_THREADS / 64][4];
@@ -167,39 +187,50 @@ __device__ void compact_item(const PmArgs& a) {
     // per thread: good pixels of each list's tiles, positions of FAST / EDGE_MM, NONE
     int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     __syncthreads();
-    for (int t0 = 0; t0 < a.ntiles; t0 += COMPACT_THREADS) {
-        const int tile = t0 + tid;
-        int4 ti = make_int4(-1, 0, 0, 0);
-        if (tile < a.ntiles) ti = a.tinfo[tile];
-        int mine[4];
+    // two ordered passes over the tiles: the interior list in strip order (its tiles read
+    // overlapping operand-plane regions, which vertical neighbours then find in L2), the
+    // other lists in tile order (measured faster for the edge search, whose per-XCD runs
+    // then spread the slow tiles more evenly)
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool strip = pass == 0;
+        for (int t0 = 0; t0 < a.ntiles; t0 += COMPACT_THREADS) {
+            const int i = t0 + tid;
+            const int tile = i < a.ntiles ? (strip ? strip_tile(i, a.tiles_x, a.ntiles) : i) : a.ntiles;
+            int4 ti = make_int4(-1, 0, 0, 0);
+            if (tile < a.ntiles) ti = a.tinfo[tile];
+            const int cls = ti.x;
+            // the classes of this pass
+            if (strip ? cls != CNT_FAST : cls == CNT_FAST) ti.x = -1;
+            int mine[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const unsigned long long m = __ballot(ti.x == cls_of[c]);
-            mine[c] = __popcll(m & lt);
-            if (lane == 0) wcnt[wave][c] = __popcll(m);
-        }
-        __syncthreads();
-        if (tid < 4) {
-            int run = base[tid];
-            for (int w = 0; w < COMPACT_THREADS / 64; ++w) {
-                const int v = wcnt[w][tid];
-                wcnt[w][tid] = run;
-                run += v;
+            for (int c = 0; c < 4; ++c) {
+                const unsigned long long m = __ballot(ti.x == cls_of[c]);
+                mine[c] = __popcll(m & lt);
+                if (lane == 0) wcnt[wave][c] = __popcll(m);
             }
-            base[tid] = run;
-        }
-        __syncthreads();
+            __syncthreads();
+            if (tid < 4) {
+                int run = base[tid];
+                for (int w = 0; w < COMPACT_THREADS / 64; ++w) {
+                    const int v = wcnt[w][tid];
+                    wcnt[w][tid] = run;
+                    run += v;
+                }
+                base[tid] = run;
+            }
+            __syncthreads();
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (ti.x == cls_of[c]) {
-                a.lists[c * a.ntiles + wcnt[wave][c] + mine[c]] = tile;
-                acc[c] += ti.y;
+            for (int c = 0; c < 4; ++c) {
+                if (ti.x == cls_of[c]) {
+                    a.lists[c * a.ntiles + wcnt[wave][c] + mine[c]] = tile;
+                    acc[c] += ti.y;
+                }
             }
+            if (ti.x == CNT_FAST) acc[4] += ti.z;
+            if (ti.x == CNT_EDGE_MM) acc[5] += ti.z;
+            if (!strip && cls == CNT_NONE) acc[6] += 1;
+            __syncthreads();
         }
-        if (ti.x == CNT_FAST) acc[4] += ti.z;
-        if (ti.x == CNT_EDGE_MM) acc[5] += ti.z;
-        if (ti.x == CNT_NONE) acc[6] += 1;
-        __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
