@@ -697,3 +697,50 @@ def test_solve_resume_equals_full_run():
     rest = gpu_solve(s2, 1, (3, 2), True)
     assert np.array_equal(full[0], rest[0]) and np.array_equal(full[2], rest[2])
     assert full[4][2] == rest[4][0]
+
+
+def test_solves_from_two_host_threads_on_two_streams():
+    """Two solves enqueued at once from two host threads, each on its own stream (the
+    loop's second stream and events are shared per device; their enqueueing is
+    serialised), give bitwise the results of the same solves run one after the other."""
+    import threading
+    scans = [random_small_scan(det=(37, 53), n_frames=7, seed=61),
+             random_small_scan(det=(40, 48), n_frames=9, seed=62, window=(2, 2))]
+    runs = [(s, 3, s.window, True, k == 1) for k, s in enumerate(scans)]
+    say("[solve] sequential reference runs")
+    want = [gpu_solve(s, n, w, r, update_dx=dxu) for s, n, w, r, dxu in runs]
+    say("[solve] two host threads, two streams")
+    got = [None, None]
+    errors = []
+
+    def work(k):
+        try:
+            s, n, w, r, dxu = runs[k]
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                sc = dev_scan(s)
+                opts = pxst.make_opts(n, w, r, dxu, (2, 2))
+                ws = pxst.alloc_workspace(sc.geom, opts)
+                u = to_dev(s.u0).clone()
+                dx = to_dev(s.dx0).clone()
+                ref = empty(s.ref_shape, torch.float32)
+                wsum = empty(s.ref_shape, torch.float64)
+                h = torch.zeros(n, dtype=torch.float64, device="cuda")
+                for _ in range(3):   # several solves in flight per thread
+                    u.copy_(to_dev(s.u0))
+                    dx.copy_(to_dev(s.dx0))
+                    pxst.solve(sc, opts, u, dx, ref, wsum, h, ws, stream=st)
+            st.synchronize()
+            got[k] = (u.cpu().numpy(), dx.cpu().numpy(), ref.cpu().numpy(), wsum.cpu().numpy(), h.cpu().numpy())
+        except Exception as e:   # reported below, in the test's thread
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        for a, b in zip(want[k], got[k]):
+            assert np.array_equal(a, b), k
