@@ -142,3 +142,73 @@ def test_over_budget_job_rejected():
     srv = serve.Server(budget_bytes=1024, max_slots=4)
     with pytest.raises(ValueError):
         srv.run(reqs)
+
+
+def test_batch_iterate_mixed_groups_bitwise():
+    """pxst_batch_iterate over jobs that fall into different groups of every shared stage
+    -- reference arithmetic (exact, bfloat16, float32 gather), frame counts, translation
+    windows, regularisation -- with the jobs at different iterations, equals each job
+    solved alone, bitwise."""
+    from paper_2003_12726_amd import CJob
+    from gpu_util import dev_scan, to_dev, empty
+    specs = [
+        dict(det=(37, 53), n=7, win=(3, 2), opts=dict(update_dx=True, tr=(1, 1))),
+        dict(det=(48, 40), n=9, win=(2, 2), opts=dict(update_dx=True, tr=(2, 1), ref_mode="bf16")),
+        dict(det=(33, 45), n=5, win=(2, 3), opts=dict(ref_mode="fp32")),
+        dict(det=(40, 64), n=6, win=(3, 3), opts=dict(update_dx=True, tr=(2, 2), sigma=1.3)),
+        dict(det=(64, 64), n=40, win=(2, 2), opts=dict(), grid=(7, 6)),   # many frames
+        dict(det=(21, 80), n=6, win=(0, 3), opts=dict(update_dx=True, tr=(0, 2))),
+    ]
+    jobs = []
+    for k, sp in enumerate(specs):
+        s = random_small_scan(det=sp["det"], n_frames=sp["n"], window=sp["win"], seed=400 + k,
+                              n_grid=sp.get("grid", (3, 3)))
+        assert s.frames.shape[0] == sp["n"]
+        opts = pxst.make_opts(3, sp["win"], True, **sp["opts"])
+        jobs.append((s, opts))
+    say("[batch] alone")
+    alone = []
+    for s, opts in jobs:
+        sc = dev_scan(s)
+        ws = pxst.alloc_workspace(sc.geom, opts)
+        u, dx = to_dev(s.u0).clone(), to_dev(s.dx0).clone()
+        ref, w = empty(s.ref_shape, torch.float32), empty(s.ref_shape, torch.float64)
+        h = torch.zeros(3, dtype=torch.float64, device="cuda")
+        pxst.solve(sc, opts, u, dx, ref, w, h, ws)
+        torch.cuda.synchronize()
+        alone.append([t.cpu().numpy() for t in (u, dx, ref, w, h)])
+    say("[batch] batched, jobs starting at different ticks")
+    state = []
+    for s, opts in jobs:
+        sc = dev_scan(s)
+        ws = pxst.alloc_workspace(sc.geom, opts)
+        st = dict(sc=sc, opts=opts, ws=ws, u=to_dev(s.u0).clone(), dx=to_dev(s.dx0).clone(),
+                  ref=empty(s.ref_shape, torch.float32), w=empty(s.ref_shape, torch.float64),
+                  h=torch.zeros(3, dtype=torch.float64, device="cuda"), it=0)
+        state.append(st)
+    start = [0, 1, 0, 2, 1, 0]          # tick at which each job joins
+    bws = torch.empty(pxst.batch_workspace_bytes(len(jobs)), dtype=torch.uint8, device="cuda")
+    tick = 0
+    while any(st["it"] <= 3 for st in state):
+        active = [k for k, st in enumerate(state) if start[k] <= tick and st["it"] <= 3]
+        cj = []
+        for k in active:
+            st = state[k]
+            j = CJob()
+            j.scan = st["sc"].c()
+            j.opts = st["opts"]
+            j.u, j.dx, j.ref, j.wsum = (st[x].data_ptr() for x in ("u", "dx", "ref", "w"))
+            j.err_hist = st["h"].data_ptr()
+            j.iter = st["it"]
+            j.ws, j.ws_bytes = st["ws"].data_ptr(), st["ws"].numel()
+            cj.append(j)
+        if cj:
+            pxst.batch_iterate(cj, bws)
+        for k in active:
+            state[k]["it"] += 1
+        tick += 1
+    torch.cuda.synchronize()
+    for k, st in enumerate(state):
+        got = [st[x].cpu().numpy() for x in ("u", "dx", "ref", "w", "h")]
+        for name, a, b in zip(("u", "dx", "ref", "wsum", "err_hist"), alone[k], got):
+            assert np.array_equal(a, b), (k, name, np.nanmax(np.abs(a - b)))
