@@ -74,22 +74,23 @@ __global__ __launch_bounds__(256) void k_tr_bbox(const TrArgs* __restrict__ jobs
 // rows and columns ix = TX - sx + {0, 1}, iy = TY - sy + {0, 1}.
 //
 // tr_fast: every lookup valid; h[r][c] is row r interpolated along the fast axis between
-// columns c and c + 1 (the fractions do not depend on the shift), so a shift costs an
-// interpolation along the slow axis and two FMAs.
+// columns c and c + 1 (the fractions do not depend on the shift).  With the white field
+// folded into the slow-axis weights, the residual of a shift is I - W g =
+// I + A h[ix][iy] + B h[ix + 1][iy] with A = -W (1 - fa), B = -W fa: two FMAs, and one
+// more for its square.
 template <int TX, int TY>
 __device__ __forceinline__ void tr_fast(const float (&h)[2 * TX + 2][2 * TY + 1], float fa, float I, float Wp,
                                         bool good, float (&err)[(2 * TX + 1) * (2 * TY + 1)], float& vC,
                                         int& cC) {
     constexpr int NXs = 2 * TX + 1, NYs = 2 * TY + 1;
     const float v = I - Wp;
-    const float nW = -Wp;
+    const float A = -Wp * (1.f - fa), B = -Wp * fa;
 #pragma unroll
     for (int ix = 0; ix < NXs; ++ix) {
 #pragma unroll
         for (int iy = 0; iy < NYs; ++iy) {
-            const float g = fmaf(fa, h[ix + 1][iy] - h[ix][iy], h[ix][iy]);
             const int s = (TX - ix + TX) * NYs + (TY - iy + TY);
-            const float rr = fmaf(nW, g, I);
+            const float rr = fmaf(B, h[ix + 1][iy], fmaf(A, h[ix][iy], I));
             err[s] = fmaf(rr, rr, err[s]);
         }
     }
@@ -179,6 +180,7 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
     bool g_n;
     float u0_n, u1_n, W_n, I_n;
     fetch(0, g_n, u0_n, u1_n, W_n, I_n);
+#pragma unroll 2
     for (int m = 0; m < NM; ++m) {
         const bool good = g_n;
         const float u0 = good ? u0_n : (float)bb.x, u1 = good ? u1_n : (float)bb.z;
@@ -307,6 +309,45 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* __restr
     // (a pixel's masked-form variance is non-zero only with its bit set)
     __shared__ float red[TR_THREADS / 64][CT * 3];
     const bool masked = __syncthreads_or(anyv != 0u ? 1 : 0);
+    float* __restrict__ out = a.part + ((size_t)n * a.nblk + tile) * (CT * 3);
+    if constexpr (STAGED) if (!masked) {
+        // (the barrier above also ends every read of the staged region) each thread's
+        // per-shift sums go to that region, shift by shift with a pitch of TR_THREADS + 8
+        // floats; eight threads per shift then add 32 entries each (thread p: entries
+        // p, p + 8, ...; the eight shifts a wave reads at a time fall on distinct banks)
+        // and combine their sums in a fixed butterfly.  The variance and count are common
+        // to all shifts.
+        constexpr int RP = TR_THREADS + 8;
+        static_assert(CT * RP <= TR_LDS_FLOATS, "per-shift sums fit the staged region");
+#pragma unroll
+        for (int s = 0; s < CT; ++s) reg[s * RP + threadIdx.x] = err[s];
+        const float vv = wave_total(vC);
+        const int c = wave_total(cC);
+        if (lane == 0) {
+            red[wave][0] = vv;
+            red[wave][1] = (float)c;
+        }
+        __syncthreads();
+        const int s = min((int)threadIdx.x >> 3, CT - 1), p = threadIdx.x & 7;
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < TR_THREADS / 8; ++k) acc += reg[s * RP + 8 * k + p];
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 4, 64);
+        if (p == 0 && (int)threadIdx.x < CT * 8) {
+            float v = 0.f, cn = 0.f;
+#pragma unroll
+            for (int w = 0; w < TR_THREADS / 64; ++w) {
+                v += red[w][0];
+                cn += red[w][1];
+            }
+            out[3 * s] = acc;
+            out[3 * s + 1] = v;
+            out[3 * s + 2] = cn;
+        }
+        return;
+    }
     if (masked) {
 #pragma unroll
         for (int s = 0; s < CT; ++s) {
@@ -337,7 +378,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* __restr
         float acc = 0.f;
 #pragma unroll
         for (int w = 0; w < TR_THREADS / 64; ++w) acc += red[w][q];
-        a.part[((size_t)n * a.nblk + tile) * (CT * 3) + q] = acc;
+        out[q] = acc;
     }
 }
 
