@@ -153,11 +153,12 @@ struct TrFrame {
 
 // The 16 pixels of a thread (column j of its tile, rows wave, wave + 4, ...): each
 // pixel's neighbourhood from the staged region (STAGED) or from the reference, then its
-// contribution to every shift.  CHECK: the neighbourhoods may hold invalid values.  The
-// next pixel's inputs are loaded while the current one is evaluated, and a pixel that
-// is masked or outside the detector runs the same instructions with zero count and
-// white-field, at the box corner (so that its reads stay inside the staged region), and
-// adds nothing.
+// contribution to every shift.  CHECK: the neighbourhoods may hold invalid values; a
+// pixel whose neighbourhood does is noted and evaluated in the masked form after the
+// others (so that the per-shift variance sums are live only then).  The next pixel's
+// inputs are loaded while the current one is evaluated, and a pixel that is masked or
+// outside the detector runs the same instructions with zero count and white-field, at
+// the box corner (so that its reads stay inside the staged region), and adds nothing.
 template <int TX, int TY, bool STAGED, bool CHECK>
 __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int i_first, int j, int4 bb,
                                           float (&err)[(2 * TX + 1) * (2 * TY + 1)],
@@ -165,6 +166,7 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
                                           float& vC, int& cC) {
     constexpr int CR = 2 * TY + 2, RR = 2 * TX + 2;
     constexpr int NM = TR_TILE / (TR_THREADS / 64);
+    static_assert(NM <= 32, "one bit per pixel of a thread");
     const size_t HW = (size_t)a.H * a.W;
     auto fetch = [&](int m, bool& good, float& u0, float& u1, float& Wp, float& I) {
         const int i = i_first + (TR_THREADS / 64) * m;
@@ -177,21 +179,16 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
         Wp = a.white[pix];
         I = (float)f.fr[pix];
     };
-    bool g_n;
-    float u0_n, u1_n, W_n, I_n;
-    fetch(0, g_n, u0_n, u1_n, W_n, I_n);
-#pragma unroll 2
-    for (int m = 0; m < NM; ++m) {
-        const bool good = g_n;
-        const float u0 = good ? u0_n : (float)bb.x, u1 = good ? u1_n : (float)bb.z;
-        const float Wp = good ? W_n : 0.f, I = good ? I_n : 0.f;
-        fetch(m + 1, g_n, u0_n, u1_n, W_n, I_n);
+    // lower corner of the neighbourhood's centre cell and the bilinear fractions
+    auto place = [&](float u0, float u1, int& a0, int& b0, float& fa, float& fb) {
         const float f0 = floorf(u0), f1 = floorf(u1);
         const float t0 = (u0 - f0) - f.fd0, t1 = (u1 - f1) - f.fd1;
-        const int a0 = (int)f0 - f.is0 - a.o0 - (t0 < 0.f ? 1 : 0);
-        const int b0 = (int)f1 - f.is1 - a.o1 - (t1 < 0.f ? 1 : 0);
-        const float fa = t0 < 0.f ? t0 + 1.f : t0, fb = t1 < 0.f ? t1 + 1.f : t1;
-        float nb[RR][CR];
+        a0 = (int)f0 - f.is0 - a.o0 - (t0 < 0.f ? 1 : 0);
+        b0 = (int)f1 - f.is1 - a.o1 - (t1 < 0.f ? 1 : 0);
+        fa = t0 < 0.f ? t0 + 1.f : t0;
+        fb = t1 < 0.f ? t1 + 1.f : t1;
+    };
+    auto load_nb = [&](float (&nb)[RR][CR], int a0, int b0) {
         if (STAGED) {
             const float* q = f.reg + (a0 - TX - f.R0) * f.RW + (b0 - TY - f.C0);
 #pragma unroll
@@ -210,15 +207,48 @@ __device__ __forceinline__ void tr_pixels(const TrArgs& a, const TrFrame& f, int
                 }
             }
         }
+    };
+    unsigned fail = 0u;   // pixels (bit m) left for the masked form
+    bool g_n;
+    float u0_n, u1_n, W_n, I_n;
+    fetch(0, g_n, u0_n, u1_n, W_n, I_n);
+#pragma unroll 2
+    for (int m = 0; m < NM; ++m) {
+        const bool good = g_n;
+        const float u0 = good ? u0_n : (float)bb.x, u1 = good ? u1_n : (float)bb.z;
+        const float Wp = good ? W_n : 0.f, I = good ? I_n : 0.f;
+        fetch(m + 1, g_n, u0_n, u1_n, W_n, I_n);
+        int a0, b0;
+        float fa, fb;
+        place(u0, u1, a0, b0, fa, fb);
         float h[RR][CR - 1];
+        {
+            float nb[RR][CR];
+            load_nb(nb, a0, b0);
 #pragma unroll
-        for (int r = 0; r < RR; ++r)
+            for (int r = 0; r < RR; ++r)
 #pragma unroll
-            for (int c = 0; c < CR - 1; ++c) h[r][c] = fmaf(fb, nb[r][c + 1] - nb[r][c], nb[r][c]);
+                for (int c = 0; c < CR - 1; ++c) h[r][c] = fmaf(fb, nb[r][c + 1] - nb[r][c], nb[r][c]);
+        }
         if (!CHECK || rows_valid<TX, TY>(h))
             tr_fast<TX, TY>(h, fa, I, Wp, good, err, vC, cC);
-        else
+        else if (good)
+            fail |= 1u << m;
+    }
+    if (CHECK) {
+        while (fail) {
+            const int m = __ffs(fail) - 1;
+            fail &= fail - 1u;
+            bool good;
+            float u0, u1, Wp, I;
+            fetch(m, good, u0, u1, Wp, I);
+            int a0, b0;
+            float fa, fb;
+            place(u0, u1, a0, b0, fa, fb);
+            float nb[RR][CR];
+            load_nb(nb, a0, b0);
             tr_masked<TX, TY>(nb, fa, fb, I, Wp, good, err, var, anyv);
+        }
     }
 }
 
