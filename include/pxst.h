@@ -401,6 +401,13 @@ int pxst_batch_iterate(const pxst_job* jobs, int32_t n_jobs, void* batch_ws,
 int pxst_profile_enable(int32_t on);
 int pxst_profile_read(const char* family, double* total_ms, int64_t* launches,
                       int64_t* work_units);
+/* Restricts the timing to the families named in `families` (comma-separated, e.g.
+ * "pm_fast"); NULL or "" selects every family again (the default).  A restricted
+ * selection brackets only those families' launches and copies no device work
+ * counters (their work units read as 0), so that timing perturbs the stream as
+ * little as possible: each event record and counter copy holds the stream for a few
+ * microseconds.  Always returns PXST_OK. */
+int pxst_profile_select(const char* families);
 
 const char* pxst_last_error(void);
 int32_t pxst_abi_version(void);

@@ -61,7 +61,7 @@ SYMBOLS = ("pxst_workspace_bytes", "pxst_update_reference", "pxst_update_referen
            "pxst_defocus_sweep", "pxst_update_translations", "pxst_error", "pxst_error_noalloc", "pxst_solve",
            "pxst_batch_workspace_bytes",
            "pxst_batch_iterate", "pxst_regularise_pixel_map", "pxst_profile_enable",
-           "pxst_profile_read", "pxst_last_error", "pxst_abi_version")
+           "pxst_profile_read", "pxst_profile_select", "pxst_last_error", "pxst_abi_version")
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pxst_profile_enable.argtypes = [i32]
     lib.pxst_profile_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64),
                                       P(ctypes.c_int64)]
+    lib.pxst_profile_select.argtypes = [ctypes.c_char_p]
     lib.pxst_last_error.restype = ctypes.c_char_p
     lib.pxst_abi_version.restype = i32
     for name in ("pxst_update_reference", "pxst_update_reference_ex", "pxst_update_pixel_map",
@@ -105,7 +106,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "pxst_update_translations",
                  "pxst_error", "pxst_solve", "pxst_batch_iterate", "pxst_regularise_pixel_map",
                  "pxst_profile_enable",
-                 "pxst_profile_read"):
+                 "pxst_profile_read", "pxst_profile_select"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -307,6 +308,13 @@ def batch_workspace_bytes(n_jobs: int) -> int:
 
 def profile_enable(on: bool = True):
     _check(load_library().pxst_profile_enable(int(bool(on))))
+
+
+def profile_select(families=None):
+    """Time only the named kernel families (an iterable of names), without device work
+    counters; None times every family again."""
+    sel = None if families is None else ",".join(families).encode()
+    _check(load_library().pxst_profile_select(sel))
 
 
 def profile_read(family: str):

@@ -57,6 +57,17 @@ struct Family {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::map<std::string, Family> g_prof;
+// families that record (all when g_prof_all); a restricted selection takes no device
+// work counters
+bool g_prof_all = true;
+std::vector<std::string> g_prof_sel;
+
+bool selected(const char* family) {
+    if (g_prof_all) return true;
+    for (const std::string& s : g_prof_sel)
+        if (s == family) return true;
+    return false;
+}
 
 hipEvent_t take_event(Family& f) {
     if (!f.pool.empty()) {
@@ -86,6 +97,7 @@ bool profiling() { return g_prof_on; }
 int profile_snapshot(const int* dev_counters, int n, hipStream_t s) {
     if (!g_prof_on || n <= 0 || n > SNAP_INTS) return -1;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_all) return -1;
     int id = -1;
     for (size_t i = 0; i < g_snaps.size(); ++i)
         if (!g_snaps[i].busy) {
@@ -114,6 +126,7 @@ void profile_end_snap(const char* family, hipStream_t s, int snap, int index, co
         return;
     }
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!selected(family)) return;
     Family& f = g_prof[family];
     if (!f.open) return;
     hipEvent_t b = take_event(f);
@@ -127,6 +140,7 @@ void profile_end_snap(const char* family, hipStream_t s, int snap, int index, co
 void profile_begin(const char* family, hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!selected(family)) return;
     Family& f = g_prof[family];
     f.open = take_event(f);
     if (f.open) hipEventRecord(f.open, s);
@@ -138,13 +152,14 @@ void profile_end(const char* family, hipStream_t s, long long work, const int* d
                  long long scale) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!selected(family)) return;
     Family& f = g_prof[family];
     if (!f.open) return;
     hipEvent_t b = take_event(f);
     if (!b) return;
     hipEventRecord(b, s);
     int* pin = nullptr;
-    if (dev_count) {
+    if (dev_count && g_prof_all) {
         pin = take_pinned(f);
         if (pin) hipMemcpyAsync(pin, dev_count, sizeof(int), hipMemcpyDeviceToHost, s);
     }
@@ -849,6 +864,24 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
 int pxst_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    return PXST_OK;
+}
+
+int pxst_profile_select(const char* families) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_sel.clear();
+    g_prof_all = families == nullptr || families[0] == '\0';
+    if (g_prof_all) return PXST_OK;
+    std::string cur;
+    for (const char* c = families;; ++c) {
+        if (*c == ',' || *c == '\0') {
+            if (!cur.empty()) g_prof_sel.push_back(cur);
+            cur.clear();
+            if (*c == '\0') break;
+        } else if (*c != ' ') {
+            cur += *c;
+        }
+    }
     return PXST_OK;
 }
 

@@ -146,6 +146,16 @@ def test_batch_workspace_checked_before_any_launch(lib):
     assert lib.pxst_batch_iterate(arr, 3, 0x1000000, need, None) == pxst.PXST_EWORKSPACE
 
 
+def test_profile_selection_host_only(lib):
+    """Timing selection is host state only: a restricted list, an empty one and NULL are
+    accepted, and reading a family that recorded nothing gives zeros."""
+    assert lib.pxst_profile_select(b"pm_fast, ref_gather") == 0
+    assert lib.pxst_profile_select(b"") == 0
+    assert lib.pxst_profile_select(None) == 0
+    pxst.profile_select(["pm_fast"])
+    pxst.profile_select(None)
+
+
 def test_product_path_does_not_import_oracle():
     """The package and its sources never reference the oracle."""
     root = os.path.dirname(pxst.__file__)
