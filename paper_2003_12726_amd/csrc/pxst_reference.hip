@@ -356,11 +356,12 @@ __device__ inline void entry_data(const float* __restrict__ u, const float* __re
     bs = make_int2(b0, b1);
 }
 
-// One work-group per row of cells (GH of them) and one more for the good pixels outside
-// the grid.  A row's work-group takes its region cells: sorts each cell's entries by
-// pixel index (a cell holds one or two pixels when u maps about one pixel per reference
-// pixel) and writes their data.  The last work-group places the pixels outside the grid
-// in pixel order and writes theirs (nothing to do for a sensible map).
+// One thread per cell of the grid (work-groups 0 .. ceil(GH GW / 256) - 1) and one more
+// work-group for the good pixels outside the grid.  A region cell's thread sorts the
+// cell's entries by pixel index (a cell holds one or two pixels when u maps about one
+// pixel per reference pixel) and writes their data.  The last work-group places the
+// pixels outside the grid in pixel order and writes theirs (nothing to do for a
+// sensible map).
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_cell_finish(const MapArgs* __restrict__ jobs, MapArgs one) {
     __shared__ unsigned wc[4];
@@ -375,28 +376,29 @@ __global__ __launch_bounds__(256) void k_cell_finish(const MapArgs* __restrict__
     unsigned* __restrict__ vals = a.vals;
     float4* __restrict__ pdata = a.pdata;
     int2* __restrict__ bsort = a.bsort;
-    if ((int)blockIdx.x > GH) return;
+    const int ncell = GH * GW, cblocks = (ncell + 255) / 256;
+    if ((int)blockIdx.x > cblocks) return;
     const GridInfo gi = *a.gi;
-    const int r = blockIdx.x;
-    if (r < GH) {
+    if ((int)blockIdx.x < cblocks) {
+        const int q = (int)blockIdx.x * 256 + (int)threadIdx.x;
+        if (q >= ncell) return;
+        const int r = q / GW, c = q - r * GW;
         int r0, r1, c0, c1;
         grid_region(gi, GH, GW, r0, r1, c0, c1);
-        if (r < r0 || r > r1) return;
-        for (int c = c0 + (int)threadIdx.x; c <= c1; c += 256) {
-            const unsigned b = cell_first(cstart, rstart, GW, r, c);
-            const unsigned n = cell_first(cstart, rstart, GW, r, c + 1) - b;
-            unsigned* v = vals + b;
-            for (unsigned i = 1; i < n; ++i) {   // insertion sort of a few entries
-                const unsigned x = v[i];
-                unsigned j = i;
-                while (j > 0 && v[j - 1] > x) {
-                    v[j] = v[j - 1];
-                    --j;
-                }
-                v[j] = x;
+        if (r < r0 || r > r1 || c < c0 || c > c1) return;
+        const unsigned b = cell_first(cstart, rstart, GW, r, c);
+        const unsigned n = cell_first(cstart, rstart, GW, r, c + 1) - b;
+        unsigned* v = vals + b;
+        for (unsigned i = 1; i < n; ++i) {   // insertion sort of a few entries
+            const unsigned x = v[i];
+            unsigned j = i;
+            while (j > 0 && v[j - 1] > x) {
+                v[j] = v[j - 1];
+                --j;
             }
-            for (unsigned i = 0; i < n; ++i) entry_data(u, white, v[i], HW, o0, o1, gi, GH, GW, pdata[b + i], bsort[b + i]);
+            v[j] = x;
         }
+        for (unsigned i = 0; i < n; ++i) entry_data(u, white, v[i], HW, o0, o1, gi, GH, GW, pdata[b + i], bsort[b + i]);
         return;
     }
     const unsigned ob = kstart[0], oe = kstart[1];
@@ -1058,11 +1060,12 @@ MapArgs make_map_args(const Geom& g, const pxst_scan& sc, const float* u, char* 
 
 // The inverted maps of n jobs (one launch per kernel; blocks past a job's grid return).
 static int launch_maps(const MapArgs* h, int n, const MapArgs* d, hipStream_t s) {
-    int parts = 1, gh = 1, hwb = 1;
+    int parts = 1, gh = 1, hwb = 1, cb = 1;
     for (int j = 0; j < n; ++j) {
         parts = std::max(parts, h[j].nparts);
         gh = std::max(gh, h[j].GH);
         hwb = std::max(hwb, (int)grid_blocks((size_t)h[j].HW, 256));
+        cb = std::max(cb, (int)grid_blocks((size_t)h[j].GH * h[j].GW, 256));
     }
     const MapArgs one = d ? MapArgs{} : h[0];
     PXST_LAUNCH_JOBS(k_grid_bbox, dim3(parts, 1, n), dim3(GRID_THREADS), 0, s, d, one);
@@ -1072,7 +1075,7 @@ static int launch_maps(const MapArgs* h, int n, const MapArgs* d, hipStream_t s)
     PXST_LAUNCH_JOBS(k_scan_rows, dim3(gh, 1, n), dim3(256), 0, s, d, one);
     PXST_LAUNCH_JOBS(k_scan_top, dim3(1, 1, n), dim3(256), 0, s, d, one);
     PXST_LAUNCH_JOBS(k_cell_scatter, dim3(hwb, 1, n), dim3(256), 0, s, d, one);
-    PXST_LAUNCH_JOBS(k_cell_finish, dim3(gh + 1, 1, n), dim3(256), 0, s, d, one);
+    PXST_LAUNCH_JOBS(k_cell_finish, dim3(cb + 1, 1, n), dim3(256), 0, s, d, one);
     return check_hip(hipGetLastError(), "inverse map");
 }
 
