@@ -349,6 +349,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_tr_partial(const TrArgs* __restr
         // to all shifts.
         constexpr int RP = TR_THREADS + 8;
         static_assert(CT * RP <= TR_LDS_FLOATS, "per-shift sums fit the staged region");
+        static_assert(CT * 8 <= TR_THREADS, "eight threads per shift");
 #pragma unroll
         for (int s = 0; s < CT; ++s) reg[s * RP + threadIdx.x] = err[s];
         const float vv = wave_total(vC);

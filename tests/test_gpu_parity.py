@@ -439,6 +439,34 @@ def test_pixel_map_high_dynamic_range_reference():
                     fixed_point=True)
 
 
+def test_profile_selection_times_only_the_named_family():
+    """With a restricted selection only the named family records its launches (without
+    device work counters) and the others none; selecting every family again restores
+    the counts; the search's results do not depend on the timing."""
+    s = random_small_scan(det=(37, 53), n_frames=7, seed=29)
+    ref, w = oracle_state(s)
+    fams = ("pm_fast", "pm_edge", "pm_generic")
+    pxst.profile_enable(True)
+    try:
+        pxst.profile_select(["pm_fast"])
+        for f in fams:
+            pxst.profile_read(f)
+        a = gpu_pixel_map(s, ref, w, s.dx0, s.u0, (3, 3), True)
+        sel = {f: pxst.profile_read(f) for f in fams}
+        pxst.profile_select(None)
+        b = gpu_pixel_map(s, ref, w, s.dx0, s.u0, (3, 3), True)
+        full = {f: pxst.profile_read(f) for f in fams}
+    finally:
+        pxst.profile_select(None)
+        pxst.profile_enable(False)
+    assert sel["pm_fast"][1] == 1 and sel["pm_fast"][2] == 0, sel
+    assert sel["pm_edge"][1] == 0 and sel["pm_generic"][1] == 0, sel
+    assert all(full[f][1] == 1 for f in fams), full
+    assert sum(full[f][2] for f in fams) > 0, full
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 def test_pixel_map_deterministic():
     s = random_small_scan(det=(37, 53), n_frames=7, seed=29)
     ref, w = oracle_state(s)
