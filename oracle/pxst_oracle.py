@@ -414,7 +414,8 @@ def linear_map(shape, scale, centre=None):
 
 def reference_contrast(ref, w):
     """Contrast of a reference image: variance over mean squared of the pixels with a
-    positive weight sum (reading of "the image will lack contrast"); 0 without any."""
+    positive weight sum (the reading taken of the paper's remark that a wrong defocus
+    leaves a reference image with little contrast); 0 without any."""
     ref, sel = _f64(ref), _f64(w) > 0
     if not sel.any():
         return 0.0

@@ -3,9 +3,10 @@
 Only the tests, the entry module's smoke check and the benchmark's CPU-baseline leg
 may import this file.  Sec. 2.2.2 ends with two optional steps applied to the pixel
 map after the search: a Gaussian filter of the map ("sigma", to regularise early
-iterations) and an irrotational constraint ("integrate": the map is integrated to a
-scalar function by least-squares conjugate gradients, then replaced by that
-function's numerical gradient, so its curl vanishes).  The paper does not give the
+iterations) and an irrotational constraint ("integrate": a scalar function whose
+gradient fits the map in the least-squares sense is found iteratively with conjugate
+gradients, and the map is replaced by that function's numerical gradient, so its curl
+vanishes).  The paper does not give the
 discretisation; the readings taken here:
 
 * filter: each component of ``u`` is convolved along both axes with the sampled
