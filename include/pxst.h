@@ -70,8 +70,8 @@ typedef struct {
     int32_t org_ss, org_fs;    /* integer origin of the reference grid              */
 } pxst_geom;
 
-/* Search window: integer offsets k in [-r, r] per axis, step 1 (Sec. 2.2.2 and
- * Sec. 2.2.3 search "within a predefined window").  refine != 0 adds the 3x3
+/* Search window: integer offsets k in [-r, r] per axis, step 1 (the searches of
+ * Sec. 2.2.2 and Sec. 2.2.3 cover a fixed window around the current value).  refine != 0 adds the 3x3
  * paraboloid sub-pixel offset around the integer minimum. */
 typedef struct {
     int32_t r_ss, r_fs;
