@@ -51,6 +51,15 @@ __device__ inline float masked_bilinear4(float v00, float v01, float v10, float 
     return den > 0.f ? num / den : qnan();
 }
 
+// The value of lane (this lane xor off) through the LDS permute unit; addr = 4 (lane
+// xor off), formed once per exchange step rather than per 32-bit half of every value.
+__device__ inline double lane_xor(double v, int addr) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Sums of ERR_FB per-lane values over the wave, fixed order: three exchange steps that
 // each halve the values a lane keeps (lane bit 5, 4, 3 picks the half), then three
 // plain steps over lane bits 2, 1, 0.  Lane l ends with the sum of value
@@ -61,16 +70,22 @@ __device__ inline double wave_sum8(double (&v)[ERR_FB], int lane) {
     for (int st = 0; st < 3; ++st) {
         const int off = 32 >> st, half = ERR_FB >> (st + 1);
         const bool hi = (lane & off) != 0;
+        const int addr = (lane ^ off) << 2;
 #pragma unroll
         for (int k = 0; k < half; ++k) {
-            const double send = hi ? v[k] : v[k + half];
-            const double keep = hi ? v[k + half] : v[k];
-            v[k] = keep + __shfl_xor(send, off, 64);
+            // (the empty asm makes the two values opaque: otherwise the compiler turns the
+            // selects into a read of the array at a run-time index, a compare-and-select
+            // chain over all ERR_FB values)
+            double a = v[k], b = v[k + half];
+            asm("" : "+v"(a), "+v"(b));
+            const double send = hi ? a : b;
+            const double keep = hi ? b : a;
+            v[k] = keep + lane_xor(send, addr);
         }
     }
     double r = v[0];
 #pragma unroll
-    for (int off = 4; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+    for (int off = 4; off > 0; off >>= 1) r += lane_xor(r, (lane ^ off) << 2);
     return r;
 }
 
