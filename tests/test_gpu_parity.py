@@ -581,6 +581,27 @@ def test_error_parity(case):
     np.testing.assert_allclose(re, o["ref"], rtol=ERR_TOL_REL, atol=1e-6 * o["ref"].max())
 
 
+@pytest.mark.parametrize("name", ["realistic", "divergent"])
+def test_error_full_size(name):
+    """The error pass at the benchmark scans' full size (256x1024 with 121 frames;
+    512x512 with 400 frames) and initial state, with the true reference minus two bands
+    of invalid pixels (the reference grid is the union of the frames' footprints, so the
+    bands are looked up: lookups with all, some and no valid corners all occur): frame
+    errors, total and pixel errors against the oracle."""
+    s = cached_scan(name)
+    ref32 = s.ref_true.astype(np.float32).astype(np.float64)
+    w = np.ones_like(ref32)
+    w[: ref32.shape[0] // 6, :] = 0.0
+    w[:, ref32.shape[1] - ref32.shape[1] // 8:] = 0.0
+    say(f"[error] {name} full size")
+    pe, fe, tot, _ = gpu_error(s, ref32, w, s.u0, s.dx0, ref_err=False)
+    o = oracle.calc_error(s.frames, s.white, s.mask, ref32, w, s.u0, s.dx0, s.origin)
+    assert o["total"] > 0
+    assert abs(tot - o["total"]) <= ERR_TOL_REL * o["total"]
+    np.testing.assert_allclose(fe, o["frame"], rtol=ERR_TOL_REL, atol=1e-9 * o["frame"].max())
+    np.testing.assert_allclose(pe, o["pixel"], rtol=ERR_TOL_REL, atol=1e-6 * o["pixel"].max())
+
+
 def test_maximum_frame_count():
     """The largest frame count the library takes (1920): the reference update, the
     pixel-map search on the matrix cores with 30 frame blocks (the contraction's byte
