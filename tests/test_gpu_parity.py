@@ -171,10 +171,12 @@ def test_reference_modes(mode):
         assert rel.max() <= 2.0 ** -8 + 1e-5, rel.max()
 
 
-def test_reference_parity_realistic_full():
-    """Full-size realistic scan (256x1024, 121 frames): whole reference compared."""
-    s = cached_scan("realistic")
-    say(f"[reference] realistic full det={s.det} N={s.n_frames}")
+@pytest.mark.parametrize("name", ["realistic", "divergent"])
+def test_reference_parity_full_size(name):
+    """Full-size scans (256x1024 with 121 frames; 512x512 with 400 frames, whose splat
+    runs in frame chunks combined afterwards): whole reference compared."""
+    s = cached_scan(name)
+    say(f"[reference] {name} full det={s.det} N={s.n_frames}")
     rg, wg = gpu_reference(s, s.u0, s.dx0)
     ro, wo = oracle_state(s)
     np.testing.assert_array_equal(wg > 0, wo > 0)
