@@ -347,7 +347,7 @@ int pxst_solve(const pxst_scan* scan, const pxst_solve_opts* opts, float* u, flo
  * Stages shared across jobs: the inverted maps and splat of the reference update
  * (exact arithmetic, also when rounded to bfloat16; one launch per kernel for the
  * jobs of each frame-chunking form), the summed-area tables of invalid reference
- * pixels, the pixel-map search (persistent launches over (job, tile) items per group
+ * pixels, the pixel-map search (shared launches over (job, tile) items per group
  * of jobs with one window; a job large enough to fill the device runs in launches of
  * its own), the translation search (one launch per kernel per translation window)
  * and the error (one launch per kernel per reference-lookup form).  Per job: the

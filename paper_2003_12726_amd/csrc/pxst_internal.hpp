@@ -188,9 +188,6 @@ BatchUpload stage_table(BatchArena& ar, const void* args, size_t bytes, const st
 // As stage_table, without offsets; returns the device address (null on overflow).
 const void* stage_raw(BatchArena& ar, const void* args, size_t bytes);
 int flush_tables(BatchArena& ar);
-// Persistent work-groups of a batched launch.
-constexpr int PERSISTENT_GROUPS = 256 * 4;
-
 // One job of a batched pixel-map search.
 struct PmJobDesc {
     Geom g;

@@ -1798,9 +1798,11 @@ __device__ void pm_mma_item(const PmArgs& a, int slot) {
 }
 
 // ------------------------------------------------------------------------ wrappers
-// Single-job launches (one work-group per item) and persistent launches over the items
-// of several jobs (item i of the batch belongs to job j with off[j] <= i < off[j + 1];
-// each job's arguments come from a device table).  A job's items and their results do
+// Single-job launches (one work-group per item) and shared launches over the items of
+// several jobs, also one work-group per item (item i of the batch belongs to job j with
+// off[j] <= i < off[j + 1]; each job's arguments come from a device table; a loop of
+// persistent work-groups over the items had kept the item state live around the body,
+// which pushed the edge search past its registers).  A job's items and their results do
 // not depend on the other jobs of the batch.
 __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item) {
     int lo = 0, hi = njobs;
@@ -1815,12 +1817,10 @@ __device__ inline int batch_job(const int* __restrict__ off, int njobs, int item
     __global__ __launch_bounds__(BOUND) void NAME(const PmArgs a) { BODY(a, (int)blockIdx.x); } \
     __global__ __launch_bounds__(BOUND) void NAME##_batch(const PmArgs* __restrict__ jobs,       \
                                                           const int* __restrict__ off, int njobs) { \
-        const int total = off[njobs];                                                         \
-        for (int item = blockIdx.x; item < total; item += gridDim.x) {                        \
-            const int j = batch_job(off, njobs, item);                                        \
-            const PmArgs a = table_entry(jobs, j);                                            \
-            BODY(a, item - off[j]);                                                           \
-        }                                                                                     \
+        const int item = blockIdx.x;                                                          \
+        if (item >= off[njobs]) return;                                                       \
+        const int j = batch_job(off, njobs, item);                                            \
+        BODY(table_entry(jobs, j), item - off[j]);                                            \
     }
 
 // single-job launch of a matrix-core search over the list counted by CNT, items in
@@ -1864,12 +1864,10 @@ __global__ __launch_bounds__(512) void k_pm_fast(const PmArgs a) {
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_fast_batch(const PmArgs* __restrict__ jobs,
                                                        const int* __restrict__ off, int njobs) {
-    const int total = off[njobs];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int j = batch_job(off, njobs, item);
-        const PmArgs a = table_entry(jobs, j);
-        pm_fast_item<CW, KR>(a, item - off[j]);
-    }
+    const int item = blockIdx.x;
+    if (item >= off[njobs]) return;
+    const int j = batch_job(off, njobs, item);
+    pm_fast_item<CW, KR>(table_entry(jobs, j), item - off[j]);
 }
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
@@ -1878,12 +1876,10 @@ __global__ __launch_bounds__(512) void k_pm_edge(const PmArgs a) {
 template <int CW, int KR>
 __global__ __launch_bounds__(512) void k_pm_edge_batch(const PmArgs* __restrict__ jobs,
                                                        const int* __restrict__ off, int njobs) {
-    const int total = off[njobs];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int j = batch_job(off, njobs, item);
-        const PmArgs a = table_entry(jobs, j);
-        pm_edge_item<CW, KR>(a, item - off[j]);
-    }
+    const int item = blockIdx.x;
+    if (item >= off[njobs]) return;
+    const int j = batch_job(off, njobs, item);
+    pm_edge_item<CW, KR>(table_entry(jobs, j), item - off[j]);
 }
 
 // ------------------------------------------------------------------------ dispatch
@@ -2206,9 +2202,9 @@ int launch_pm_setup(const Geom& g, const pxst_scan& sc, char* ws, const Layout& 
 
 // Batched pixel-map search of several jobs, in two phases so that a caller can stage the
 // argument tables of all its batched stages before one copy: staging (host only) and
-// launching.  Per group of jobs sharing a window: counters reset and one persistent
-// classification over every tile of every job, then one persistent launch of each
-// kernel class.
+// launching.  Per group of jobs sharing a window: counters reset and one shared
+// classification over every tile of every job, then one shared launch of each kernel
+// class.
 struct PmGroup {
     PmPlan pl;
     int m = 0, grid = 0, max_n = 1, mm_on = 0;
@@ -2259,7 +2255,7 @@ int stage_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar,
         std::vector<int> off(n + 1, 0);
         for (int j = 0; j < n; ++j) off[j + 1] = off[j] + base[j].ntiles;
         b->cls = stage_table(ar, base.data(), n * sizeof(PmArgs), off);
-        b->cls_grid = std::min(off[n], 256 * 16);
+        b->cls_grid = off[n];
         // groups of jobs with the same window and the same kernel choice (each job's
         // choice depends on its own sizes only, so a job is classified and searched the
         // same way alone and in a batch)
@@ -2287,7 +2283,7 @@ int stage_pixel_map_batch(const PmJobDesc* jobs_in, int n_in, BatchArena& ar,
                 go[q + 1] = go[q] + base[grp[q]].ntiles;
                 G.max_n = std::max(G.max_n, base[grp[q]].N);
             }
-            G.grid = std::min(go[G.m], PERSISTENT_GROUPS);
+            G.grid = go[G.m];
             G.g = stage_table(ar, G.ga.data(), G.m * sizeof(PmArgs), go);
             if (!(G.mm_on & 1)) G.f = stage_table(ar, fa.data(), G.m * sizeof(PmArgs), go);
             G.e = stage_table(ar, ea.data(), G.m * sizeof(PmArgs), go);
